@@ -1,0 +1,303 @@
+/*
+ * Correctness oracle for PFAC DNA matching -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark may load this code.  The GPU library never links, calls or
+ * includes it, and this file includes nothing from the GPU library.
+ *
+ * What it computes (the plain definition the PFAC walk reaches exactly):
+ *   For a text T[0..n) and patterns p_1..p_P over {A,C,G,T} (IDs 1..P in
+ *   input order, as the rows of the sample transition table in Sec. V.A,
+ *   Table I, are numbered),
+ *     match[i] = ID of the LONGEST pattern p_k with T[i..i+|p_k|) == p_k,
+ *                the smallest such ID when several equal patterns tie,
+ *                0 when no pattern starts at i.  PFAC reports only the
+ *                longest pattern per start position (Sec. IV), at the
+ *                position its thread starts from (Sec. IV, Fig. 3).
+ *     total    = number of pairs (k, i) with T[i..i+|p_k|) == p_k, every
+ *                pattern ID counted (duplicates included).
+ *   Only the four upper-case bytes A, C, G and T are bases (the table has
+ *   four columns, Sec. V.A); any other text byte has no transition.
+ *
+ * How it computes it: the classic sequential Aho-Corasick machine the paper
+ * summarises in Sec. III -- goto function built by inserting the keywords
+ * one at a time (Sec. III, Fig. 1; Sec. V.A), failure function over all
+ * goto states in breadth-first order (Sec. III, Fig. 2), output function,
+ * then one left-to-right pass over the text following failure links on a
+ * missing goto (Sec. III).  Each reported occurrence ending at j with
+ * length l is converted to its start j-l+1 and folded into match[] with the
+ * longest-wins / smaller-ID-on-tie rule.  A dictionary (output) link per
+ * state -- the nearest state on the failure chain with a non-empty output
+ * -- enumerates every keyword ending at j.
+ *
+ * Nothing here is blocked, fused or reordered for speed.  The
+ * multi-threaded entry point only splits start positions into contiguous
+ * chunks, runs the same scan on each chunk (extended by the longest
+ * pattern length minus one so every occurrence starting in the chunk is
+ * seen), and keeps occurrences whose start lies inside the chunk; the
+ * result is identical to the single-threaded scan.
+ */
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_E_ARG -1
+#define OR_E_PATTERN -2
+#define OR_E_NOMEM -4
+
+/* symbol index of a byte: A=0 C=1 G=2 T=3, -1 for every other byte */
+static int sym(uint8_t b) {
+  switch (b) {
+    case 'A': return 0;
+    case 'C': return 1;
+    case 'G': return 2;
+    case 'T': return 3;
+    default: return -1;
+  }
+}
+
+typedef struct {
+  int64_t nstates;     /* states allocated so far, root = 0 */
+  int64_t cap;
+  int64_t *go;         /* go[4*s + a]: goto(s, a), -1 = fail */
+  int64_t *fail;       /* failure function */
+  int64_t *dict;       /* nearest failure-chain state with output, -1 = none */
+  int64_t *out_head;   /* first keyword index (0-based) ending at s, -1 = none */
+  int64_t *out_next;   /* per keyword: next keyword ending at the same state */
+  uint32_t *kw_len;    /* per keyword: its length */
+  uint32_t nkw;
+  uint32_t max_len;
+} machine;
+
+static void machine_free(machine *m) {
+  free(m->go); free(m->fail); free(m->dict); free(m->out_head);
+  free(m->out_next); free(m->kw_len);
+  memset(m, 0, sizeof(*m));
+}
+
+static int new_state(machine *m) {
+  if (m->nstates == m->cap) {
+    int64_t nc = m->cap ? 2 * m->cap : 64;
+    int64_t *g = (int64_t *)realloc(m->go, (size_t)nc * 4 * sizeof(int64_t));
+    if (!g) return OR_E_NOMEM;
+    m->go = g;
+    int64_t *h = (int64_t *)realloc(m->out_head, (size_t)nc * sizeof(int64_t));
+    if (!h) return OR_E_NOMEM;
+    m->out_head = h;
+    m->cap = nc;
+  }
+  int64_t s = m->nstates++;
+  for (int a = 0; a < 4; ++a) m->go[4 * s + a] = -1;
+  m->out_head[s] = -1;
+  return OR_OK;
+}
+
+/* Goto function and output function: insert each keyword in input order;
+ * a new state is created for every character that has no transition yet
+ * (Sec. III, Fig. 1 numbering; Sec. V.A insertion). */
+static int build_goto(machine *m, const char *const *pats, const uint32_t *lens,
+                      uint32_t num, int64_t *bad_index) {
+  memset(m, 0, sizeof(*m));
+  m->nkw = num;
+  m->out_next = (int64_t *)malloc((size_t)(num ? num : 1) * sizeof(int64_t));
+  m->kw_len = (uint32_t *)malloc((size_t)(num ? num : 1) * sizeof(uint32_t));
+  if (!m->out_next || !m->kw_len) return OR_E_NOMEM;
+  if (new_state(m) != OR_OK) return OR_E_NOMEM;
+  for (uint32_t k = 0; k < num; ++k) {
+    if (lens[k] == 0) { if (bad_index) *bad_index = k; return OR_E_PATTERN; }
+    for (uint32_t t = 0; t < lens[k]; ++t)
+      if (sym((uint8_t)pats[k][t]) < 0) { if (bad_index) *bad_index = k; return OR_E_PATTERN; }
+  }
+  for (uint32_t k = 0; k < num; ++k) {
+    int64_t s = 0;
+    for (uint32_t t = 0; t < lens[k]; ++t) {
+      int a = sym((uint8_t)pats[k][t]);
+      if (m->go[4 * s + a] < 0) {
+        if (new_state(m) != OR_OK) return OR_E_NOMEM;
+        m->go[4 * s + a] = m->nstates - 1;
+      }
+      s = m->go[4 * s + a];
+    }
+    /* append keyword k to output(s), keeping keyword order */
+    m->kw_len[k] = lens[k];
+    m->out_next[k] = -1;
+    if (m->out_head[s] < 0) {
+      m->out_head[s] = k;
+    } else {
+      int64_t q = m->out_head[s];
+      while (m->out_next[q] >= 0) q = m->out_next[q];
+      m->out_next[q] = k;
+    }
+    if (lens[k] > m->max_len) m->max_len = lens[k];
+  }
+  return OR_OK;
+}
+
+/* Failure function in breadth-first order (Sec. III, Fig. 2), plus the
+ * dictionary link used to enumerate every output on the failure chain. */
+static int build_failure(machine *m) {
+  int64_t S = m->nstates;
+  m->fail = (int64_t *)malloc((size_t)S * sizeof(int64_t));
+  m->dict = (int64_t *)malloc((size_t)S * sizeof(int64_t));
+  int64_t *queue = (int64_t *)malloc((size_t)S * sizeof(int64_t));
+  if (!m->fail || !m->dict || !queue) { free(queue); return OR_E_NOMEM; }
+  int64_t head = 0, tail = 0;
+  m->fail[0] = 0;
+  m->dict[0] = -1;
+  for (int a = 0; a < 4; ++a) {
+    int64_t u = m->go[a];
+    if (u >= 0) { m->fail[u] = 0; m->dict[u] = -1; queue[tail++] = u; }
+  }
+  while (head < tail) {
+    int64_t r = queue[head++];
+    for (int a = 0; a < 4; ++a) {
+      int64_t u = m->go[4 * r + a];
+      if (u < 0) continue;
+      queue[tail++] = u;
+      /* f(u): longest proper suffix of u's string that is a trie state */
+      int64_t v = m->fail[r];
+      while (v != 0 && m->go[4 * v + a] < 0) v = m->fail[v];
+      int64_t w = m->go[4 * v + a];
+      m->fail[u] = (w >= 0 && w != u) ? w : 0;
+      int64_t f = m->fail[u];
+      m->dict[u] = (m->out_head[f] >= 0) ? f : m->dict[f];
+    }
+  }
+  free(queue);
+  return OR_OK;
+}
+
+/* Record keyword k of length l ending at text index j. */
+static void record(int32_t *match, uint32_t *bestlen, uint64_t *total,
+                   uint64_t lo, uint64_t hi, uint64_t j, uint32_t k, uint32_t l) {
+  uint64_t s = j + 1 - l;
+  if (s < lo || s >= hi) return;
+  *total += 1;
+  int32_t id = (int32_t)k + 1;
+  if (l > bestlen[s] || (l == bestlen[s] && id < match[s])) {
+    bestlen[s] = l;
+    match[s] = id;
+  }
+}
+
+/* One left-to-right pass (Sec. III) over text[lo .. min(n, hi+max_len-1)),
+ * starting from the root at lo, keeping occurrences that start in [lo, hi). */
+static void scan_range(const machine *m, const uint8_t *text, uint64_t n,
+                       uint64_t lo, uint64_t hi, int32_t *match, uint32_t *bestlen,
+                       uint64_t *total) {
+  uint64_t end = hi + (m->max_len ? m->max_len - 1 : 0);
+  if (end > n) end = n;
+  int64_t s = 0;
+  for (uint64_t j = lo; j < end; ++j) {
+    int a = sym(text[j]);
+    if (a < 0) { s = 0; continue; }          /* no transition: restart at the root */
+    while (s != 0 && m->go[4 * s + a] < 0) s = m->fail[s];
+    int64_t nx = m->go[4 * s + a];
+    s = nx >= 0 ? nx : 0;
+    int64_t t = (m->out_head[s] >= 0) ? s : m->dict[s];
+    while (t >= 0) {
+      for (int64_t k = m->out_head[t]; k >= 0; k = m->out_next[k])
+        record(match, bestlen, total, lo, hi, j, (uint32_t)k, m->kw_len[k]);
+      t = m->dict[t];
+    }
+  }
+}
+
+static int build_machine(machine *m, const char *const *pats, const uint32_t *lens,
+                         uint32_t num, int64_t *bad_index) {
+  int rc = build_goto(m, pats, lens, num, bad_index);
+  if (rc == OR_OK) rc = build_failure(m);
+  if (rc != OR_OK) machine_free(m);
+  return rc;
+}
+
+/* Single-threaded oracle scan. match has n entries. */
+int oracle_scan(const char *const *pats, const uint32_t *lens, uint32_t num,
+                const uint8_t *text, uint64_t n, int32_t *match, uint64_t *total,
+                int64_t *bad_index) {
+  if ((num && (!pats || !lens)) || (n && (!text || !match)) || !total) return OR_E_ARG;
+  machine m;
+  int rc = build_machine(&m, pats, lens, num, bad_index);
+  if (rc != OR_OK) return rc;
+  uint32_t *bestlen = (uint32_t *)calloc(n ? n : 1, sizeof(uint32_t));
+  if (!bestlen) { machine_free(&m); return OR_E_NOMEM; }
+  memset(match, 0, n * sizeof(int32_t));
+  *total = 0;
+  scan_range(&m, text, n, 0, n, match, bestlen, total);
+  free(bestlen);
+  machine_free(&m);
+  return OR_OK;
+}
+
+typedef struct {
+  const machine *m;
+  const uint8_t *text;
+  uint64_t n, lo, hi;
+  int32_t *match;
+  uint32_t *bestlen;
+  uint64_t total;
+} chunk_job;
+
+static void *chunk_main(void *arg) {
+  chunk_job *jb = (chunk_job *)arg;
+  scan_range(jb->m, jb->text, jb->n, jb->lo, jb->hi, jb->match, jb->bestlen, &jb->total);
+  return NULL;
+}
+
+/* Multi-threaded oracle scan: contiguous chunks of start positions, one
+ * thread each.  Identical result to oracle_scan. */
+int oracle_scan_mt(const char *const *pats, const uint32_t *lens, uint32_t num,
+                   const uint8_t *text, uint64_t n, int32_t *match, uint64_t *total,
+                   int64_t *bad_index, int nthreads) {
+  if ((num && (!pats || !lens)) || (n && (!text || !match)) || !total || nthreads < 1)
+    return OR_E_ARG;
+  machine m;
+  int rc = build_machine(&m, pats, lens, num, bad_index);
+  if (rc != OR_OK) return rc;
+  uint32_t *bestlen = (uint32_t *)calloc(n ? n : 1, sizeof(uint32_t));
+  chunk_job *jobs = (chunk_job *)calloc((size_t)nthreads, sizeof(chunk_job));
+  pthread_t *th = (pthread_t *)calloc((size_t)nthreads, sizeof(pthread_t));
+  if (!bestlen || !jobs || !th) {
+    free(bestlen); free(jobs); free(th); machine_free(&m); return OR_E_NOMEM;
+  }
+  memset(match, 0, n * sizeof(int32_t));
+  uint64_t per = (n + (uint64_t)nthreads - 1) / (uint64_t)nthreads;
+  for (int t = 0; t < nthreads; ++t) {
+    uint64_t lo = per * (uint64_t)t, hi = lo + per;
+    if (lo > n) lo = n;
+    if (hi > n) hi = n;
+    jobs[t] = (chunk_job){&m, text, n, lo, hi, match, bestlen, 0};
+    pthread_create(&th[t], NULL, chunk_main, &jobs[t]);
+  }
+  *total = 0;
+  for (int t = 0; t < nthreads; ++t) {
+    pthread_join(th[t], NULL);
+    *total += jobs[t].total;
+  }
+  free(bestlen); free(jobs); free(th);
+  machine_free(&m);
+  return OR_OK;
+}
+
+/* Expose the insertion-order goto function, before any renumbering, so
+ * tests can compare it with the state numbering of Sec. III, Fig. 1 and the
+ * edges of Sec. V.A, Table I.  go_out gets 4*cap entries (A,C,G,T order,
+ * -1 = fail), final_out gets cap entries (smallest keyword ID ending at the
+ * state, 0 = none).  Returns the state count, or a negative error. */
+int64_t oracle_goto(const char *const *pats, const uint32_t *lens, uint32_t num,
+                    int64_t *go_out, int32_t *final_out, int64_t cap) {
+  machine m;
+  int64_t bad = -1;
+  int rc = build_goto(&m, pats, lens, num, &bad);
+  if (rc != OR_OK) { machine_free(&m); return rc; }
+  int64_t S = m.nstates;
+  if (S <= cap) {
+    memcpy(go_out, m.go, (size_t)S * 4 * sizeof(int64_t));
+    for (int64_t s = 0; s < S; ++s)
+      final_out[s] = m.out_head[s] >= 0 ? (int32_t)m.out_head[s] + 1 : 0;
+  }
+  machine_free(&m);
+  return S;
+}
