@@ -1,0 +1,203 @@
+/*
+ * pfac.h -- C ABI of the MI355X (gfx950) PFAC DNA matcher.
+ *
+ * PFAC (Parallel Failure-less Aho-Corasick, paper Sec. IV): every start
+ * position of a DNA text runs its own walk through the goto trie of the
+ * patterns, with no failure links, stops at the first missing transition,
+ * and reports the longest pattern it passed (only the longest: sub-patterns
+ * of a longer match at the same start are not reported, Sec. IV).  The
+ * transition table has four columns, one per base (Sec. V.A, Table I), and
+ * is built on the host by inserting the patterns one at a time (Sec. V.A);
+ * matching runs on the GPU (Sec. V.B).
+ *
+ * Conventions shared by every entry point
+ *   - Bases are the upper-case ASCII bytes 'A','C','G','T'.  Any other text
+ *     byte has no transition, so a walk that reaches it stops there.
+ *   - Pattern IDs are 1 + the pattern's index in the input array (Table I
+ *     numbers its three patterns 1, 2, 3 in input order); 0 means "no match".
+ *     When several identical patterns are given, the smallest ID is reported
+ *     and every copy is counted in the occurrence totals.
+ *   - Text encodings: PFAC_TEXT_ASCII, one byte per base; PFAC_TEXT_2BIT,
+ *     A=0 C=1 G=2 T=3, base 4k+j in bits 2j..2j+1 of byte k (every value is
+ *     a valid base).
+ *   - Every function returns a pfac_status (0 on success) and never throws
+ *     or aborts.  Device pointers are hipMalloc'ed memory of the device that
+ *     is current on the calling thread; the caller owns them.  `stream` is a
+ *     hipStream_t (NULL = the legacy default stream).  Match calls are
+ *     asynchronous with respect to the host: they only enqueue work on
+ *     `stream`; results are valid once the stream reaches that point.
+ *   - Argument errors are reported synchronously before anything is
+ *     enqueued; on error no output buffer is written.
+ */
+#ifndef PFAC_H
+#define PFAC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PFAC_OK = 0,
+  PFAC_E_ARG = -1,        /* null/invalid argument, size out of range, wrong device */
+  PFAC_E_PATTERN = -2,    /* empty pattern or pattern byte outside A,C,G,T */
+  PFAC_E_TOO_LARGE = -3,  /* trie would need 2^31 or more states */
+  PFAC_E_NOMEM = -4,      /* host or device allocation failed */
+  PFAC_E_HIP = -5,        /* a HIP runtime call failed */
+  PFAC_E_NODEV = -6       /* no usable gfx950 device */
+} pfac_status;
+
+enum { PFAC_TEXT_ASCII = 0, PFAC_TEXT_2BIT = 1 };
+
+/* Opaque trie.  Immutable after pfac_build_table; it owns its device memory
+ * and may be used concurrently from several streams and host threads. */
+typedef struct pfac_table pfac_table;
+
+/* One reported start position: pos = start index in the text, pid = the
+ * longest pattern starting there (never 0). */
+typedef struct {
+  uint32_t pos;
+  int32_t pid;
+} pfac_hit;
+
+/* One reported start position of a batched call (text = index in the
+ * descriptor array). */
+typedef struct {
+  uint32_t text;
+  uint32_t pos;
+  int32_t pid;
+} pfac_batch_hit;
+
+typedef struct {
+  uint64_t num_states;     /* trie states including the root */
+  uint32_t num_patterns;
+  uint32_t max_len;        /* longest pattern */
+  uint32_t min_len;        /* shortest pattern */
+  uint32_t max_depth_full; /* deepest level d at which all 4^d prefixes are trie states */
+  uint64_t device_bytes;   /* device memory owned by the table */
+  uint64_t states_to_depth[9]; /* states of depth <= d, d = 0..8 (BFS prefix sizes) */
+} pfac_table_stats;
+
+/* Launch shape of a match call.  Any field left 0 is chosen by the library.
+ * Results never depend on the plan (every plan computes the same walk). */
+typedef struct {
+  uint32_t block;       /* threads per workgroup: 256, 512 or 1024 */
+  uint32_t jump_depth;  /* root jump depth K: 0 = walk every level from the root,
+                           4..7 = first K levels resolved by one LDS lookup of the
+                           K-base window; PFAC_JUMP_OFF forces 0 */
+  uint32_t hot_states;  /* rows of the breadth-first state prefix staged in LDS
+                           (PFAC_HOT_NONE = none) */
+  uint32_t grid;        /* persistent workgroups (0 = fill the device) */
+  uint32_t variant;     /* PFAC_VARIANT_TILED (LDS text tile + halo) or
+                           PFAC_VARIANT_GLOBAL (text and table read straight from
+                           global memory, one walk per thread) */
+} pfac_plan;
+
+#define PFAC_JUMP_OFF 0xFFFFFFFFu
+#define PFAC_HOT_NONE 0xFFFFFFFFu
+enum { PFAC_VARIANT_TILED = 0, PFAC_VARIANT_GLOBAL = 1 };
+
+/* Per-text descriptor of a batched call (all offsets are from the bases the
+ * call passes).  A text of ASCII encoding starting at a 16-byte aligned
+ * address is read with 16-byte loads; any other start is read byte-wise. */
+typedef struct {
+  uint64_t text_offset;   /* byte offset of the text in d_text_base */
+  uint64_t n;             /* bases (< 2^32) */
+  uint64_t match_offset;  /* element offset of its match array in d_match_base */
+  uint32_t table;         /* index into the tables[] array of the call */
+  uint32_t enc;           /* PFAC_TEXT_ASCII or PFAC_TEXT_2BIT */
+} pfac_text_desc;
+
+/*
+ * Build the failure-less goto trie of `num` patterns (Sec. V.A: patterns
+ * inserted one at a time, a new state per new character; Sec. V.B: the
+ * table is then copied to the device).  States are renumbered in
+ * breadth-first order (the state order of Nishimura et al., Sec. II) so that
+ * shallow, frequently visited states form a contiguous prefix.
+ *   patterns[k]  pointer to lengths[k] bytes (not NUL-terminated), host memory
+ *   num          >= 1
+ *   out          receives the table; free it with pfac_free_table
+ *   bad_index    optional; receives the index of the first invalid pattern on
+ *                PFAC_E_PATTERN, -1 otherwise
+ * Synchronous.  The table lives on the device current at the call.
+ */
+int pfac_build_table(const char* const* patterns, const uint32_t* lengths, uint32_t num,
+                     pfac_table** out, int64_t* bad_index);
+
+int pfac_table_info(const pfac_table* table, pfac_table_stats* out);
+
+/* Frees host and device memory (synchronises the device first).  NULL is a no-op. */
+void pfac_free_table(pfac_table* table);
+
+/*
+ * Match one text (Sec. IV semantics; one walk per start position, Sec. V.B).
+ *   d_text      device text of n bases in encoding `enc` (n < 2^32; n = 0 is allowed)
+ *   d_match     device int32[n] or NULL: longest pattern ID per start position, 0 = none
+ *   d_hits      device pfac_hit[hit_cap] or NULL: the positions with match != 0, in
+ *               ascending position order; only the first hit_cap are written
+ *   d_counters  device uint64[2] (required): [0] = number of positions with a match
+ *               (may exceed hit_cap: the caller can retry with a larger buffer),
+ *               [1] = total (pattern, position) occurrences, every pattern ID counted
+ *   plan        NULL for the library's choice
+ * Scratch memory (tile status words for the ordered hit list) is owned by the
+ * library, one area per (device, stream); calls on one stream reuse it in order.
+ */
+int pfac_match(const pfac_table* table, const void* d_text, uint64_t n, int enc,
+               int32_t* d_match, pfac_hit* d_hits, uint64_t hit_cap, uint64_t* d_counters,
+               const pfac_plan* plan, void* stream);
+
+/*
+ * Match many texts in one persistent launch: workgroups take (text, tile)
+ * items from a device work queue in text-then-position order.
+ *   tables/num_tables  host array of tables (all on the current device)
+ *   descs/num_texts    host array of descriptors (copied by the call)
+ *   d_text_base        device base of all texts
+ *   d_match_base       device int32 base or NULL (then no dense output)
+ *   d_hits             device pfac_batch_hit[hit_cap] or NULL; hits ordered by
+ *                      (text index, position)
+ *   d_counters         device uint64[2 + 2*num_texts]: [0] hits, [1] occurrences over
+ *                      the batch, then per text t: [2+2t] hits, [3+2t] occurrences.
+ *                      Text t's hits start at the sum of [2+2u] over u < t.
+ */
+int pfac_match_batch(const pfac_table* const* tables, uint32_t num_tables,
+                     const pfac_text_desc* descs, uint32_t num_texts, const void* d_text_base,
+                     int32_t* d_match_base, pfac_batch_hit* d_hits, uint64_t hit_cap,
+                     uint64_t* d_counters, const pfac_plan* plan, void* stream);
+
+/* The plan the library would use for `table` and a text of n bases (fields
+ * filled in, none left 0). */
+int pfac_default_plan(const pfac_table* table, uint64_t n, int enc, pfac_plan* out);
+
+/*
+ * Host-only build of the same table pfac_build_table uploads (no device
+ * needed), for inspection and tests.  Buffers are caller-owned host memory:
+ *   next     uint32[4*cap]: row s, column a (A=0,C=1,G=2,T=3) = child state in
+ *            bits 0..30 (0 = no transition; the root, state 0, is never a
+ *            child), bit 31 set when the child is a final state
+ *   pid      int32[cap]: smallest pattern ID ending at the state, 0 = none
+ *   mult     uint32[cap]: number of pattern IDs ending at the state
+ *   jump     uint32[4^K] or NULL, with K = jump_depth (4..7): the root jump
+ *            entry of every K-base window (first base in the low bits): state
+ *            after the K steps (0 if the walk stopped earlier), bit 31 set if
+ *            a final state was passed; jump_pid/jump_cnt (or NULL) receive the
+ *            longest pattern passed and the occurrences passed
+ * States are numbered breadth-first.  *num_states always receives the state
+ * count; arrays are written only when it is <= cap.
+ */
+int pfac_build_host(const char* const* patterns, const uint32_t* lengths, uint32_t num,
+                    uint32_t* next, int32_t* pid, uint32_t* mult, uint64_t cap,
+                    uint32_t jump_depth, uint32_t* jump, int32_t* jump_pid, uint32_t* jump_cnt,
+                    uint64_t* num_states, int64_t* bad_index);
+
+/* Human-readable text of a status code (static storage). */
+const char* pfac_strerror(int status);
+
+/* Library version string. */
+const char* pfac_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PFAC_H */

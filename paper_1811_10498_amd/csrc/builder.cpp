@@ -1,0 +1,176 @@
+// Host-side construction of the failure-less goto trie.
+//
+// Paper Sec. V.A: the table has one row per state and four columns (one
+// per base); patterns are inserted one at a time, each new character that
+// has no transition yet creating a new state; Sec. V.B: the host builds the
+// table and copies it to the device.  Differences from the paper's table:
+//   * a pattern's last character also allocates a fresh state (the printed
+//     sample table reuses the number it gives the last cell, which makes two
+//     prefixes share a row);
+//   * states are renumbered breadth-first after insertion (the state order
+//     Nishimura et al. use for cache locality, Sec. II), so the shallow states
+//     that every walk visits form a contiguous prefix that fits in LDS;
+//   * the matched-pattern ID moves out of the cell into a per-state output
+//     entry; the cell keeps one bit saying the child is final.
+#include <string.h>
+
+#include <algorithm>
+#include <array>
+#include <new>
+
+#include "pfac_internal.h"
+
+namespace pfac {
+
+static inline int base_code(uint8_t b) {
+  switch (b) {
+    case 'A': return 0;
+    case 'C': return 1;
+    case 'G': return 2;
+    case 'T': return 3;
+    default: return -1;
+  }
+}
+
+int build_host_table(const char* const* patterns, const uint32_t* lengths, uint32_t num,
+                     HostTable* out, int64_t* bad_index) {
+  if (bad_index) *bad_index = -1;
+  if (!patterns || !lengths || num == 0 || !out) return PFAC_E_ARG;
+  for (uint32_t k = 0; k < num; ++k) {
+    bool ok = lengths[k] > 0 && patterns[k] != nullptr;
+    for (uint32_t t = 0; ok && t < lengths[k]; ++t)
+      ok = base_code((uint8_t)patterns[k][t]) >= 0;
+    if (!ok) {
+      if (bad_index) *bad_index = k;
+      return PFAC_E_PATTERN;
+    }
+  }
+  try {
+    // 1. insertion-order trie
+    std::vector<std::array<uint32_t, 4>> kids(1, {0, 0, 0, 0});
+    std::vector<int32_t> fin_pid(1, 0);
+    std::vector<uint32_t> fin_mult(1, 0);
+    uint32_t maxl = 0, minl = UINT32_MAX;
+    for (uint32_t k = 0; k < num; ++k) {
+      uint32_t s = 0;
+      for (uint32_t t = 0; t < lengths[k]; ++t) {
+        int a = base_code((uint8_t)patterns[k][t]);
+        if (kids[s][a] == 0) {
+          if (kids.size() >= (size_t)kStateMask) return PFAC_E_TOO_LARGE;
+          kids[s][a] = (uint32_t)kids.size();
+          kids.push_back({0, 0, 0, 0});
+          fin_pid.push_back(0);
+          fin_mult.push_back(0);
+        }
+        s = kids[s][a];
+      }
+      if (fin_pid[s] == 0) fin_pid[s] = (int32_t)(k + 1);   // smallest ID wins
+      fin_mult[s] += 1;
+      maxl = std::max(maxl, lengths[k]);
+      minl = std::min(minl, lengths[k]);
+    }
+    const uint64_t S = kids.size();
+    // 2. breadth-first renumbering (children visited in A,C,G,T order)
+    std::vector<uint32_t> order;  // order[new] = old
+    order.reserve(S);
+    std::vector<uint32_t> newid(S, 0);
+    std::vector<uint64_t> depth_start;
+    order.push_back(0);
+    depth_start.push_back(0);
+    size_t level_begin = 0;
+    while (level_begin < order.size()) {
+      size_t level_end = order.size();
+      for (size_t i = level_begin; i < level_end; ++i) {
+        for (int a = 0; a < 4; ++a) {
+          uint32_t c = kids[order[i]][a];
+          if (c) order.push_back(c);
+        }
+      }
+      if (order.size() > level_end) depth_start.push_back(level_end);
+      level_begin = level_end;
+    }
+    depth_start.push_back(S);
+    for (uint64_t i = 0; i < S; ++i) newid[order[i]] = (uint32_t)i;
+    // 3. packed tables
+    out->next.assign(S * 4, 0);
+    out->out.assign(S, OutEntry{0, 0});
+    for (uint64_t i = 0; i < S; ++i) {
+      uint32_t o = order[i];
+      for (int a = 0; a < 4; ++a) {
+        uint32_t c = kids[o][a];
+        if (c) out->next[i * 4 + a] = newid[c] | (fin_pid[c] ? kFinalBit : 0u);
+      }
+      out->out[i] = OutEntry{fin_pid[o], fin_mult[o]};
+    }
+    out->num_states = S;
+    out->num_patterns = num;
+    out->max_len = maxl;
+    out->min_len = minl;
+    out->depth_start = depth_start;
+    // deepest fully populated level
+    uint32_t full = 0;
+    for (uint32_t d = 1; d + 1 < depth_start.size(); ++d) {
+      uint64_t cnt = depth_start[d + 1] - depth_start[d];
+      if (d < 32 && cnt == (1ull << (2 * d))) full = d; else break;
+    }
+    out->max_depth_full = full;
+    // 4. root jump tables: walk each K-base window from the root
+    for (uint32_t K = kMinJump; K <= kMaxJump; ++K) {
+      const uint32_t E = 1u << (2 * K);
+      out->jump[K].assign(E, 0);
+      out->jres[K].assign(E, OutEntry{0, 0});
+      for (uint32_t x = 0; x < E; ++x) {
+        uint32_t s = 0;
+        int32_t best = 0;
+        uint32_t cnt = 0;
+        bool finals = false, alive = true;
+        for (uint32_t d = 0; d < K; ++d) {
+          uint32_t e = out->next[(uint64_t)s * 4 + ((x >> (2 * d)) & 3)];
+          if (e == 0) { alive = false; break; }
+          s = e & kStateMask;
+          if (e & kFinalBit) {
+            finals = true;
+            best = out->out[s].pid;
+            cnt += out->out[s].mult;
+          }
+        }
+        out->jump[K][x] = (alive ? s : 0u) | (finals ? kFinalBit : 0u);
+        out->jres[K][x] = OutEntry{best, cnt};
+      }
+    }
+  } catch (const std::bad_alloc&) {
+    return PFAC_E_NOMEM;
+  }
+  return PFAC_OK;
+}
+
+}  // namespace pfac
+
+extern "C" int pfac_build_host(const char* const* patterns, const uint32_t* lengths, uint32_t num,
+                               uint32_t* next, int32_t* pid, uint32_t* mult, uint64_t cap,
+                               uint32_t jump_depth, uint32_t* jump, int32_t* jump_pid,
+                               uint32_t* jump_cnt, uint64_t* num_states, int64_t* bad_index) {
+  using namespace pfac;
+  if (!num_states) return PFAC_E_ARG;
+  if (jump && (jump_depth < kMinJump || jump_depth > kMaxJump)) return PFAC_E_ARG;
+  HostTable h;
+  int rc = build_host_table(patterns, lengths, num, &h, bad_index);
+  if (rc != PFAC_OK) return rc;
+  *num_states = h.num_states;
+  if (h.num_states <= cap) {
+    if (next) memcpy(next, h.next.data(), h.next.size() * sizeof(uint32_t));
+    for (uint64_t s = 0; s < h.num_states; ++s) {
+      if (pid) pid[s] = h.out[s].pid;
+      if (mult) mult[s] = h.out[s].mult;
+    }
+  }
+  if (jump) {
+    const uint32_t E = 1u << (2 * jump_depth);
+    memcpy(jump, h.jump[jump_depth].data(), E * sizeof(uint32_t));
+    for (uint32_t x = 0; x < E; ++x) {
+      if (jump_pid) jump_pid[x] = h.jres[jump_depth][x].pid;
+      if (jump_cnt) jump_cnt[x] = h.jres[jump_depth][x].mult;
+    }
+  }
+  return PFAC_OK;
+}

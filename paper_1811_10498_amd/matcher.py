@@ -1,0 +1,203 @@
+"""Python binding of the PFAC matcher: tables, single-text and batched matching.
+
+Every step of the matching runs in libpfac.so; this module only marshals
+arguments (torch tensors supply device memory and streams).
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+ENCODINGS = {"ascii": L.PFAC_TEXT_ASCII, "2bit": L.PFAC_TEXT_2BIT}
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def _plan_struct(plan) -> Optional[L.PfacPlan]:
+    if plan is None:
+        return None
+    if isinstance(plan, L.PfacPlan):
+        return plan
+    p = L.PfacPlan()
+    for k, v in dict(plan).items():
+        setattr(p, k, int(v))
+    return p
+
+
+class Table:
+    """Failure-less goto trie of a pattern set, resident on the current GPU."""
+
+    def __init__(self, patterns: Sequence[bytes]):
+        pats = [bytes(p) for p in patterns]
+        self.num_patterns = len(pats)
+        bufs = [ctypes.create_string_buffer(p, max(1, len(p))) for p in pats]
+        arr = (ctypes.c_void_p * max(1, len(pats)))()
+        for i, b in enumerate(bufs):
+            arr[i] = ctypes.addressof(b)
+        lens = (ctypes.c_uint32 * max(1, len(pats)))(*[len(p) for p in pats])
+        h = ctypes.c_void_p()
+        bad = ctypes.c_int64(-1)
+        rc = L.lib().pfac_build_table(ctypes.cast(arr, ctypes.c_void_p),
+                                      ctypes.cast(lens, ctypes.c_void_p), len(pats),
+                                      ctypes.byref(h), ctypes.byref(bad))
+        if rc != 0:
+            e = L.PfacError(rc, "pfac_build_table")
+            e.bad_index = bad.value
+            raise e
+        self._h = h
+        self._lib = L.lib()
+        st = L.PfacTableStats()
+        L.check(self._lib.pfac_table_info(self._h, ctypes.byref(st)), "pfac_table_info")
+        self.num_states = int(st.num_states)
+        self.max_len = int(st.max_len)
+        self.min_len = int(st.min_len)
+        self.max_depth_full = int(st.max_depth_full)
+        self.device_bytes = int(st.device_bytes)
+        self.states_to_depth = [int(x) for x in st.states_to_depth]
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.pfac_free_table(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def default_plan(self, n: int = 0, enc: str = "ascii") -> dict:
+        p = L.PfacPlan()
+        L.check(self._lib.pfac_default_plan(self._h, int(n), ENCODINGS[enc], ctypes.byref(p)),
+                "pfac_default_plan")
+        return p.as_dict()
+
+
+@dataclass
+class MatchResult:
+    match: Optional[torch.Tensor]       # int32[n] or None
+    hits: Optional[torch.Tensor]        # int32[hit_cap, 2] (pos, pid) or None
+    counters: torch.Tensor              # int64[2]: number of hits, total occurrences
+
+    def num_hits(self) -> int:
+        return int(self.counters[0].item())
+
+    def total(self) -> int:
+        return int(self.counters[1].item())
+
+    def hit_list(self) -> np.ndarray:
+        """(k, 2) array of (position, pattern id), k = min(num_hits, hit_cap)."""
+        k = min(self.num_hits(), 0 if self.hits is None else self.hits.shape[0])
+        h = self.hits[:k].cpu().numpy().astype(np.int64)
+        h[:, 0] &= 0xFFFFFFFF
+        return h
+
+
+def n_bases(text: torch.Tensor, enc: str) -> int:
+    return int(text.numel()) if enc == "ascii" else 4 * int(text.numel())
+
+
+def match(table: Table, text: torch.Tensor, n: Optional[int] = None, enc: str = "ascii",
+          dense: bool = True, hits: bool = True, hit_cap: Optional[int] = None, plan=None,
+          stream=None, out: Optional[MatchResult] = None) -> MatchResult:
+    """Match one device text.  ``text`` is a uint8 CUDA tensor (ASCII bytes,
+    or 2-bit packed with ``enc='2bit'`` and ``n`` bases).  Asynchronous on
+    ``stream`` (default: the current torch stream)."""
+    if text.device.type != "cuda" or text.dtype != torch.uint8:
+        raise TypeError("text must be a uint8 CUDA tensor")
+    if not text.is_contiguous():
+        raise ValueError("text must be contiguous")
+    if n is None:
+        n = n_bases(text, enc)
+    if n > n_bases(text, enc):
+        raise ValueError("n exceeds the text buffer")
+    dev = text.device
+    if out is None:
+        m = torch.empty(n, dtype=torch.int32, device=dev) if dense else None
+        cap = (n // 16 + 1024) if hit_cap is None else int(hit_cap)
+        h = torch.empty((cap, 2), dtype=torch.int32, device=dev) if hits else None
+        c = torch.empty(2, dtype=torch.int64, device=dev)
+        out = MatchResult(m, h, c)
+    p = _plan_struct(plan)
+    rc = table._lib.pfac_match(
+        table.handle, text.data_ptr(), int(n), ENCODINGS[enc],
+        out.match.data_ptr() if out.match is not None else None,
+        out.hits.data_ptr() if out.hits is not None else None,
+        int(out.hits.shape[0]) if out.hits is not None else 0,
+        out.counters.data_ptr(), ctypes.byref(p) if p is not None else None,
+        _stream_handle(stream))
+    L.check(rc, "pfac_match")
+    return out
+
+
+@dataclass
+class BatchResult:
+    match: Optional[torch.Tensor]        # int32, per-text arrays at match offsets
+    hits: Optional[torch.Tensor]         # int32[hit_cap, 3] (text, pos, pid)
+    counters: torch.Tensor               # int64[2 + 2T]
+    match_offsets: np.ndarray            # per-text element offsets into ``match``
+
+    def per_text(self):
+        """(hits, occurrences) per text as numpy int64 arrays."""
+        c = self.counters.cpu().numpy()
+        return c[2::2], c[3::2]
+
+
+def match_batch(tables: Sequence[Table], text_base: torch.Tensor, offsets, lengths,
+                table_index=None, enc="ascii", dense: bool = True, hits: bool = True,
+                hit_cap: Optional[int] = None, plan=None, stream=None,
+                match_out: Optional[torch.Tensor] = None,
+                match_offsets=None) -> BatchResult:
+    """Match many texts stored in one device buffer in one persistent launch.
+
+    ``offsets`` are byte offsets of each text in ``text_base``, ``lengths``
+    their base counts, ``table_index`` the table of each text (default 0),
+    ``enc`` one encoding name or one per text."""
+    offsets = np.asarray(offsets, dtype=np.uint64)
+    lengths = np.asarray(lengths, dtype=np.uint64)
+    T = int(lengths.size)
+    if table_index is None:
+        table_index = np.zeros(T, dtype=np.uint32)
+    table_index = np.asarray(table_index, dtype=np.uint32)
+    encs = (np.full(T, ENCODINGS[enc], dtype=np.uint32) if isinstance(enc, str)
+            else np.array([ENCODINGS[e] for e in enc], dtype=np.uint32))
+    if match_offsets is None:
+        match_offsets = np.concatenate([[0], np.cumsum(lengths)[:-1]]).astype(np.uint64) \
+            if T else np.zeros(0, dtype=np.uint64)
+    total = int(lengths.sum())
+    dev = text_base.device
+    descs = (L.PfacTextDesc * max(1, T))()
+    for i in range(T):
+        descs[i].text_offset = int(offsets[i])
+        descs[i].n = int(lengths[i])
+        descs[i].match_offset = int(match_offsets[i])
+        descs[i].table = int(table_index[i])
+        descs[i].enc = int(encs[i])
+    if dense and match_out is None:
+        match_out = torch.empty(max(1, total), dtype=torch.int32, device=dev)
+    cap = (total // 16 + 1024) if hit_cap is None else int(hit_cap)
+    h = torch.empty((cap, 3), dtype=torch.int32, device=dev) if hits else None
+    c = torch.empty(2 + 2 * T, dtype=torch.int64, device=dev)
+    tabs = (ctypes.c_void_p * len(tables))(*[t.handle.value for t in tables])
+    p = _plan_struct(plan)
+    rc = tables[0]._lib.pfac_match_batch(
+        ctypes.cast(tabs, ctypes.c_void_p), len(tables), ctypes.cast(descs, ctypes.c_void_p), T,
+        text_base.data_ptr(), match_out.data_ptr() if dense else None,
+        h.data_ptr() if h is not None else None, cap if h is not None else 0, c.data_ptr(),
+        ctypes.byref(p) if p is not None else None, _stream_handle(stream))
+    L.check(rc, "pfac_match_batch")
+    return BatchResult(match_out if dense else None, h, c, match_offsets)

@@ -1,0 +1,289 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle,
+bit-exact (integer matching: match array, total occurrences, ordered hit list)."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from _checkers import read_golden
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1811_10498_amd as pf  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def _gpu(patterns, text_ascii, plan=None, enc="ascii", hit_cap=None, table=None, offset=0):
+    """Run the GPU path on an ASCII host text (packing it when enc='2bit')."""
+    t = np.asarray(text_ascii, dtype=np.uint8)
+    n = int(t.size)
+    if enc == "2bit":
+        buf = W.pack2bit(W.ascii_to_codes(t))
+    else:
+        buf = t
+    if offset:
+        buf = np.concatenate([np.zeros(offset, dtype=np.uint8), buf])
+    dt = torch.from_numpy(np.array(buf, dtype=np.uint8)).to(DEV)
+    if offset:
+        dt = dt[offset:]
+    tab = table or pf.Table(patterns)
+    res = pf.match(tab, dt, n=n, enc=enc, plan=plan, hit_cap=n + 16 if hit_cap is None else hit_cap)
+    torch.cuda.synchronize()
+    return res
+
+
+def _check(res, patterns, text_ascii, m_ref=None, total_ref=None):
+    if m_ref is None:
+        m_ref, total_ref = oracle.scan(patterns, np.asarray(text_ascii, dtype=np.uint8), threads=8)
+    m = res.match.cpu().numpy()
+    bad = np.nonzero(m != m_ref)[0]
+    assert bad.size == 0, "first mismatch at %d: gpu %d oracle %d (%d mismatches)" % (
+        bad[0], m[bad[0]], m_ref[bad[0]], bad.size)
+    assert res.total() == total_ref
+    pos, ids = oracle.hits_of(m_ref)
+    assert res.num_hits() == pos.size
+    h = res.hit_list()
+    assert np.array_equal(h[:, 0], pos) and np.array_equal(h[:, 1], ids)
+
+
+def _pats(s):
+    return [p.encode() for p in s.split()]
+
+
+@pytest.mark.parametrize("name", ["ex1_fig1_text.txt", "ex2_table1_text.txt"])
+def test_worked_examples(name):
+    ex = read_golden(name)
+    pats = _pats(ex["patterns"])
+    text = np.frombuffer(ex["text"].encode(), dtype=np.uint8)
+    res = _gpu(pats, text)
+    assert res.match.cpu().numpy().tolist() == [int(x) for x in ex["match"].split()]
+    assert res.total() == int(ex["total"])
+
+
+def test_tiny_workload_full():
+    w = W.plain_workload(0)
+    print("c0: n=%d patterns=%d" % (w.n, len(w.patterns)), flush=True)
+    res = _gpu(w.patterns, w.text)
+    _check(res, w.patterns, w.text)
+
+
+def test_markov_workload_reduced():
+    w = W.plain_workload(1, n=8_000_003)
+    print("c1 reduced: n=%d patterns=%d" % (w.n, len(w.patterns)), flush=True)
+    res = _gpu(w.patterns, w.text)
+    _check(res, w.patterns, w.text)
+
+
+def test_packed_big_trie_reduced():
+    w = W.plain_workload(2, n=4_000_037, num_patterns=200_000)
+    print("c2 reduced: n=%d patterns=%d" % (w.n, len(w.patterns)), flush=True)
+    ascii_text = w.ascii()
+    m_ref, total_ref = oracle.scan(w.patterns, ascii_text, threads=8)
+    tab = pf.Table(w.patterns)
+    dt = torch.from_numpy(w.text).to(DEV)
+    res = pf.match(tab, dt, n=w.n, enc="2bit", hit_cap=w.n)
+    torch.cuda.synchronize()
+    _check(res, w.patterns, ascii_text, m_ref, total_ref)
+    # same text as ASCII gives the same answer
+    res2 = _gpu(w.patterns, ascii_text, table=tab)
+    _check(res2, w.patterns, ascii_text, m_ref, total_ref)
+
+
+PLANS = [
+    dict(variant=pf.PFAC_VARIANT_GLOBAL),
+    dict(block=256, jump_depth=pf.PFAC_JUMP_OFF, hot_states=pf.PFAC_HOT_NONE),
+    dict(block=256, jump_depth=4, hot_states=pf.PFAC_HOT_NONE),
+    dict(block=512, jump_depth=5, hot_states=64),
+    dict(block=1024, jump_depth=6, hot_states=pf.PFAC_HOT_NONE),
+    dict(block=512, jump_depth=7, hot_states=pf.PFAC_HOT_NONE),
+    dict(block=256, jump_depth=7, hot_states=2000),
+    dict(block=1024, jump_depth=7, hot_states=2000, grid=3),
+]
+
+
+@pytest.mark.parametrize("plan", range(len(PLANS)))
+def test_every_plan_gives_identical_results(plan):
+    g = W.rng(31)
+    text = W.uniform_ascii(300_017, g)
+    pats = (W.cut_patterns(text, 300, 4, 40, g) + W.random_patterns(300, 3, 12, g)
+            + [b"A", b"ACGT", b"ACGT", b"CG"])
+    text[1000:1010] = ord("N")
+    text[5000] = ord("a")
+    print("plan", PLANS[plan], flush=True)
+    res = _gpu(pats, text, plan=PLANS[plan])
+    _check(res, pats, text)
+
+
+def test_edge_sizes_and_ragged_tails():
+    g = W.rng(32)
+    pats = W.random_patterns(100, 1, 10, g) + [b"ACGTACGTACGTACGTACGT"]
+    tab = pf.Table(pats)
+    for n in [0, 1, 2, 3, 5, 19, 20, 21, 4095, 4096, 4097, 8191, 8192, 8193, 16384 + 7,
+              3 * 8192 - 1, 100_000]:
+        text = W.uniform_ascii(n, g)
+        print("n=%d" % n, flush=True)
+        for plan in (None, dict(block=256, jump_depth=7), dict(variant=pf.PFAC_VARIANT_GLOBAL)):
+            res = _gpu(pats, text, plan=plan, table=tab)
+            _check(res, pats, text)
+            res = _gpu(pats, text, plan=plan, table=tab, enc="2bit")
+            _check(res, pats, text)
+
+
+def test_every_byte_value_and_misaligned_text():
+    g = W.rng(33)
+    text = W.uniform_ascii(50_000, g)
+    junk = g.integers(0, 256, size=5000).astype(np.uint8)
+    idx = g.integers(0, text.size, size=5000)
+    text[idx] = junk
+    text[:256] = np.arange(256, dtype=np.uint8)
+    pats = W.random_patterns(200, 1, 6, g) + W.cut_patterns(text[20000:], 50, 5, 30, g)
+    pats = [p for p in pats if all(c in b"ACGT" for c in p)]
+    for off in (0, 1, 3, 7):
+        res = _gpu(pats, text, offset=off)
+        _check(res, pats, text)
+
+
+def test_homopolymer_worst_case_walks():
+    """All-A text against A, AA, ..., A^64: every walk runs to the deepest
+    state (the longest walks the method has)."""
+    pats = [b"A" * L for L in range(1, 65)] + [b"C" * 64]
+    text = np.full(70_001, ord("A"), dtype=np.uint8)
+    text[40_000] = ord("C")
+    for plan in (None, dict(variant=pf.PFAC_VARIANT_GLOBAL), dict(block=256, jump_depth=4)):
+        res = _gpu(pats, text, plan=plan)
+        _check(res, pats, text)
+
+
+def test_single_state_trie_and_long_patterns():
+    text = W.uniform_ascii(10_000, W.rng(34))
+    res = _gpu([b"G"], text)
+    _check(res, [b"G"], text)
+    long_pats = [bytes(text[100:100 + 5000]), b"ACGT" * 1500]   # halo beyond LDS staging
+    res = _gpu(long_pats, text)
+    _check(res, long_pats, text)
+    short = [b"ACGT" * 3000]                                    # longer than the text
+    res = _gpu(short, text[:9000])
+    _check(res, short, text[:9000])
+
+
+def test_duplicates_report_smallest_id_and_count_all():
+    text = np.frombuffer(b"ACGTTACGTAACGT" * 1000, dtype=np.uint8)
+    pats = [b"CGT", b"ACGT", b"ACGT", b"CGT", b"ACGT"]
+    res = _gpu(pats, text)
+    _check(res, pats, text)
+    assert set(np.unique(res.match.cpu().numpy())) <= {0, 1, 2}
+
+
+def test_hit_list_overflow_reports_true_count():
+    w = W.plain_workload(0, n=300_000)
+    pats = w.patterns + W.random_patterns(50, 4, 5, W.rng(35))
+    m_ref, total_ref = oracle.scan(pats, w.text)
+    pos, ids = oracle.hits_of(m_ref)
+    cap = pos.size // 3
+    res = _gpu(pats, w.text, hit_cap=cap)
+    assert res.num_hits() == pos.size and res.total() == total_ref
+    h = res.hits[:cap].cpu().numpy()
+    assert np.array_equal(h[:, 0], pos[:cap]) and np.array_equal(h[:, 1], ids[:cap])
+
+
+def test_outputs_are_optional():
+    w = W.plain_workload(0, n=100_000)
+    m_ref, total_ref = oracle.scan(w.patterns, w.text)
+    tab = pf.Table(w.patterns)
+    dt = torch.from_numpy(w.text).to(DEV)
+    r1 = pf.match(tab, dt, dense=False, hit_cap=w.n)
+    r2 = pf.match(tab, dt, hits=False)
+    torch.cuda.synchronize()
+    assert r1.match is None and r1.total() == total_ref
+    pos, ids = oracle.hits_of(m_ref)
+    assert np.array_equal(r1.hit_list()[:, 0], pos)
+    assert np.array_equal(r2.match.cpu().numpy(), m_ref) and r2.num_hits() == pos.size
+
+
+def test_invalid_arguments_are_rejected():
+    with pytest.raises(pf.PfacError) as e:
+        pf.Table([b"ACGT", b"ACXT"])
+    assert e.value.code == -2 and e.value.bad_index == 1
+    with pytest.raises(pf.PfacError):
+        pf.Table([])
+    tab = pf.Table([b"ACGT"])
+    dt = torch.zeros(16, dtype=torch.uint8, device=DEV)
+    with pytest.raises(pf.PfacError):
+        pf.match(tab, dt, plan=dict(block=300))
+    with pytest.raises(pf.PfacError):
+        pf.match(tab, dt, plan=dict(jump_depth=9))
+
+
+def test_batch_matches_per_text_oracle():
+    wb = W.batch_workload(num_texts=300, num_patterns=3000, median=3000.0, hi=60_000)
+    print("batch: texts=%d bases=%d" % (wb.lengths.size, wb.total_bases), flush=True)
+    tab = pf.Table(wb.patterns)
+    base = torch.from_numpy(wb.buffer).to(DEV)
+    for plan in (None, dict(block=256, jump_depth=6), dict(variant=pf.PFAC_VARIANT_GLOBAL)):
+        res = pf.match_batch([tab], base, wb.offsets, wb.lengths, plan=plan)
+        torch.cuda.synchronize()
+        m = res.match.cpu().numpy()
+        c = res.counters.cpu().numpy()
+        hits = res.hits.cpu().numpy()
+        hpos = 0
+        tot_h = tot_o = 0
+        for t in range(wb.lengths.size):
+            txt = wb.text(t)
+            m_ref, total_ref = oracle.scan(wb.patterns, txt)
+            o = int(res.match_offsets[t])
+            assert np.array_equal(m[o:o + txt.size], m_ref), t
+            pos, ids = oracle.hits_of(m_ref)
+            assert c[2 + 2 * t] == pos.size and c[3 + 2 * t] == total_ref
+            hh = hits[hpos:hpos + pos.size]
+            assert np.all(hh[:, 0] == t)
+            assert np.array_equal(hh[:, 1], pos) and np.array_equal(hh[:, 2], ids)
+            hpos += pos.size
+            tot_h += pos.size
+            tot_o += total_ref
+        assert c[0] == tot_h and c[1] == tot_o
+
+
+def test_batch_several_tables_and_encodings():
+    g = W.rng(36)
+    sets = [W.random_patterns(50, 3, 9, g), W.random_patterns(500, 8, 20, g), [b"ACGT"]]
+    tabs = [pf.Table(s) for s in sets]
+    texts = [W.uniform_ascii(int(L), g) for L in [0, 1, 17, 4096, 10_000, 33_333, 7]]
+    # ASCII texts at unaligned offsets, then the same texts packed
+    parts, offs, encs, lens = [], [], [], []
+    cur = 0
+    for t in texts:
+        pad = 3
+        parts.append(np.zeros(pad, dtype=np.uint8))
+        cur += pad
+        offs.append(cur)
+        parts.append(t)
+        cur += t.size
+        encs.append("ascii")
+        lens.append(t.size)
+    for t in texts:
+        pad = (-cur) % 16
+        parts.append(np.zeros(pad, dtype=np.uint8))
+        cur += pad
+        p = W.pack2bit(W.ascii_to_codes(t))
+        offs.append(cur)
+        parts.append(p)
+        cur += p.size
+        encs.append("2bit")
+        lens.append(t.size)
+    buf = torch.from_numpy(np.concatenate(parts)).to(DEV)
+    tid = [i % 3 for i in range(len(lens))]
+    res = pf.match_batch(tabs, buf, offs, lens, table_index=tid, enc=encs)
+    torch.cuda.synchronize()
+    m = res.match.cpu().numpy()
+    c = res.counters.cpu().numpy()
+    for i, L in enumerate(lens):
+        t = texts[i % len(texts)]
+        m_ref, total_ref = oracle.scan(sets[tid[i]], t)
+        o = int(res.match_offsets[i])
+        assert np.array_equal(m[o:o + L], m_ref), i
+        assert c[3 + 2 * i] == total_ref

@@ -1,0 +1,182 @@
+"""CPU tests of the library's host side: the C ABI loads and exports every
+declared symbol, and the host-built table (breadth-first numbering, packed
+edges, root jump tables) reproduces the oracle when walked."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from _checkers import read_golden
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FINAL = 0x80000000
+MASK = 0x7FFFFFFF
+
+
+def _lib():
+    from paper_1811_10498_amd import _lib as L
+    return L.lib()
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib()
+    declared = set()
+    inc = os.path.join(ROOT, "include")
+    for name in os.listdir(inc):
+        if name.endswith(".h"):
+            src = open(os.path.join(inc, name)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            declared |= set(re.findall(r"^\s*(?:const\s+)?[\w ]+\*?\s*\b(pfac_\w+)\s*\(", src,
+                                       flags=re.M))
+    assert {"pfac_build_table", "pfac_match", "pfac_match_batch"} <= declared
+    for sym in sorted(declared):
+        assert hasattr(lib, sym), sym
+    assert lib.pfac_version().decode().startswith("pfac")
+    assert lib.pfac_strerror(-2).decode()
+
+
+def host_table(patterns, K=None):
+    lib = _lib()
+    pats = [bytes(p) for p in patterns]
+    bufs = [ctypes.create_string_buffer(p, max(1, len(p))) for p in pats]
+    arr = (ctypes.c_void_p * len(pats))(*[ctypes.addressof(b) for b in bufs])
+    lens = (ctypes.c_uint32 * len(pats))(*[len(p) for p in pats])
+    S = ctypes.c_uint64(0)
+    bad = ctypes.c_int64(-1)
+    rc = lib.pfac_build_host(ctypes.cast(arr, ctypes.c_void_p), ctypes.cast(lens, ctypes.c_void_p),
+                             len(pats), None, None, None, 0, 0, None, None, None,
+                             ctypes.byref(S), ctypes.byref(bad))
+    if rc != 0:
+        return rc, bad.value, None
+    cap = S.value
+    nxt = np.zeros(4 * cap, dtype=np.uint32)
+    pid = np.zeros(cap, dtype=np.int32)
+    mult = np.zeros(cap, dtype=np.uint32)
+    jump = jpid = jcnt = None
+    if K:
+        jump = np.zeros(4 ** K, dtype=np.uint32)
+        jpid = np.zeros(4 ** K, dtype=np.int32)
+        jcnt = np.zeros(4 ** K, dtype=np.uint32)
+    rc = lib.pfac_build_host(ctypes.cast(arr, ctypes.c_void_p), ctypes.cast(lens, ctypes.c_void_p),
+                             len(pats), nxt.ctypes.data, pid.ctypes.data, mult.ctypes.data, cap,
+                             K or 0, jump.ctypes.data if K else None,
+                             jpid.ctypes.data if K else None, jcnt.ctypes.data if K else None,
+                             ctypes.byref(S), ctypes.byref(bad))
+    assert rc == 0
+    return 0, -1, dict(next=nxt.reshape(-1, 4), pid=pid, mult=mult, jump=jump, jpid=jpid,
+                       jcnt=jcnt, S=cap)
+
+
+CODE = {ord("A"): 0, ord("C"): 1, ord("G"): 2, ord("T"): 3}
+
+
+def walk_all(t, text):
+    """PFAC walk (paper Sec. IV) over the host table, every start position."""
+    text = bytes(text)
+    n = len(text)
+    m = np.zeros(n, dtype=np.int32)
+    total = 0
+    nxt, pid, mult = t["next"], t["pid"], t["mult"]
+    for i in range(n):
+        s = 0
+        for q in range(i, n):
+            c = CODE.get(text[q])
+            if c is None:
+                break
+            e = int(nxt[s, c])
+            if e == 0:
+                break
+            s = e & MASK
+            if e & FINAL:
+                m[i] = pid[s]
+                total += int(mult[s])
+    return m, total
+
+
+def test_fig1_breadth_first_numbering():
+    g = read_golden("fig1_goto.txt")
+    pats = [p.encode() for p in g["patterns"].split()]
+    rc, _, t = host_table(pats)
+    assert rc == 0 and t["S"] == 10
+    # breadth-first: depth 1 = A, C, T; depth 2 = AC, CT, TG; depth 3 = ACG, CTG; depth 4 = CTGT
+    finals = {int(t["pid"][s]): s for s in range(t["S"]) if t["pid"][s]}
+    assert finals == {1: 4, 2: 7, 3: 9, 4: 6}
+    # every edge points to a larger state number and the state depth never decreases
+    depth = np.zeros(t["S"], dtype=int)
+    for s in range(t["S"]):
+        for a in range(4):
+            e = int(t["next"][s, a])
+            if e:
+                assert (e & MASK) > s
+                depth[e & MASK] = depth[s] + 1
+                assert bool(e & FINAL) == bool(t["pid"][e & MASK])
+    assert np.all(np.diff(depth) >= 0)
+
+
+def test_walking_host_table_reproduces_oracle_small():
+    g = W.rng(41)
+    for case in range(60):
+        pats = W.random_patterns(int(g.integers(1, 20)), 1, 7, g)
+        if case % 3 == 0:
+            pats += pats[: 3]          # duplicates
+        text = W.uniform_ascii(int(g.integers(0, 400)), g)
+        if text.size > 10:
+            text[int(g.integers(0, text.size))] = ord("N")
+        rc, _, t = host_table(pats)
+        assert rc == 0
+        m, total = walk_all(t, text)
+        mr, tr = oracle.scan(pats, text)
+        assert np.array_equal(m, mr) and total == tr
+
+
+def test_walking_host_table_reproduces_oracle_workload():
+    w = W.plain_workload(0, n=20_000)
+    rc, _, t = host_table(w.patterns)
+    m, total = walk_all(t, w.text)
+    mr, tr = oracle.scan(w.patterns, w.text)
+    assert np.array_equal(m, mr) and total == tr
+
+
+@pytest.mark.parametrize("K", [4, 5, 6, 7])
+def test_root_jump_table_is_the_k_step_walk(K):
+    g = W.rng(50 + K)
+    pats = W.random_patterns(300, 1, 12, g) + [b"A" * 3, b"ACG", b"ACG"]
+    rc, _, t = host_table(pats, K=K)
+    nxt, pid, mult = t["next"], t["pid"], t["mult"]
+    for x in range(4 ** K):
+        s, best, cnt, alive, fin = 0, 0, 0, True, False
+        for d in range(K):
+            e = int(nxt[s, (x >> (2 * d)) & 3])
+            if e == 0:
+                alive = False
+                break
+            s = e & MASK
+            if e & FINAL:
+                fin = True
+                best = int(pid[s])
+                cnt += int(mult[s])
+        j = int(t["jump"][x])
+        assert (j & MASK) == (s if alive else 0)
+        assert bool(j & FINAL) == fin
+        if fin:
+            assert t["jpid"][x] == best and t["jcnt"][x] == cnt
+
+
+def test_host_build_rejects_bad_patterns():
+    rc, bad, _ = host_table([b"ACGT", b"AC-T"])
+    assert rc == -2 and bad == 1
+    rc, bad, _ = host_table([b"ACGT", b""])
+    assert rc == -2 and bad == 1
+    rc, bad, _ = host_table([b"acgt"])
+    assert rc == -2 and bad == 0
+
+
+def test_state_counts_of_workload_tries():
+    """Trie sizes of the benchmark pattern sets (recorded in the design notes)."""
+    w = W.plain_workload(0)
+    rc, _, t = host_table(w.patterns)
+    assert 2000 < t["S"] < 3500
