@@ -80,22 +80,19 @@ typedef struct {
 } pfac_table_stats;
 
 /* Launch shape of a match call.  Any field left 0 is chosen by the library.
- * Results never depend on the plan (every plan computes the same walk). */
+ * Results never depend on the plan: every plan computes the same walks. */
 typedef struct {
   uint32_t block;       /* threads per workgroup: 256, 512 or 1024 */
-  uint32_t jump_depth;  /* root jump depth K: 0 = walk every level from the root,
-                           4..7 = first K levels resolved by one LDS lookup of the
-                           K-base window; PFAC_JUMP_OFF forces 0 */
-  uint32_t hot_states;  /* rows of the breadth-first state prefix staged in LDS
-                           (PFAC_HOT_NONE = none) */
+  uint32_t depth;       /* filter depth D, 6..10: every position first looks up its
+                           D-base window in an LDS bitmap of 4^D bits; only windows
+                           whose walk continues past depth D (or passes a final state
+                           within D bases) go on to the global-memory trie */
   uint32_t grid;        /* persistent workgroups (0 = fill the device) */
-  uint32_t variant;     /* PFAC_VARIANT_TILED (LDS text tile + halo) or
-                           PFAC_VARIANT_GLOBAL (text and table read straight from
-                           global memory, one walk per thread) */
+  uint32_t variant;     /* PFAC_VARIANT_TILED (LDS text tile + filter bitmap) or
+                           PFAC_VARIANT_GLOBAL (every walk from the root, text and
+                           table read straight from global memory) */
 } pfac_plan;
 
-#define PFAC_JUMP_OFF 0xFFFFFFFFu
-#define PFAC_HOT_NONE 0xFFFFFFFFu
 enum { PFAC_VARIANT_TILED = 0, PFAC_VARIANT_GLOBAL = 1 };
 
 /* Per-text descriptor of a batched call (all offsets are from the bases the
@@ -177,17 +174,17 @@ int pfac_default_plan(const pfac_table* table, uint64_t n, int enc, pfac_plan* o
  *            child), bit 31 set when the child is a final state
  *   pid      int32[cap]: smallest pattern ID ending at the state, 0 = none
  *   mult     uint32[cap]: number of pattern IDs ending at the state
- *   jump     uint32[4^K] or NULL, with K = jump_depth (4..7): the root jump
- *            entry of every K-base window (first base in the low bits): state
- *            after the K steps (0 if the walk stopped earlier), bit 31 set if
- *            a final state was passed; jump_pid/jump_cnt (or NULL) receive the
- *            longest pattern passed and the occurrences passed
+ *   jump     uint32[4^D] or NULL, D = depth (6..10): for every D-base window
+ *            (first base in the low bits) the state reached after D steps of
+ *            the walk (0 if it stopped earlier), bit 31 set if a final state was
+ *            passed; jump_pid/jump_cnt (or NULL) receive the longest pattern
+ *            passed and the occurrences passed within the D steps
  * States are numbered breadth-first.  *num_states always receives the state
- * count; arrays are written only when it is <= cap.
+ * count; the state arrays are written only when it is <= cap.
  */
 int pfac_build_host(const char* const* patterns, const uint32_t* lengths, uint32_t num,
                     uint32_t* next, int32_t* pid, uint32_t* mult, uint64_t cap,
-                    uint32_t jump_depth, uint32_t* jump, int32_t* jump_pid, uint32_t* jump_cnt,
+                    uint32_t depth, uint32_t* jump, int32_t* jump_pid, uint32_t* jump_cnt,
                     uint64_t* num_states, int64_t* bad_index);
 
 /* Human-readable text of a status code (static storage). */

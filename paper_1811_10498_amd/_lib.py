@@ -10,8 +10,6 @@ LIB_PATH = os.path.join(HERE, "libpfac.so")
 
 PFAC_TEXT_ASCII = 0
 PFAC_TEXT_2BIT = 1
-PFAC_JUMP_OFF = 0xFFFFFFFF
-PFAC_HOT_NONE = 0xFFFFFFFF
 PFAC_VARIANT_TILED = 0
 PFAC_VARIANT_GLOBAL = 1
 
@@ -22,9 +20,8 @@ EXPORTS = (
 
 
 class PfacPlan(ctypes.Structure):
-    _fields_ = [("block", ctypes.c_uint32), ("jump_depth", ctypes.c_uint32),
-                ("hot_states", ctypes.c_uint32), ("grid", ctypes.c_uint32),
-                ("variant", ctypes.c_uint32)]
+    _fields_ = [("block", ctypes.c_uint32), ("depth", ctypes.c_uint32),
+                ("grid", ctypes.c_uint32), ("variant", ctypes.c_uint32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}

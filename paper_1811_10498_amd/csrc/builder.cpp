@@ -114,29 +114,51 @@ int build_host_table(const char* const* patterns, const uint32_t* lengths, uint3
       if (d < 32 && cnt == (1ull << (2 * d))) full = d; else break;
     }
     out->max_depth_full = full;
-    // 4. root jump tables: walk each K-base window from the root
-    for (uint32_t K = kMinJump; K <= kMaxJump; ++K) {
-      const uint32_t E = 1u << (2 * K);
-      out->jump[K].assign(E, 0);
-      out->jres[K].assign(E, OutEntry{0, 0});
-      for (uint32_t x = 0; x < E; ++x) {
-        uint32_t s = 0;
-        int32_t best = 0;
-        uint32_t cnt = 0;
-        bool finals = false, alive = true;
-        for (uint32_t d = 0; d < K; ++d) {
-          uint32_t e = out->next[(uint64_t)s * 4 + ((x >> (2 * d)) & 3)];
-          if (e == 0) { alive = false; break; }
-          s = e & kStateMask;
-          if (e & kFinalBit) {
-            finals = true;
-            best = out->out[s].pid;
-            cnt += out->out[s].mult;
-          }
+    // 4. root jump tables of depth D: the result of the first D steps of the
+    //    walk for every D-base window, filled by a depth-first pass over the
+    //    trie (windows that leave the trie early share their entry)
+    for (uint32_t D = kMinJump; D <= kMaxJump; ++D) {
+      const uint64_t E = 1ull << (2 * D);
+      out->jump[D].assign(E, 0);
+      out->jres[D].assign(E, OutEntry{0, 0});
+      out->bitmap[D].assign(E / 32, 0);
+      struct Frame { uint32_t s; uint32_t d; uint64_t key; int32_t best; uint32_t cnt; };
+      std::vector<Frame> stack;
+      stack.push_back(Frame{0, 0, 0, 0, 0});
+      while (!stack.empty()) {
+        const Frame f = stack.back();
+        stack.pop_back();
+        if (f.d == D) {
+          out->jump[D][f.key] = f.s | (f.cnt ? kFinalBit : 0u);
+          out->jres[D][f.key] = OutEntry{f.best, f.cnt};
+          continue;
         }
-        out->jump[K][x] = (alive ? s : 0u) | (finals ? kFinalBit : 0u);
-        out->jres[K][x] = OutEntry{best, cnt};
+        for (uint32_t a = 0; a < 4; ++a) {
+          const uint32_t e = out->next[(uint64_t)f.s * 4 + a];
+          const uint64_t key = f.key | ((uint64_t)a << (2 * f.d));
+          if (e == 0) {
+            // walk stops after d bases: every window with this prefix gets
+            // the finals passed so far (nothing if none)
+            if (f.cnt) {
+              const uint64_t stride = 1ull << (2 * (f.d + 1));
+              for (uint64_t x = key; x < E; x += stride) {
+                out->jump[D][x] = kFinalBit;
+                out->jres[D][x] = OutEntry{f.best, f.cnt};
+              }
+            }
+            continue;
+          }
+          const uint32_t c = e & kStateMask;
+          Frame g{c, f.d + 1, key, f.best, f.cnt};
+          if (e & kFinalBit) {
+            g.best = out->out[c].pid;
+            g.cnt += out->out[c].mult;
+          }
+          stack.push_back(g);
+        }
       }
+      for (uint64_t x = 0; x < E; ++x)
+        if (out->jump[D][x]) out->bitmap[D][x >> 5] |= 1u << (x & 31);
     }
   } catch (const std::bad_alloc&) {
     return PFAC_E_NOMEM;
@@ -148,11 +170,11 @@ int build_host_table(const char* const* patterns, const uint32_t* lengths, uint3
 
 extern "C" int pfac_build_host(const char* const* patterns, const uint32_t* lengths, uint32_t num,
                                uint32_t* next, int32_t* pid, uint32_t* mult, uint64_t cap,
-                               uint32_t jump_depth, uint32_t* jump, int32_t* jump_pid,
+                               uint32_t depth, uint32_t* jump, int32_t* jump_pid,
                                uint32_t* jump_cnt, uint64_t* num_states, int64_t* bad_index) {
   using namespace pfac;
   if (!num_states) return PFAC_E_ARG;
-  if (jump && (jump_depth < kMinJump || jump_depth > kMaxJump)) return PFAC_E_ARG;
+  if (jump && (depth < kMinJump || depth > kMaxJump)) return PFAC_E_ARG;
   HostTable h;
   int rc = build_host_table(patterns, lengths, num, &h, bad_index);
   if (rc != PFAC_OK) return rc;
@@ -165,11 +187,11 @@ extern "C" int pfac_build_host(const char* const* patterns, const uint32_t* leng
     }
   }
   if (jump) {
-    const uint32_t E = 1u << (2 * jump_depth);
-    memcpy(jump, h.jump[jump_depth].data(), E * sizeof(uint32_t));
-    for (uint32_t x = 0; x < E; ++x) {
-      if (jump_pid) jump_pid[x] = h.jres[jump_depth][x].pid;
-      if (jump_cnt) jump_cnt[x] = h.jres[jump_depth][x].mult;
+    const uint64_t E = 1ull << (2 * depth);
+    memcpy(jump, h.jump[depth].data(), E * sizeof(uint32_t));
+    for (uint64_t x = 0; x < E; ++x) {
+      if (jump_pid) jump_pid[x] = h.jres[depth][x].pid;
+      if (jump_cnt) jump_cnt[x] = h.jres[depth][x].mult;
     }
   }
   return PFAC_OK;

@@ -3,25 +3,30 @@
 // Semantics (paper Sec. IV): every start position of the text walks the
 // failure-less goto trie from the root, one base per step, stops at the
 // first missing transition, and reports the last (= longest) pattern it
-// passed.  The paper launches one thread per character with the text staged
-// in shared memory and the table read through the texture cache (Sec. V.B,
-// V.C, Sec. VII).  The gfx950 design keeps the walk and reorganises the
-// memory side:
-//   * text: 16-byte coalesced loads of a tile plus a halo of max_len-1
-//     bases, converted once to 2 bits per base (plus an "invalid" bit) in LDS;
-//   * table: the first K levels of every walk are one LDS lookup of a root
-//     jump table indexed by the K-base window (K = 4..7); deeper levels read
-//     the breadth-first numbered next-state table, optionally with its
-//     hot prefix staged in LDS, the rest served by L2 / Infinity Cache;
-//   * outputs: dense int32 per position with 16-byte non-temporal stores,
-//     and a position-ordered hit list built with a block scan plus a
-//     decoupled look-back across tiles (tiles are taken from an atomic
-//     ticket, so every tile's predecessors are already running);
-//   * the launch is persistent: workgroups loop over tiles (and over the
-//     texts of a batch) until the ticket passes the last tile.
+// passed.  The paper launches one thread per character, stages the text in
+// shared memory and reads the table through the texture cache (Sec. V.B,
+// V.C, VII).  The gfx950 design keeps the walk and reorganises the memory
+// side around one observation: in a random-like text almost every walk ends
+// within the first log4(#patterns) levels, where the trie is dense.
+//   * Filter: the first D steps of every walk (D = 6..10) depend only on the
+//     D-base window at the position.  A bitmap of 4^D bits in LDS says which
+//     windows lead anywhere (continue past depth D, or pass a final state);
+//     every other position reports nothing after one LDS lookup.
+//   * Deep walks: the surviving positions of a wave are compacted into an
+//     LDS queue and walked by all 64 lanes together: one global read of the
+//     depth-D jump table, then the breadth-first numbered next-state table
+//     (L2 / Infinity Cache resident), one base per step.
+//   * Text: each wave stages its 1024-position tile plus a halo of
+//     max_len-1 bases with 16-byte loads, as 2-bit codes plus an "invalid"
+//     bit per base (bytes other than A,C,G,T, and everything past the end).
+//   * Outputs: the dense int32 array leaves through LDS with 16-byte
+//     non-temporal stores; hits are counted per tile and parked in a
+//     fixed-size slot per tile; a reduce kernel and a scatter kernel then
+//     place them in position order.  No workgroup ever waits for another.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <utility>
@@ -31,9 +36,11 @@
 
 namespace pfac {
 
-constexpr uint32_t kPPT = 16;               // start positions per thread per tile
-constexpr uint32_t kGroups = kPPT / 4;      // groups of 4 consecutive positions
-constexpr uint32_t kMaxHaloLds = 4096;      // longest halo staged in LDS (bases)
+constexpr uint32_t kTile = 1024;       // start positions per wave tile
+constexpr uint32_t kSub = 256;         // positions per sub-chunk (4 per lane)
+constexpr uint32_t kSlot = 16;         // hits parked per tile
+constexpr uint32_t kMaxHalo = 4096;    // longest halo staged in LDS (bases)
+constexpr uint32_t kRedTiles = 4096;   // tiles per reduce/scatter workgroup
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
@@ -47,33 +54,33 @@ struct DevSeg {
 };
 static_assert(sizeof(DevSeg) == sizeof(pfac_text_desc), "descriptor layout");
 
-// Look-back status word: [63:42] launch epoch, [41:40] flag, [39:0] value.
-constexpr uint32_t kEpochBits = 22;
-constexpr uint64_t kValMask = (1ull << 40) - 1;
-constexpr unsigned long long kFlagAgg = 1ull << 40;
-constexpr unsigned long long kFlagIncl = 2ull << 40;
+struct Slot {
+  uint32_t pos;
+  int32_t pid;
+};
 
-struct KParams {
-  const DevTable* tables;         // device array, indexed by DevSeg::table (batch)
-  const DevSeg* segs;             // device array (batch)
-  const uint64_t* tile_prefix;    // device [nsegs+1] first tile of each text (batch)
-  uint32_t nsegs;
-  uint32_t single;                // 1: one text, described by seg0/tab0
-  uint64_t total_tiles;
+// Parameters of the scan kernel (one table per launch).
+struct ScanParams {
+  const uint32_t* next;
+  const OutEntry* out;
+  const uint32_t* jump;           // depth-D jump table (TILED)
+  const OutEntry* jres;
+  const uint32_t* bitmap;         // 4^D bits (TILED)
+  uint32_t D;
+  uint32_t halo;                  // staged bases past the tile, multiple of 64
+  uint32_t single;                // 1: one text (seg0), tiles 0..local_tiles-1
+  uint32_t ngroup;                // batch: texts handled by this launch
+  DevSeg seg0;
+  const DevSeg* segs;             // batch: all texts
+  const uint32_t* group_segs;     // batch: text index of each text of this launch
+  const uint64_t* group_prefix;   // batch: [ngroup+1] first local tile of each
+  const uint64_t* tile_prefix;    // batch: [nsegs+1] first global tile of each text
+  uint64_t local_tiles;
   const uint8_t* text;
   int32_t* match;
-  void* hits;
-  uint64_t hit_cap;
-  unsigned long long* counters;   // [2]
-  unsigned long long* seg_counters;  // [2*nsegs] (batch) or nullptr
-  uint32_t* ticket;
-  unsigned long long* status;
-  uint32_t epoch;
-  uint32_t K;
-  uint32_t hot;
-  uint32_t halo;                  // staged halo, multiple of 64 bases
-  DevSeg seg0;
-  DevTable tab0;
+  uint32_t* tile_hits;            // [tiles]
+  unsigned long long* tile_occ;   // [tiles]
+  Slot* slots;                    // [tiles * kSlot] or nullptr
 };
 
 // ---------------------------------------------------------------- device helpers
@@ -87,100 +94,39 @@ __device__ __forceinline__ int ascii_code(uint32_t b) {
 // 0,1,2,3; a byte is a base iff re-encoding its code gives the byte back.
 __device__ __forceinline__ void ascii4(uint32_t x, uint32_t& code8, uint32_t& inv4) {
   const uint32_t cb = ((x >> 1) ^ (x >> 2)) & 0x03030303u;
-  const uint32_t expect = __builtin_amdgcn_perm(0u, 0x54474341u, cb);  // bytes 'A','C','G','T'
+  const uint32_t expect = __builtin_amdgcn_perm(0u, 0x54474341u, cb);  // 'A','C','G','T'
   const uint32_t t = x ^ expect;
   const uint32_t nz = (((t & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | t) & 0x80808080u;
   inv4 = ((nz >> 7) * 0x01020408u) >> 24;
   code8 = (cb * 0x01041040u) >> 24;
 }
 
-template <int BLOCK>
-__device__ __forceinline__ unsigned long long block_sum_u64(unsigned long long v,
-                                                            unsigned long long* red) {
-  #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  const int w = threadIdx.x >> 6;
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[w] = v;
-  __syncthreads();
-  unsigned long long s = 0;
-  #pragma unroll
-  for (int i = 0; i < BLOCK / 64; ++i) s += red[i];
-  return s;
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
 }
 
-// Exclusive block scan of a small per-thread count; *total gets the sum.
-template <int BLOCK>
-__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* wsum, uint32_t* total) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+  #pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Exclusive prefix over the 64 lanes; *total receives the wave sum.
+__device__ __forceinline__ uint32_t wave_excl(uint32_t v, uint32_t* total) {
+  const int lane = threadIdx.x & 63;
   uint32_t inc = v;
   #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
-    uint32_t y = __shfl_up(inc, o, 64);
+    const uint32_t y = __shfl_up(inc, o, 64);
     if (lane >= o) inc += y;
   }
-  __syncthreads();
-  if (lane == 63) wsum[w] = inc;
-  __syncthreads();
-  uint32_t before = 0, all = 0;
-  #pragma unroll
-  for (int i = 0; i < BLOCK / 64; ++i) {
-    const uint32_t s = wsum[i];
-    before += (i < w) ? s : 0u;
-    all += s;
-  }
-  *total = all;
-  return before + inc - v;
+  *total = __shfl(inc, 63, 64);
+  return inc - v;
 }
 
-// Decoupled look-back (run by all 64 lanes of one wave): publishes this
-// tile's aggregate, sums predecessors back to the nearest inclusive prefix,
-// publishes the inclusive prefix and returns the exclusive one.
-__device__ uint64_t lookback(unsigned long long* status, uint64_t tile, uint64_t agg,
-                             uint32_t epoch) {
-  const int lane = threadIdx.x & 63;
-  const unsigned long long tag = (unsigned long long)epoch << 42;
-  if (tile == 0) {
-    if (lane == 0)
-      __hip_atomic_store(&status[0], tag | kFlagIncl | (agg & kValMask), __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    return 0;
-  }
-  if (lane == 0)
-    __hip_atomic_store(&status[tile], tag | kFlagAgg | (agg & kValMask), __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-  uint64_t prefix = 0;
-  int64_t base = (int64_t)tile - 1;
-  for (;;) {
-    const int64_t idx = base - lane;
-    unsigned long long v = 0;
-    uint32_t flag = 2;
-    if (idx >= 0) {
-      v = __hip_atomic_load(&status[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      flag = ((uint32_t)(v >> 42) == epoch) ? (uint32_t)((v >> 40) & 3) : 0u;
-    }
-    const uint64_t incl = __ballot(flag == 2);
-    const uint64_t notready = __ballot(flag == 0);
-    const int first = incl ? __builtin_ctzll(incl) : 64;
-    const uint64_t upto = (first >= 63) ? ~0ull : ((2ull << first) - 1);
-    if (notready & upto) {
-      __builtin_amdgcn_s_sleep(1);
-      continue;
-    }
-    unsigned long long val = (lane <= first) ? (v & kValMask) : 0ull;
-    #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) val += __shfl_xor(val, o, 64);
-    prefix += val;
-    if (first < 64) break;
-    base -= 64;
-  }
-  if (lane == 0)
-    __hip_atomic_store(&status[tile], tag | kFlagIncl | ((prefix + agg) & kValMask),
-                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return prefix;
-}
-
-// One base of the text for the global-memory variant (out of range = invalid).
+// One base of a text in global memory (out of range = invalid).
 __device__ __forceinline__ int global_base(const uint8_t* t, uint64_t n, uint32_t enc,
                                            uint64_t q) {
   if (q >= n) return -1;
@@ -188,31 +134,32 @@ __device__ __forceinline__ int global_base(const uint8_t* t, uint64_t n, uint32_
   return (t[q >> 2] >> (2 * (q & 3))) & 3;
 }
 
-// Continue one walk from state s at text index q (tile-local for LDS text).
-// s == 0 means "at the root": the root row is row 0 and no edge points back
-// to it, so the loop needs no special case.
+// Continue a walk from state s.  LDS text: q is a tile-local index into the
+// staged codes; global text: q is the text index.  s == 0 is the root: the
+// root row is row 0 and no edge leads back to it.
 template <bool GLOBAL>
-__device__ __forceinline__ void walk(uint32_t s, uint32_t q, const uint32_t* __restrict__ pk,
+__device__ __forceinline__ void walk(uint32_t s, uint64_t q, const uint32_t* __restrict__ pk,
                                      const uint32_t* __restrict__ iv,
-                                     const uint32_t* __restrict__ hot_l, uint32_t hot,
-                                     const DevTable& tab, const uint8_t* gtext, uint64_t gn,
-                                     uint32_t genc, uint64_t gq0, int32_t& best,
+                                     const uint32_t* __restrict__ next,
+                                     const OutEntry* __restrict__ out, const uint8_t* gtext,
+                                     uint64_t gn, uint32_t genc, int32_t& best,
                                      unsigned long long& occ) {
   for (;;) {
     uint32_t c;
     if (GLOBAL) {
-      const int b = global_base(gtext, gn, genc, gq0 + q);
+      const int b = global_base(gtext, gn, genc, q);
       if (b < 0) break;
       c = (uint32_t)b;
     } else {
-      if ((iv[q >> 5] >> (q & 31)) & 1u) break;
-      c = (pk[q >> 4] >> (2 * (q & 15))) & 3u;
+      const uint32_t qq = (uint32_t)q;
+      if ((iv[qq >> 5] >> (qq & 31)) & 1u) break;
+      c = (pk[qq >> 4] >> (2 * (qq & 15))) & 3u;
     }
-    const uint32_t e = (s < hot) ? hot_l[s * 4 + c] : tab.next[(uint64_t)s * 4 + c];
+    const uint32_t e = next[(uint64_t)s * 4 + c];
     if (e == 0) break;
     s = e & kStateMask;
     if (e & kFinalBit) {
-      const OutEntry o = tab.out[s];
+      const OutEntry o = out[s];
       best = o.pid;
       occ += o.mult;
     }
@@ -220,18 +167,18 @@ __device__ __forceinline__ void walk(uint32_t s, uint32_t q, const uint32_t* __r
   }
 }
 
-// Stage the text of [t0, t0+span) of one text into LDS as 2-bit codes (16
-// per word) plus an invalid bit per base (32 per word).  Bases past the end
-// of the text are invalid.
-template <int BLOCK>
-__device__ __forceinline__ void stage_text(const uint8_t* __restrict__ t, uint64_t n, uint32_t enc,
-                                           uint64_t t0, uint32_t span, uint32_t* pk,
-                                           uint32_t* iv) {
+// Stage bases [t0, t0+span) of one text into a wave's LDS area: 2-bit codes
+// (16 per word) and an invalid bit per base (32 per word); bases past the
+// end of the text are invalid, and two sentinel words follow the span.
+__device__ __forceinline__ void stage_text(const uint8_t* __restrict__ t, uint64_t n,
+                                           uint32_t enc, uint64_t t0, uint32_t span,
+                                           uint32_t* pk, uint32_t* iv) {
+  const uint32_t lane = threadIdx.x & 63;
   const uint32_t nwords = span / 16;
   uint16_t* iv16 = reinterpret_cast<uint16_t*>(iv);
   if (enc == PFAC_TEXT_ASCII) {
     const bool aligned = ((reinterpret_cast<uintptr_t>(t) & 15) == 0);
-    for (uint32_t c = threadIdx.x; c < nwords; c += BLOCK) {
+    for (uint32_t c = lane; c < nwords; c += 64) {
       const uint64_t g = t0 + 16ull * c;
       uint32_t w[4];
       if (aligned && g + 16 <= n) {
@@ -261,15 +208,14 @@ __device__ __forceinline__ void stage_text(const uint8_t* __restrict__ t, uint64
       iv16[c] = (uint16_t)inv;
     }
   } else {
-    const uint8_t* tb = t;  // byte k holds bases 4k..4k+3
-    const bool aligned = ((reinterpret_cast<uintptr_t>(tb) & 15) == 0);
+    const bool aligned = ((reinterpret_cast<uintptr_t>(t) & 15) == 0);
     const uint32_t nchunks = span / 64;   // 16 bytes = 64 bases
-    for (uint32_t c = threadIdx.x; c < nchunks; c += BLOCK) {
+    for (uint32_t c = lane; c < nchunks; c += 64) {
       const uint64_t g = t0 + 64ull * c;
       uint32_t w[4];
       uint32_t inv[4] = {0, 0, 0, 0};
       if (aligned && g + 64 <= n) {
-        const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(tb + g / 4));
+        const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(t + g / 4));
         w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
       } else {
         #pragma unroll
@@ -277,7 +223,7 @@ __device__ __forceinline__ void stage_text(const uint8_t* __restrict__ t, uint64
           uint32_t x = 0, m = 0;
           for (int b = 0; b < 16; ++b) {
             const uint64_t q = g + 16 * k + b;
-            if (q < n) x |= (uint32_t)((tb[q >> 2] >> (2 * (q & 3))) & 3u) << (2 * b);
+            if (q < n) x |= (uint32_t)((t[q >> 2] >> (2 * (q & 3))) & 3u) << (2 * b);
             else m |= 1u << b;
           }
           w[k] = x;
@@ -291,246 +237,423 @@ __device__ __forceinline__ void stage_text(const uint8_t* __restrict__ t, uint64
       }
     }
   }
-  // sentinel words after the staged span: no bases, all invalid
-  if (threadIdx.x < 2) {
-    pk[nwords + threadIdx.x] = 0;
-    iv[span / 32 + threadIdx.x] = 0xFFFFFFFFu;
+  if (lane < 2) {
+    pk[nwords + lane] = 0;
+    iv[span / 32 + lane] = 0xFFFFFFFFu;
   }
 }
 
+// LDS of one wave, in 32-bit words, each part a multiple of 4 words so the
+// 16-byte LDS accesses stay aligned: text codes (+2 sentinel words), invalid
+// bits (+2), output staging of a sub-chunk, queue of a sub-chunk (16-bit).
+__host__ __device__ constexpr uint32_t round4(uint32_t x) { return (x + 3) & ~3u; }
+__host__ __device__ constexpr uint32_t pk_words(uint32_t halo) {
+  return round4((kTile + halo) / 16 + 2);
+}
+__host__ __device__ constexpr uint32_t iv_words(uint32_t halo) {
+  return round4((kTile + halo) / 32 + 2);
+}
+__host__ __device__ constexpr uint32_t wave_words(uint32_t halo) {
+  return pk_words(halo) + iv_words(halo) + kSub + kSub / 2;
+}
+
+// Main scan.  Each wave takes whole 1024-position tiles (grid-stride).
 template <int BLOCK, bool GLOBAL>
-__global__ __launch_bounds__(BLOCK) void pfac_kernel(KParams p) {
+__global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
   extern __shared__ uint32_t lds[];
-  constexpr uint32_t TILE = BLOCK * kPPT;
-  __shared__ uint32_t s_tile_lo, s_seg;
-  __shared__ unsigned long long s_red[BLOCK / 64];
-  __shared__ uint32_t s_wsum[BLOCK / 64];
-  __shared__ unsigned long long s_prefix;
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const uint32_t D = GLOBAL ? 0u : p.D;
+  const uint32_t bm_words = GLOBAL ? 0u : (1u << (2 * D)) / 32;
+  uint32_t* bm = lds;
+  const uint32_t span = kTile + p.halo;
+  uint32_t* pk = lds + bm_words + wave * (GLOBAL ? 0u : wave_words(p.halo));
+  uint32_t* iv = pk + pk_words(p.halo);
+  int32_t* outs = reinterpret_cast<int32_t*>(iv + iv_words(p.halo));
+  uint16_t* queue = reinterpret_cast<uint16_t*>(outs + kSub);
+  __shared__ int32_t g_outs[GLOBAL ? BLOCK / 64 * kSub : 1];
+  __shared__ uint16_t g_queue[GLOBAL ? BLOCK / 64 * kSub : 1];
+  if (GLOBAL) {
+    outs = g_outs + wave * kSub;
+    queue = g_queue + wave * kSub;
+  }
 
-  const uint32_t K = GLOBAL ? 0u : p.K;
-  const uint32_t hot = GLOBAL ? 0u : p.hot;
-  const uint32_t jsize = K ? (1u << (2 * K)) : 0u;
-  const uint32_t span = TILE + p.halo;
-  uint32_t* jump_l = lds;
-  uint32_t* hot_l = lds + jsize;
-  uint32_t* pk = hot_l + 4 * hot;
-  uint32_t* iv = pk + span / 16 + 2;
-
-  uint32_t loaded_table = 0xFFFFFFFFu;
-  unsigned long long occ_acc = 0, hits_acc = 0;  // single-text totals of this workgroup
-
-  for (;;) {
-    if (threadIdx.x == 0) {
-      const uint32_t tk = atomicAdd(p.ticket, 1u);
-      s_tile_lo = tk;
-      uint32_t sg = 0;
-      if (!p.single && tk < p.total_tiles) {
-        // last text whose first tile is <= tk (texts with no tiles are skipped)
-        uint32_t lo = 0, hi = p.nsegs;   // invariant: prefix[lo] <= tk < prefix[hi]
-        while (hi - lo > 1) {
-          const uint32_t mid = (lo + hi) >> 1;
-          if (p.tile_prefix[mid] <= tk) lo = mid; else hi = mid;
-        }
-        sg = lo;
-      }
-      s_seg = sg;
-    }
+  if (!GLOBAL) {
+    const u32x4* src = reinterpret_cast<const u32x4*>(p.bitmap);
+    u32x4* dst = reinterpret_cast<u32x4*>(bm);
+    for (uint32_t i = threadIdx.x; i < bm_words / 4; i += BLOCK) dst[i] = src[i];
     __syncthreads();
-    const uint64_t tile = s_tile_lo;
-    if (tile >= p.total_tiles) break;
-    const uint32_t segi = s_seg;
-    const DevSeg seg = p.single ? p.seg0 : p.segs[segi];
-    const uint64_t ts = p.single ? tile : tile - p.tile_prefix[segi];
-    const DevTable tab = p.single ? p.tab0 : p.tables[seg.table];
-    const uint64_t t0 = ts * TILE;
+  }
+
+  const uint32_t dmask = (1u << D) - 1u;
+  const uint32_t xmask = (uint32_t)((1ull << (2 * D)) - 1u);
+  const uint64_t nwaves = (uint64_t)gridDim.x * (BLOCK / 64);
+  for (uint64_t lt = (uint64_t)blockIdx.x * (BLOCK / 64) + wave; lt < p.local_tiles;
+       lt += nwaves) {
+    // ---- which text and tile
+    DevSeg seg;
+    uint64_t ts, gtile;
+    if (p.single) {
+      seg = p.seg0;
+      ts = lt;
+      gtile = lt;
+    } else {
+      uint32_t lo = 0, hi = p.ngroup;   // prefix[lo] <= lt < prefix[hi]
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (p.group_prefix[mid] <= lt) lo = mid; else hi = mid;
+      }
+      const uint32_t si = p.group_segs[lo];
+      seg = p.segs[si];
+      ts = lt - p.group_prefix[lo];
+      gtile = p.tile_prefix[si] + ts;
+    }
+    const uint64_t t0 = ts * kTile;
     const uint64_t n = seg.n;
     const uint8_t* text = p.text + seg.text_off;
-
-    if (!GLOBAL) {
-      if (seg.table != loaded_table) {
-        // root jump table and hot rows of this trie into LDS
-        const uint4* js = reinterpret_cast<const uint4*>(tab.jump);
-        uint4* jd = reinterpret_cast<uint4*>(jump_l);
-        for (uint32_t i = threadIdx.x; i < jsize / 4; i += BLOCK) jd[i] = js[i];
-        const uint32_t hrows = min(hot, tab.num_states);
-        for (uint32_t i = threadIdx.x; i < 4 * hot; i += BLOCK)
-          hot_l[i] = (i < 4 * hrows) ? tab.next[i] : 0u;
-        loaded_table = seg.table;
-      }
-      stage_text<BLOCK>(text, n, seg.enc, t0, span, pk, iv);
-      __syncthreads();
-    }
-
-    // ---- walks: first K levels from the jump table, then the deep loop
-    int32_t best[kPPT];
-    uint32_t st[kPPT];
-    uint32_t pend = 0, slow = 0;
-    unsigned long long occ = 0;
-    const uint32_t kmask = (1u << K) - 1u;
-    const uint32_t xmask = (1u << (2 * K)) - 1u;
-    #pragma unroll
-    for (uint32_t g = 0; g < kGroups; ++g) {
-      const uint32_t q0 = g * 4 * BLOCK + 4 * threadIdx.x;
-      uint64_t win = 0, ivw = 0;
-      if (!GLOBAL && K) {
-        win = ((uint64_t)pk[(q0 >> 4) + 1] << 32 | pk[q0 >> 4]) >> (2 * (q0 & 15));
-        ivw = ((uint64_t)iv[(q0 >> 5) + 1] << 32 | iv[q0 >> 5]) >> (q0 & 31);
-      }
-      #pragma unroll
-      for (uint32_t r = 0; r < 4; ++r) {
-        const uint32_t i = g * 4 + r;
-        best[i] = 0;
-        st[i] = 0;
-        if (!GLOBAL && K && ((uint32_t)(ivw >> r) & kmask) == 0) {
-          const uint32_t x = (uint32_t)(win >> (2 * r)) & xmask;
-          const uint32_t e = jump_l[x];
-          st[i] = e & kStateMask;
-          if (e & kFinalBit) {
-            const OutEntry o = tab.jres[x];
-            best[i] = o.pid;
-            occ += o.mult;
-          }
-          if (st[i]) pend |= 1u << i;
-        } else {
-          pend |= 1u << i;
-          slow |= 1u << i;
-        }
-      }
-    }
-    #pragma unroll
-    for (uint32_t i = 0; i < kPPT; ++i) {
-      if ((pend >> i) & 1u) {
-        const uint32_t q = (i / 4) * 4 * BLOCK + 4 * threadIdx.x + (i % 4) +
-                           (((slow >> i) & 1u) ? 0u : K);
-        walk<GLOBAL>(st[i], q, pk, iv, hot_l, hot, tab, text, n, seg.enc, t0, best[i], occ);
-      }
-    }
-
-    // ---- dense output: 16-byte non-temporal stores of 4 consecutive positions
-    uint32_t hc[kGroups];
-    uint32_t th_hits = 0;
     int32_t* mrow = p.match ? p.match + seg.match_off : nullptr;
     const bool maligned = mrow && ((reinterpret_cast<uintptr_t>(mrow) & 15) == 0);
-    #pragma unroll
-    for (uint32_t g = 0; g < kGroups; ++g) {
-      const uint64_t pos = t0 + g * 4 * BLOCK + 4 * threadIdx.x;
-      hc[g] = (best[4 * g] != 0) + (best[4 * g + 1] != 0) + (best[4 * g + 2] != 0) +
-              (best[4 * g + 3] != 0);
-      th_hits += hc[g];
-      if (mrow) {
-        if (maligned && pos + 4 <= n) {
-          const i32x4 v = {best[4 * g], best[4 * g + 1], best[4 * g + 2], best[4 * g + 3]};
-          __builtin_nontemporal_store(v, reinterpret_cast<i32x4*>(mrow + pos));
-        } else {
-          #pragma unroll
-          for (uint32_t r = 0; r < 4; ++r)
-            if (pos + r < n) mrow[pos + r] = best[4 * g + r];
-        }
-      }
+
+    if (!GLOBAL) {
+      stage_text(text, n, seg.enc, t0, span, pk, iv);
+      wave_sync();
     }
 
-    // ---- tile totals, ordered hit list
-    const unsigned long long tile_hits = block_sum_u64<BLOCK>(th_hits, s_red);
-    if (p.single) {
-      hits_acc += tile_hits;
-      occ_acc += occ;
-    } else {
-      const unsigned long long tile_occ = block_sum_u64<BLOCK>(occ, s_red);
-      if (threadIdx.x == 0) {
-        if (tile_hits) {
-          atomicAdd(&p.counters[0], tile_hits);
-          atomicAdd(&p.seg_counters[2 * segi], tile_hits);
-        }
-        if (tile_occ) {
-          atomicAdd(&p.counters[1], tile_occ);
-          atomicAdd(&p.seg_counters[2 * segi + 1], tile_occ);
-        }
-      }
-    }
-    if (p.hits) {
-      if (threadIdx.x < 64) {
-        const uint64_t pre = lookback(p.status, tile, tile_hits, p.epoch);
-        if (threadIdx.x == 0) s_prefix = pre;
-      }
-      __syncthreads();
-      if (tile_hits) {
-        uint64_t off = s_prefix;
+    unsigned long long occ = 0;
+    uint32_t tile_hits = 0;
+    #pragma unroll 1
+    for (uint32_t sc = 0; sc < kTile / kSub; ++sc) {
+      // ---- classify this lane's 4 positions
+      const uint32_t q0 = sc * kSub + 4 * lane;          // tile-local index
+      const uint64_t pos0 = t0 + q0;                      // text index
+      uint32_t want = 0, slow = 0;
+      if (GLOBAL) {
         #pragma unroll
-        for (uint32_t g = 0; g < kGroups; ++g) {
-          uint32_t tot;
-          const uint32_t ex = block_excl_scan<BLOCK>(hc[g], s_wsum, &tot);
-          uint64_t o = off + ex;
+        for (uint32_t r = 0; r < 4; ++r)
+          if (pos0 + r < n) { want |= 1u << r; slow |= 1u << r; }
+      } else {
+        const uint64_t win =
+            ((uint64_t)pk[(q0 >> 4) + 1] << 32 | pk[q0 >> 4]) >> (2 * (q0 & 15));
+        const uint64_t ivw = ((uint64_t)iv[(q0 >> 5) + 1] << 32 | iv[q0 >> 5]) >> (q0 & 31);
+        #pragma unroll
+        for (uint32_t r = 0; r < 4; ++r) {
+          if (pos0 + r >= n) continue;
+          if (((uint32_t)(ivw >> r) & dmask) != 0) {
+            want |= 1u << r;       // window not all bases: walk from the root
+            slow |= 1u << r;
+          } else {
+            const uint32_t x = (uint32_t)(win >> (2 * r)) & xmask;
+            if ((bm[x >> 5] >> (x & 31)) & 1u) want |= 1u << r;
+          }
+        }
+      }
+      *reinterpret_cast<i32x4*>(outs + 4 * lane) = i32x4{0, 0, 0, 0};
+      // ---- compact the surviving positions of the wave into the queue
+      uint32_t count = 0;
+      #pragma unroll
+      for (uint32_t r = 0; r < 4; ++r) {
+        const uint64_t m = __ballot((want >> r) & 1u);
+        if ((want >> r) & 1u) {
+          const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+          queue[count + rank] = (uint16_t)((4 * lane + r) | (((slow >> r) & 1u) << 15));
+        }
+        count += (uint32_t)__popcll(m);
+      }
+      wave_sync();
+      // ---- walk the queued positions with all lanes
+      for (uint32_t i = lane; i < count; i += 64) {
+        const uint32_t e = queue[i];
+        const uint32_t qs = e & 0x7FFFu;                 // sub-chunk index
+        const uint32_t qt = sc * kSub + qs;              // tile index
+        int32_t best = 0;
+        if (GLOBAL) {
+          walk<true>(0u, t0 + qt, nullptr, nullptr, p.next, p.out, text, n, seg.enc, best, occ);
+        } else if (e & 0x8000u) {
+          walk<false>(0u, qt, pk, iv, p.next, p.out, nullptr, 0, 0, best, occ);
+        } else {
+          const uint64_t w =
+              ((uint64_t)pk[(qt >> 4) + 1] << 32 | pk[qt >> 4]) >> (2 * (qt & 15));
+          const uint32_t x = (uint32_t)w & xmask;
+          const uint32_t j = p.jump[x];
+          if (j & kFinalBit) {
+            const OutEntry o = p.jres[x];
+            best = o.pid;
+            occ += o.mult;
+          }
+          const uint32_t s = j & kStateMask;
+          if (s) walk<false>(s, qt + D, pk, iv, p.next, p.out, nullptr, 0, 0, best, occ);
+        }
+        if (best) outs[qs] = best;
+      }
+      wave_sync();
+      // ---- dense output: one 16-byte store per lane, 1 KB per wave
+      const i32x4 v = *reinterpret_cast<const i32x4*>(outs + 4 * lane);
+      if (mrow) {
+        if (maligned && pos0 + 4 <= n) {
+          __builtin_nontemporal_store(v, reinterpret_cast<i32x4*>(mrow + pos0));
+        } else {
+          if (pos0 < n) mrow[pos0] = v.x;
+          if (pos0 + 1 < n) mrow[pos0 + 1] = v.y;
+          if (pos0 + 2 < n) mrow[pos0 + 2] = v.z;
+          if (pos0 + 3 < n) mrow[pos0 + 3] = v.w;
+        }
+      }
+      // ---- hits of this sub-chunk, in position order, into the tile's slot
+      const uint32_t c = (v.x != 0) + (v.y != 0) + (v.z != 0) + (v.w != 0);
+      if (__ballot(c != 0)) {
+        uint32_t tot;
+        uint32_t o = tile_hits + wave_excl(c, &tot);
+        if (p.slots) {
+          Slot* sl = p.slots + gtile * kSlot;
+          const int32_t vv[4] = {v.x, v.y, v.z, v.w};
           #pragma unroll
           for (uint32_t r = 0; r < 4; ++r) {
-            const int32_t b = best[4 * g + r];
-            if (b) {
-              if (o < p.hit_cap) {
-                const uint32_t pos = (uint32_t)(t0 + g * 4 * BLOCK + 4 * threadIdx.x + r);
-                if (p.single) {
-                  pfac_hit h; h.pos = pos; h.pid = b;
-                  reinterpret_cast<pfac_hit*>(p.hits)[o] = h;
-                } else {
-                  pfac_batch_hit h; h.text = segi; h.pos = pos; h.pid = b;
-                  reinterpret_cast<pfac_batch_hit*>(p.hits)[o] = h;
-                }
-              }
+            if (vv[r]) {
+              if (o < kSlot) sl[o] = Slot{(uint32_t)(pos0 + r), vv[r]};
               ++o;
             }
           }
-          off += tot;
         }
+        tile_hits += tot;
       }
+      wave_sync();
     }
-  }
-
-  if (p.single) {
-    // hits_acc is already a workgroup total (same value in every thread)
-    const unsigned long long o = block_sum_u64<BLOCK>(occ_acc, s_red);
-    if (threadIdx.x == 0) {
-      if (hits_acc) atomicAdd(&p.counters[0], hits_acc);
-      if (o) atomicAdd(&p.counters[1], o);
+    const unsigned long long tocc = wave_sum(occ);
+    if (lane == 0) {
+      p.tile_hits[gtile] = tile_hits;
+      p.tile_occ[gtile] = tocc;
     }
   }
 }
 
-// Zero the counters and the ticket; for a batch also compute the first
-// tile of every text (one workgroup).
-__global__ __launch_bounds__(1024) void pfac_prep_kernel(const DevSeg* segs, uint32_t nsegs,
-                                                         uint32_t tile, uint64_t* tile_prefix,
-                                                         unsigned long long* counters,
-                                                         unsigned long long* seg_counters,
-                                                         uint32_t* ticket) {
-  __shared__ uint64_t wsum[16];
-  __shared__ uint64_t carry;
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (threadIdx.x == 0) {
-    counters[0] = 0;
-    counters[1] = 0;
-    *ticket = 0;
-    carry = 0;
-  }
-  if (seg_counters)
-    for (uint32_t i = threadIdx.x; i < 2 * nsegs; i += 1024) seg_counters[i] = 0;
-  if (!tile_prefix) return;
-  __syncthreads();
-  for (uint32_t b = 0; b < nsegs; b += 1024) {
-    const uint32_t i = b + threadIdx.x;
-    const uint64_t v = (i < nsegs) ? (segs[i].n + tile - 1) / tile : 0;
-    uint64_t inc = v;
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint64_t y = __shfl_up(inc, o, 64);
-      if (lane >= o) inc += y;
+// Per block of kRedTiles tiles: sums of hits and occurrences.  The last
+// block to finish (atomic ticket, reset by that block for the next launch)
+// turns the block sums into block prefixes and writes the totals.
+__global__ __launch_bounds__(1024) void pfac_reduce_kernel(
+    const uint32_t* tile_hits, const unsigned long long* tile_occ, uint64_t tiles,
+    unsigned long long* block_hits, unsigned long long* block_occ,
+    unsigned long long* block_prefix, uint32_t* done, unsigned long long* counters) {
+  __shared__ unsigned long long red_h[16], red_o[16];
+  __shared__ unsigned long long wsum[16];
+  __shared__ unsigned long long carry_h, carry_o;
+  __shared__ bool last;
+  const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t base = (uint64_t)blockIdx.x * kRedTiles;
+  unsigned long long h = 0, o = 0;
+  for (uint32_t i = threadIdx.x; i < kRedTiles; i += 1024) {
+    const uint64_t t = base + i;
+    if (t < tiles) {
+      h += tile_hits[t];
+      o += tile_occ[t];
     }
+  }
+  h = wave_sum(h);
+  o = wave_sum(o);
+  if (lane == 0) { red_h[w] = h; red_o[w] = o; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long sh = 0, so = 0;
+    for (int i = 0; i < 16; ++i) { sh += red_h[i]; so += red_o[i]; }
+    __hip_atomic_store(&block_hits[blockIdx.x], sh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&block_occ[blockIdx.x], so, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+    const uint32_t prev = atomicAdd(done, 1u);
+    last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  // the last block: exclusive scan of the block sums
+  if (threadIdx.x == 0) { carry_h = 0; carry_o = 0; }
+  __syncthreads();
+  for (uint32_t b0 = 0; b0 < gridDim.x; b0 += 1024) {
+    const uint32_t b = b0 + threadIdx.x;
+    unsigned long long vh = 0, vo = 0;
+    if (b < gridDim.x) {
+      vh = __hip_atomic_load(&block_hits[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      vo = __hip_atomic_load(&block_occ[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    unsigned long long inc = vh;
+    for (int off = 1; off < 64; off <<= 1) {
+      const unsigned long long y = __shfl_up(inc, off, 64);
+      if ((int)lane >= off) inc += y;
+    }
+    const unsigned long long so = wave_sum(vo);
     if (lane == 63) wsum[w] = inc;
+    if (lane == 0) red_o[w] = so;
     __syncthreads();
-    uint64_t before = carry;
-    for (int k = 0; k < w; ++k) before += wsum[k];
-    if (i < nsegs) tile_prefix[i] = before + inc - v;
+    unsigned long long before = carry_h;
+    for (uint32_t k = 0; k < w; ++k) before += wsum[k];
+    if (b < gridDim.x) block_prefix[b] = before + inc - vh;
     __syncthreads();
-    if (threadIdx.x == 1023) carry = before + inc;
+    if (threadIdx.x == 0) {
+      unsigned long long th = 0, to = 0;
+      for (int k = 0; k < 16; ++k) { th += wsum[k]; to += red_o[k]; }
+      carry_h += th;
+      carry_o += to;
+    }
     __syncthreads();
   }
-  if (threadIdx.x == 0) tile_prefix[nsegs] = carry;
+  if (threadIdx.x == 0) {
+    counters[0] = carry_h;
+    counters[1] = carry_o;
+    *done = 0;
+  }
+}
+
+// Parameters of the scatter kernel.
+struct ScatterParams {
+  const uint32_t* tile_hits;
+  const Slot* slots;
+  const unsigned long long* block_prefix;
+  uint64_t tiles;
+  void* hits;                     // pfac_hit* (single) or pfac_batch_hit* (batch)
+  uint64_t hit_cap;
+  uint32_t single;
+  // tile -> text (batch), and what an overflowing tile needs to redo its hits
+  uint32_t nsegs;
+  const DevSeg* segs;
+  const uint64_t* tile_prefix;
+  DevSeg seg0;
+  const uint8_t* text;
+  const int32_t* match;           // dense output if it was written, else nullptr
+  const DevTable* tables;         // batch: device array indexed by DevSeg::table
+  DevTable tab0;
+};
+
+__device__ __forceinline__ void put_hit(const ScatterParams& p, uint64_t o, uint32_t text,
+                                        uint32_t pos, int32_t pid) {
+  if (o >= p.hit_cap) return;
+  if (p.single) {
+    reinterpret_cast<pfac_hit*>(p.hits)[o] = pfac_hit{pos, pid};
+  } else {
+    reinterpret_cast<pfac_batch_hit*>(p.hits)[o] = pfac_batch_hit{text, pos, pid};
+  }
+}
+
+__device__ __forceinline__ uint32_t text_of_tile(const ScatterParams& p, uint64_t t) {
+  uint32_t lo = 0, hi = p.nsegs;   // tile_prefix[lo] <= t < tile_prefix[hi]
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (p.tile_prefix[mid] <= t) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Places every tile's hits at its position-ordered offset.  Tiles with more
+// hits than their slot holds take them from the dense output when it was
+// written, otherwise walk their positions again from the root.
+__global__ __launch_bounds__(1024) void pfac_scatter_kernel(ScatterParams p) {
+  __shared__ uint32_t wsum[16];
+  __shared__ uint32_t ovf_tile[kRedTiles];
+  __shared__ unsigned long long ovf_off[kRedTiles];
+  __shared__ uint32_t novf;
+  const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t base = (uint64_t)blockIdx.x * kRedTiles;
+  if (threadIdx.x == 0) novf = 0;
+  // 4 consecutive tiles per thread
+  uint32_t h[4];
+  uint32_t sum = 0;
+  #pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint64_t t = base + 4 * threadIdx.x + k;
+    h[k] = (t < p.tiles) ? p.tile_hits[t] : 0u;
+    sum += h[k];
+  }
+  uint32_t inc = sum;
+  #pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(inc, off, 64);
+    if ((int)lane >= off) inc += y;
+  }
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  uint64_t off = p.block_prefix[blockIdx.x];
+  for (uint32_t k = 0; k < w; ++k) off += wsum[k];
+  off += inc - sum;
+  #pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const uint64_t t = base + 4 * threadIdx.x + k;
+    if (h[k] && off < p.hit_cap) {
+      if (h[k] <= kSlot) {
+        const uint32_t text = p.single ? 0u : text_of_tile(p, t);
+        for (uint32_t j = 0; j < h[k]; ++j) {
+          const Slot s = p.slots[t * kSlot + j];
+          put_hit(p, off + j, text, s.pos, s.pid);
+        }
+      } else {
+        const uint32_t i = atomicAdd(&novf, 1u);
+        ovf_tile[i] = 4 * threadIdx.x + k;
+        ovf_off[i] = off;
+      }
+    }
+    off += h[k];
+  }
+  __syncthreads();
+  // tiles whose hits did not fit their slot: one wave each
+  for (uint32_t i = w; i < novf; i += 16) {
+    const uint64_t t = base + ovf_tile[i];
+    uint64_t o = ovf_off[i];
+    uint32_t text = 0;
+    DevSeg seg = p.seg0;
+    uint64_t ts = t;
+    DevTable tab = p.tab0;
+    if (!p.single) {
+      text = text_of_tile(p, t);
+      seg = p.segs[text];
+      ts = t - p.tile_prefix[text];
+      tab = p.tables[seg.table];
+    }
+    const uint64_t t0 = ts * kTile;
+    const uint8_t* tx = p.text + seg.text_off;
+    for (uint32_t sc = 0; sc < kTile / kSub; ++sc) {
+      const uint64_t pos0 = t0 + sc * kSub + 4 * lane;
+      int32_t v[4] = {0, 0, 0, 0};
+      #pragma unroll
+      for (uint32_t r = 0; r < 4; ++r) {
+        if (pos0 + r >= seg.n) continue;
+        if (p.match) {
+          v[r] = p.match[seg.match_off + pos0 + r];
+        } else {
+          unsigned long long unused = 0;
+          walk<true>(0u, pos0 + r, nullptr, nullptr, tab.next, tab.out, tx, seg.n, seg.enc,
+                     v[r], unused);
+        }
+      }
+      const uint32_t c = (v[0] != 0) + (v[1] != 0) + (v[2] != 0) + (v[3] != 0);
+      uint32_t tot;
+      uint64_t oo = o + wave_excl(c, &tot);
+      #pragma unroll
+      for (uint32_t r = 0; r < 4; ++r)
+        if (v[r]) put_hit(p, oo++, text, (uint32_t)(pos0 + r), v[r]);
+      o += tot;
+    }
+  }
+}
+
+// Batch: per-text hit and occurrence totals, one wave per text.
+__global__ __launch_bounds__(256) void pfac_text_totals_kernel(
+    const uint32_t* tile_hits, const unsigned long long* tile_occ, const uint64_t* tile_prefix,
+    uint32_t nsegs, unsigned long long* seg_counters) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint64_t s = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (s >= nsegs) return;
+  unsigned long long h = 0, o = 0;
+  for (uint64_t t = tile_prefix[s] + lane; t < tile_prefix[s + 1]; t += 64) {
+    h += tile_hits[t];
+    o += tile_occ[t];
+  }
+  h = wave_sum(h);
+  o = wave_sum(o);
+  if (lane == 0) {
+    seg_counters[2 * s] = h;
+    seg_counters[2 * s + 1] = o;
+  }
+}
+
+// Zero the counters of a call that has no tiles at all.
+__global__ void pfac_zero_kernel(unsigned long long* c, uint32_t n) {
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) c[i] = 0;
 }
 
 // ---------------------------------------------------------------- host side
@@ -563,180 +686,223 @@ static DeviceInfo device_info(int dev) {
   return d;
 }
 
-// Scratch of one (device, stream): ticket, look-back status words, and the
-// batch descriptor copies.
+// Library-owned scratch of one (device, stream): per-tile counts and hit
+// slots, block sums, the reduce ticket, and batch descriptor copies.  Calls
+// on one stream use it in stream order.
 struct Workspace {
-  uint32_t* ticket = nullptr;
-  unsigned long long* status = nullptr;
-  uint64_t status_cap = 0;
-  uint64_t* tile_prefix = nullptr;
-  DevSeg* segs = nullptr;
-  uint64_t segs_cap = 0;
-  DevTable* tabs = nullptr;
-  uint64_t tabs_cap = 0;
-  uint32_t epoch = 0;
+  uint8_t* mem = nullptr;
+  uint64_t cap_tiles = 0;
+  uint32_t* tile_hits = nullptr;
+  unsigned long long* tile_occ = nullptr;
+  Slot* slots = nullptr;
+  unsigned long long* block_hits = nullptr;
+  unsigned long long* block_occ = nullptr;
+  unsigned long long* block_prefix = nullptr;
+  uint32_t* done = nullptr;
+  void* batch = nullptr;           // descriptors, prefixes, group lists, table views
+  uint64_t batch_cap = 0;
+  uint8_t* stage = nullptr;        // pinned host copy of `batch` being uploaded
+  hipEvent_t staged = nullptr;     // recorded after the upload that read `stage`
+  bool staged_pending = false;
 };
 
 static std::map<std::pair<int, void*>, Workspace*> g_ws;
 
-static int grow(void** ptr, uint64_t* cap, uint64_t need, size_t elem, hipStream_t stream,
-                bool zero) {
-  if (*cap >= need && *ptr) return PFAC_OK;
-  uint64_t nc = need < 1024 ? 1024 : need + need / 2;
-  if (*ptr) {
+static int ensure_tiles(Workspace* ws, uint64_t tiles, hipStream_t stream) {
+  if (tiles <= ws->cap_tiles && ws->mem) return PFAC_OK;
+  const uint64_t cap = std::max<uint64_t>(tiles + tiles / 4, 4096);
+  const uint64_t blocks = (cap + kRedTiles - 1) / kRedTiles;
+  auto al = [](uint64_t x) { return (x + 255) / 256 * 256; };
+  const uint64_t o_hits = 0;
+  const uint64_t o_occ = al(o_hits + cap * 4);
+  const uint64_t o_slots = al(o_occ + cap * 8);
+  const uint64_t o_bh = al(o_slots + cap * kSlot * sizeof(Slot));
+  const uint64_t o_bo = al(o_bh + blocks * 8);
+  const uint64_t o_bp = al(o_bo + blocks * 8);
+  const uint64_t o_done = al(o_bp + blocks * 8);
+  const uint64_t total = al(o_done + 256);
+  if (ws->mem) {
     if (hipStreamSynchronize(stream) != hipSuccess) return PFAC_E_HIP;
-    (void)hipFree(*ptr);
-    *ptr = nullptr;
-    *cap = 0;
+    (void)hipFree(ws->mem);
+    ws->mem = nullptr;
+    ws->cap_tiles = 0;
   }
-  if (hipMalloc(ptr, nc * elem) != hipSuccess) {
-    *ptr = nullptr;
+  void* m = nullptr;
+  if (hipMalloc(&m, total) != hipSuccess) return PFAC_E_NOMEM;
+  ws->mem = static_cast<uint8_t*>(m);
+  if (hipMemset(ws->mem + o_done, 0, 256) != hipSuccess) return PFAC_E_HIP;
+  ws->cap_tiles = cap;
+  ws->tile_hits = reinterpret_cast<uint32_t*>(ws->mem + o_hits);
+  ws->tile_occ = reinterpret_cast<unsigned long long*>(ws->mem + o_occ);
+  ws->slots = reinterpret_cast<Slot*>(ws->mem + o_slots);
+  ws->block_hits = reinterpret_cast<unsigned long long*>(ws->mem + o_bh);
+  ws->block_occ = reinterpret_cast<unsigned long long*>(ws->mem + o_bo);
+  ws->block_prefix = reinterpret_cast<unsigned long long*>(ws->mem + o_bp);
+  ws->done = reinterpret_cast<uint32_t*>(ws->mem + o_done);
+  return PFAC_OK;
+}
+
+static int ensure_batch(Workspace* ws, uint64_t bytes, hipStream_t stream) {
+  if (!ws->staged && hipEventCreateWithFlags(&ws->staged, hipEventDisableTiming) != hipSuccess)
+    return PFAC_E_HIP;
+  // the previous upload must have finished reading the pinned stage
+  if (ws->staged_pending) {
+    if (hipEventSynchronize(ws->staged) != hipSuccess) return PFAC_E_HIP;
+    ws->staged_pending = false;
+  }
+  if (bytes <= ws->batch_cap && ws->batch) return PFAC_OK;
+  const uint64_t cap = std::max<uint64_t>(bytes + bytes / 2, 1 << 16);
+  if (ws->batch) {
+    if (hipStreamSynchronize(stream) != hipSuccess) return PFAC_E_HIP;
+    (void)hipFree(ws->batch);
+    (void)hipHostFree(ws->stage);
+    ws->batch = nullptr;
+    ws->stage = nullptr;
+    ws->batch_cap = 0;
+  }
+  if (hipMalloc(&ws->batch, cap) != hipSuccess) {
+    ws->batch = nullptr;
     return PFAC_E_NOMEM;
   }
-  if (zero && hipMemset(*ptr, 0, nc * elem) != hipSuccess) return PFAC_E_HIP;
-  *cap = nc;
+  void* st = nullptr;
+  if (hipHostMalloc(&st, cap, hipHostMallocDefault) != hipSuccess) {
+    (void)hipFree(ws->batch);
+    ws->batch = nullptr;
+    return PFAC_E_NOMEM;
+  }
+  ws->stage = static_cast<uint8_t*>(st);
+  ws->batch_cap = cap;
   return PFAC_OK;
 }
 
-static int get_workspace(int dev, hipStream_t stream, uint64_t tiles, uint64_t nsegs,
-                         uint64_t ntabs, Workspace** out) {
+static Workspace* get_workspace(int dev, hipStream_t stream) {
   std::lock_guard<std::mutex> lk(g_mu);
   Workspace*& ws = g_ws[{dev, (void*)stream}];
-  if (!ws) {
-    ws = new (std::nothrow) Workspace();
-    if (!ws) return PFAC_E_NOMEM;
-    if (hipMalloc(&ws->ticket, 256) != hipSuccess) return PFAC_E_NOMEM;
-  }
-  const uint64_t old_cap = ws->status_cap;
-  int rc = grow(reinterpret_cast<void**>(&ws->status), &ws->status_cap, tiles,
-                sizeof(unsigned long long), stream, true);
-  if (rc) return rc;
-  if (ws->status_cap != old_cap) ws->epoch = 0;   // fresh zeroed status words
-  if (nsegs) {
-    uint64_t cap_prefix = ws->segs_cap;
-    rc = grow(reinterpret_cast<void**>(&ws->segs), &ws->segs_cap, nsegs, sizeof(DevSeg), stream,
-              false);
-    if (rc) return rc;
-    if (ws->segs_cap != cap_prefix || !ws->tile_prefix) {
-      if (ws->tile_prefix) (void)hipFree(ws->tile_prefix);
-      ws->tile_prefix = nullptr;
-      if (hipMalloc(&ws->tile_prefix, (ws->segs_cap + 1) * sizeof(uint64_t)) != hipSuccess)
-        return PFAC_E_NOMEM;
-    }
-  }
-  if (ntabs) {
-    rc = grow(reinterpret_cast<void**>(&ws->tabs), &ws->tabs_cap, ntabs, sizeof(DevTable), stream,
-              false);
-    if (rc) return rc;
-  }
-  // launch epochs tag the status words, so they never need clearing; when
-  // the tag would wrap, clear them once
-  ws->epoch += 1;
-  if (ws->epoch >= (1u << kEpochBits)) {
-    if (hipMemsetAsync(ws->status, 0, ws->status_cap * sizeof(unsigned long long), stream) !=
-        hipSuccess)
-      return PFAC_E_HIP;
-    ws->epoch = 1;
-  }
-  *out = ws;
-  return PFAC_OK;
-}
-
-static uint32_t lds_bytes(uint32_t block, uint32_t K, uint32_t hot, uint32_t halo) {
-  const uint32_t span = block * kPPT + halo;
-  const uint32_t words = (K ? (1u << (2 * K)) : 0u) + 4 * hot + (span / 16 + 2) + (span / 32 + 2);
-  return 4 * words;
+  if (!ws) ws = new (std::nothrow) Workspace();
+  return ws;
 }
 
 static uint32_t halo_for(uint32_t max_len) {
   uint32_t h = max_len > 1 ? max_len - 1 : 0;
-  if (h < 16) h = 16;   // room for the root jump window of the last positions
+  if (h < 16) h = 16;   // room for the filter window of the last positions
   return (h + 63) / 64 * 64;
 }
 
-using KernelFn = void (*)(KParams);
+static uint32_t scan_lds_bytes(uint32_t block, uint32_t D, uint32_t halo) {
+  return 4u * ((1u << (2 * D)) / 32 + (block / 64) * wave_words(halo));
+}
 
-static KernelFn pick_kernel(uint32_t block, bool global) {
+using ScanFn = void (*)(ScanParams);
+
+static ScanFn pick_scan(uint32_t block, bool global) {
   switch (block) {
-    case 256: return global ? pfac_kernel<256, true> : pfac_kernel<256, false>;
-    case 512: return global ? pfac_kernel<512, true> : pfac_kernel<512, false>;
-    case 1024: return global ? pfac_kernel<1024, true> : pfac_kernel<1024, false>;
+    case 256: return global ? pfac_scan_kernel<256, true> : pfac_scan_kernel<256, false>;
+    case 512: return global ? pfac_scan_kernel<512, true> : pfac_scan_kernel<512, false>;
+    case 1024: return global ? pfac_scan_kernel<1024, true> : pfac_scan_kernel<1024, false>;
     default: return nullptr;
   }
 }
 
-// Fill unset plan fields; reject plans that cannot run.
-static int resolve_plan(const pfac_plan* in, uint32_t max_len, uint64_t num_states, int dev,
-                        pfac_plan* out) {
+// Filter depth the library picks: deepen while at least 5 % of the windows
+// of the next level are trie prefixes, capped at 9 (32 KB of LDS).
+static uint32_t auto_depth(const HostTable& h) {
+  uint32_t D = kMinJump;
+  for (uint32_t d = kMinJump; d <= 9; ++d) {
+    const uint64_t at_d = (d + 1 < h.depth_start.size())
+                              ? h.depth_start[d + 1] - h.depth_start[d] : 0;
+    D = d;
+    if ((double)at_d < 0.05 * (double)(1ull << (2 * d))) break;
+  }
+  return D;
+}
+
+static int resolve_plan(const pfac_plan* in, const HostTable& h, int dev, pfac_plan* out) {
   const DeviceInfo di = device_info(dev);
   if (!di.ok) return PFAC_E_NODEV;
-  pfac_plan p = in ? *in : pfac_plan{0, 0, 0, 0, 0};
+  pfac_plan p = in ? *in : pfac_plan{0, 0, 0, 0};
   if (p.variant != PFAC_VARIANT_TILED && p.variant != PFAC_VARIANT_GLOBAL) return PFAC_E_ARG;
-  const uint32_t halo = halo_for(max_len);
-  if (p.variant == PFAC_VARIANT_TILED && halo > kMaxHaloLds) {
-    if (in && in->variant == PFAC_VARIANT_TILED && in->block) return PFAC_E_ARG;
+  const uint32_t halo = halo_for(h.max_len);
+  if (p.variant == PFAC_VARIANT_TILED && halo > kMaxHalo) {
+    if (in && in->depth) return PFAC_E_ARG;
     p.variant = PFAC_VARIANT_GLOBAL;  // patterns too long to stage a halo in LDS
   }
   if (p.block == 0) p.block = 512;
   if (p.block != 256 && p.block != 512 && p.block != 1024) return PFAC_E_ARG;
   if (p.variant == PFAC_VARIANT_GLOBAL) {
-    p.jump_depth = PFAC_JUMP_OFF;
-    p.hot_states = PFAC_HOT_NONE;
-  } else {
-    const uint32_t budget = (uint32_t)di.lds_per_block;
-    if (p.jump_depth == 0)
-      p.jump_depth = lds_bytes(p.block, 7, 0, halo) <= budget ? 7u : 6u;
-    if (p.jump_depth != PFAC_JUMP_OFF && (p.jump_depth < kMinJump || p.jump_depth > kMaxJump))
-      return PFAC_E_ARG;
-    const uint32_t K = p.jump_depth == PFAC_JUMP_OFF ? 0 : p.jump_depth;
-    if (p.hot_states == 0) {
-      // stage the whole table when it fits in what the jump table leaves
-      const uint32_t base = lds_bytes(p.block, K, 0, halo);
-      const uint64_t want = num_states;
-      const uint64_t room = budget > base ? (budget - base) / 16 : 0;
-      p.hot_states = (want <= room && want * 16 <= 48 * 1024) ? (uint32_t)want : PFAC_HOT_NONE;
-    }
-    const uint32_t hot = p.hot_states == PFAC_HOT_NONE ? 0 : p.hot_states;
-    if (lds_bytes(p.block, K, hot, halo) > (uint32_t)di.lds_per_block) return PFAC_E_ARG;
+    p.depth = 0;
+    *out = p;
+    return PFAC_OK;
   }
+  if (p.depth == 0) {
+    p.depth = auto_depth(h);
+    while (p.depth > kMinJump &&
+           scan_lds_bytes(p.block, p.depth, halo) > (uint32_t)di.lds_per_block)
+      --p.depth;
+  }
+  if (p.depth < kMinJump || p.depth > kMaxJump) return PFAC_E_ARG;
+  if (scan_lds_bytes(p.block, p.depth, halo) > (uint32_t)di.lds_per_block) return PFAC_E_ARG;
   *out = p;
   return PFAC_OK;
 }
 
-static int launch(const KParams& kp_in, const pfac_plan& plan, uint32_t halo, int dev,
-                  hipStream_t stream, const DevSeg* d_segs, uint32_t nsegs, uint64_t* d_prefix,
-                  unsigned long long* d_seg_counters) {
-  KParams kp = kp_in;
-  const bool global = plan.variant == PFAC_VARIANT_GLOBAL;
-  kp.K = (global || plan.jump_depth == PFAC_JUMP_OFF) ? 0 : plan.jump_depth;
-  kp.hot = (global || plan.hot_states == PFAC_HOT_NONE) ? 0 : plan.hot_states;
-  kp.halo = global ? 0 : halo;
-  const uint32_t lds = global ? 0 : lds_bytes(plan.block, kp.K, kp.hot, halo);
-  KernelFn fn = pick_kernel(plan.block, global);
-  if (!fn) return PFAC_E_ARG;
-  hipLaunchKernelGGL(pfac_prep_kernel, dim3(1), dim3(1024), 0, stream, d_segs, nsegs,
-                     plan.block * kPPT, d_prefix, kp.counters, d_seg_counters, kp.ticket);
-  if (hipGetLastError() != hipSuccess) return PFAC_E_HIP;
-  if (kp.total_tiles == 0) return PFAC_OK;
-  uint64_t grid = plan.grid;
-  if (grid == 0) {
-    if (lds > 48 * 1024)
-      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+static uint64_t grid_for(ScanFn fn, const pfac_plan& plan, uint32_t lds, int dev,
+                         uint64_t tiles) {
+  if (lds > 48 * 1024)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  uint64_t g = plan.grid;
+  if (g == 0) {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn),
                                                      (int)plan.block, lds) != hipSuccess ||
         per_cu < 1)
       per_cu = 1;
-    grid = (uint64_t)per_cu * (uint64_t)device_info(dev).cus;
-  } else if (lds > 48 * 1024) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    g = (uint64_t)per_cu * (uint64_t)device_info(dev).cus;
   }
-  if (grid > kp.total_tiles) grid = kp.total_tiles;
-  hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(plan.block), lds, stream, kp);
+  const uint64_t waves = plan.block / 64;
+  const uint64_t need = (tiles + waves - 1) / waves;
+  if (g > need) g = need;
+  return g ? g : 1;
+}
+
+static int launch_scan(const ScanParams& sp, const pfac_plan& plan, int dev, hipStream_t stream) {
+  if (sp.local_tiles == 0) return PFAC_OK;
+  const bool global = plan.variant == PFAC_VARIANT_GLOBAL;
+  ScanFn fn = pick_scan(plan.block, global);
+  if (!fn) return PFAC_E_ARG;
+  const uint32_t lds = global ? 0u : scan_lds_bytes(plan.block, sp.D, sp.halo);
+  const uint64_t grid = grid_for(fn, plan, lds, dev, sp.local_tiles);
+  hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(plan.block), lds, stream, sp);
+  return hipGetLastError() == hipSuccess ? PFAC_OK : PFAC_E_HIP;
+}
+
+static int launch_tail(Workspace* ws, uint64_t tiles, unsigned long long* counters,
+                       ScatterParams* sc, bool want_hits, hipStream_t stream) {
+  const uint32_t blocks = (uint32_t)((tiles + kRedTiles - 1) / kRedTiles);
+  hipLaunchKernelGGL(pfac_reduce_kernel, dim3(blocks), dim3(1024), 0, stream, ws->tile_hits,
+                     ws->tile_occ, tiles, ws->block_hits, ws->block_occ, ws->block_prefix,
+                     ws->done, counters);
   if (hipGetLastError() != hipSuccess) return PFAC_E_HIP;
+  if (want_hits) {
+    sc->tile_hits = ws->tile_hits;
+    sc->slots = ws->slots;
+    sc->block_prefix = ws->block_prefix;
+    sc->tiles = tiles;
+    hipLaunchKernelGGL(pfac_scatter_kernel, dim3(blocks), dim3(1024), 0, stream, *sc);
+    if (hipGetLastError() != hipSuccess) return PFAC_E_HIP;
+  }
   return PFAC_OK;
+}
+
+static void fill_table(ScanParams& sp, const pfac_table* t, const pfac_plan& pl) {
+  sp.next = t->dev.next;
+  sp.out = t->dev.out;
+  if (pl.variant == PFAC_VARIANT_TILED) {
+    sp.D = pl.depth;
+    sp.jump = t->dev.jump[pl.depth];
+    sp.jres = t->dev.jres[pl.depth];
+    sp.bitmap = t->dev.bitmap[pl.depth];
+  }
 }
 
 }  // namespace pfac
@@ -758,7 +924,7 @@ const char* pfac_strerror(int s) {
   }
 }
 
-const char* pfac_version(void) { return "pfac-mi355x 0.1 (gfx950)"; }
+const char* pfac_version(void) { return "pfac-mi355x 0.2 (gfx950)"; }
 
 int pfac_build_table(const char* const* patterns, const uint32_t* lengths, uint32_t num,
                      pfac_table** out, int64_t* bad_index) {
@@ -776,45 +942,42 @@ int pfac_build_table(const char* const* patterns, const uint32_t* lengths, uint3
   }
   t->device = dev;
   const HostTable& h = t->host;
-  // one device allocation: next | out | jump[K] | jres[K] | views
+  // one device allocation: next | out | per depth: jump, jres, bitmap
   auto align = [](uint64_t x) { return (x + 255) / 256 * 256; };
   uint64_t off = 0;
   const uint64_t o_next = off; off = align(off + h.next.size() * 4);
   const uint64_t o_out = off; off = align(off + h.out.size() * sizeof(OutEntry));
-  uint64_t o_jump[kMaxJump + 1] = {}, o_jres[kMaxJump + 1] = {};
-  for (uint32_t K = kMinJump; K <= kMaxJump; ++K) {
-    o_jump[K] = off; off = align(off + h.jump[K].size() * 4);
-    o_jres[K] = off; off = align(off + h.jres[K].size() * sizeof(OutEntry));
+  uint64_t o_jump[kMaxJump + 1] = {}, o_jres[kMaxJump + 1] = {}, o_bm[kMaxJump + 1] = {};
+  for (uint32_t D = kMinJump; D <= kMaxJump; ++D) {
+    o_jump[D] = off; off = align(off + h.jump[D].size() * 4);
+    o_jres[D] = off; off = align(off + h.jres[D].size() * sizeof(OutEntry));
+    o_bm[D] = off; off = align(off + h.bitmap[D].size() * 4);
   }
-  const uint64_t o_views = off; off = align(off + (kMaxJump + 1) * sizeof(DevTable));
   if (hipMalloc(&t->dmem, off) != hipSuccess) {
     delete t;
     return PFAC_E_NOMEM;
   }
   t->dbytes = off;
   char* base = static_cast<char*>(t->dmem);
-  t->d_next = reinterpret_cast<uint32_t*>(base + o_next);
-  t->d_out = reinterpret_cast<OutEntry*>(base + o_out);
-  bool ok = hipMemcpy(t->d_next, h.next.data(), h.next.size() * 4, hipMemcpyHostToDevice) ==
-                hipSuccess &&
-            hipMemcpy(t->d_out, h.out.data(), h.out.size() * sizeof(OutEntry),
-                      hipMemcpyHostToDevice) == hipSuccess;
-  DevTable views[kMaxJump + 1];
-  for (uint32_t K = 0; K <= kMaxJump; ++K) {
-    views[K] = DevTable{t->d_next, t->d_out, nullptr, nullptr, (uint32_t)h.num_states, h.max_len};
-    if (K >= kMinJump) {
-      t->d_jump[K] = reinterpret_cast<uint32_t*>(base + o_jump[K]);
-      t->d_jres[K] = reinterpret_cast<OutEntry*>(base + o_jres[K]);
-      ok = ok && hipMemcpy(t->d_jump[K], h.jump[K].data(), h.jump[K].size() * 4,
-                           hipMemcpyHostToDevice) == hipSuccess;
-      ok = ok && hipMemcpy(t->d_jres[K], h.jres[K].data(), h.jres[K].size() * sizeof(OutEntry),
-                           hipMemcpyHostToDevice) == hipSuccess;
-      views[K].jump = t->d_jump[K];
-      views[K].jres = t->d_jres[K];
-    }
+  auto put = [&](uint64_t o, const void* src, size_t bytes) {
+    return hipMemcpy(base + o, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+  };
+  bool ok = put(o_next, h.next.data(), h.next.size() * 4) &&
+            put(o_out, h.out.data(), h.out.size() * sizeof(OutEntry));
+  DevTable& v = t->dev;
+  memset(&v, 0, sizeof(v));
+  v.next = reinterpret_cast<const uint32_t*>(base + o_next);
+  v.out = reinterpret_cast<const OutEntry*>(base + o_out);
+  v.num_states = (uint32_t)h.num_states;
+  v.max_len = h.max_len;
+  for (uint32_t D = kMinJump; D <= kMaxJump; ++D) {
+    ok = ok && put(o_jump[D], h.jump[D].data(), h.jump[D].size() * 4) &&
+         put(o_jres[D], h.jres[D].data(), h.jres[D].size() * sizeof(OutEntry)) &&
+         put(o_bm[D], h.bitmap[D].data(), h.bitmap[D].size() * 4);
+    v.jump[D] = reinterpret_cast<const uint32_t*>(base + o_jump[D]);
+    v.jres[D] = reinterpret_cast<const OutEntry*>(base + o_jres[D]);
+    v.bitmap[D] = reinterpret_cast<const uint32_t*>(base + o_bm[D]);
   }
-  t->d_views = reinterpret_cast<DevTable*>(base + o_views);
-  ok = ok && hipMemcpy(t->d_views, views, sizeof(views), hipMemcpyHostToDevice) == hipSuccess;
   if (!ok) {
     (void)hipFree(t->dmem);
     delete t;
@@ -853,17 +1016,7 @@ void pfac_free_table(pfac_table* t) {
 int pfac_default_plan(const pfac_table* t, uint64_t n, int enc, pfac_plan* out) {
   (void)n;
   if (!t || !out || (enc != PFAC_TEXT_ASCII && enc != PFAC_TEXT_2BIT)) return PFAC_E_ARG;
-  return resolve_plan(nullptr, t->host.max_len, t->host.num_states, t->device, out);
-}
-
-static DevTable view_of(const pfac_table* t, uint32_t K) {
-  const HostTable& h = t->host;
-  DevTable v{t->d_next, t->d_out, nullptr, nullptr, (uint32_t)h.num_states, h.max_len};
-  if (K >= kMinJump && K <= kMaxJump) {
-    v.jump = t->d_jump[K];
-    v.jres = t->d_jres[K];
-  }
-  return v;
+  return resolve_plan(nullptr, t->host, t->device, out);
 }
 
 int pfac_match(const pfac_table* t, const void* d_text, uint64_t n, int enc, int32_t* d_match,
@@ -877,31 +1030,45 @@ int pfac_match(const pfac_table* t, const void* d_text, uint64_t n, int enc, int
   if (dev != t->device) return PFAC_E_ARG;
   hipStream_t stream = static_cast<hipStream_t>(stream_);
   pfac_plan pl;
-  int rc = resolve_plan(plan, t->host.max_len, t->host.num_states, dev, &pl);
+  int rc = resolve_plan(plan, t->host, dev, &pl);
   if (rc) return rc;
-  const uint64_t tile = (uint64_t)pl.block * kPPT;
-  const uint64_t tiles = (n + tile - 1) / tile;
-  Workspace* ws = nullptr;
-  rc = get_workspace(dev, stream, tiles ? tiles : 1, 0, 0, &ws);
+  unsigned long long* counters = reinterpret_cast<unsigned long long*>(d_counters);
+  const uint64_t tiles = (n + kTile - 1) / kTile;
+  if (tiles == 0) {
+    hipLaunchKernelGGL(pfac_zero_kernel, dim3(1), dim3(64), 0, stream, counters, 2u);
+    return hipGetLastError() == hipSuccess ? PFAC_OK : PFAC_E_HIP;
+  }
+  Workspace* ws = get_workspace(dev, stream);
+  if (!ws) return PFAC_E_NOMEM;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    rc = ensure_tiles(ws, tiles, stream);
+  }
   if (rc) return rc;
-  KParams kp;
-  memset(&kp, 0, sizeof(kp));
-  kp.single = 1;
-  kp.nsegs = 1;
-  kp.total_tiles = tiles;
-  kp.text = static_cast<const uint8_t*>(d_text);
-  kp.match = d_match;
-  kp.hits = d_hits;
-  kp.hit_cap = hit_cap;
-  kp.counters = reinterpret_cast<unsigned long long*>(d_counters);
-  kp.ticket = ws->ticket;
-  kp.status = ws->status;
-  kp.epoch = ws->epoch;
-  kp.seg0 = DevSeg{0, n, 0, 0, (uint32_t)enc};
-  const uint32_t K = (pl.variant == PFAC_VARIANT_GLOBAL || pl.jump_depth == PFAC_JUMP_OFF)
-                         ? 0 : pl.jump_depth;
-  kp.tab0 = view_of(t, K);
-  return launch(kp, pl, halo_for(t->host.max_len), dev, stream, nullptr, 0, nullptr, nullptr);
+  ScanParams sp;
+  memset(&sp, 0, sizeof(sp));
+  fill_table(sp, t, pl);
+  sp.halo = pl.variant == PFAC_VARIANT_TILED ? halo_for(t->host.max_len) : 0;
+  sp.single = 1;
+  sp.seg0 = DevSeg{0, n, 0, 0, (uint32_t)enc};
+  sp.local_tiles = tiles;
+  sp.text = static_cast<const uint8_t*>(d_text);
+  sp.match = d_match;
+  sp.tile_hits = ws->tile_hits;
+  sp.tile_occ = ws->tile_occ;
+  sp.slots = d_hits ? ws->slots : nullptr;
+  rc = launch_scan(sp, pl, dev, stream);
+  if (rc) return rc;
+  ScatterParams sc;
+  memset(&sc, 0, sizeof(sc));
+  sc.hits = d_hits;
+  sc.hit_cap = hit_cap;
+  sc.single = 1;
+  sc.seg0 = sp.seg0;
+  sc.text = sp.text;
+  sc.match = d_match;
+  sc.tab0 = t->dev;
+  return launch_tail(ws, tiles, counters, &sc, d_hits != nullptr && hit_cap > 0, stream);
 }
 
 int pfac_match_batch(const pfac_table* const* tables, uint32_t num_tables,
@@ -912,13 +1079,8 @@ int pfac_match_batch(const pfac_table* const* tables, uint32_t num_tables,
   if (d_hits == nullptr) hit_cap = 0;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return PFAC_E_NODEV;
-  uint32_t max_len = 0;
-  uint64_t max_states = 0;
-  for (uint32_t i = 0; i < num_tables; ++i) {
+  for (uint32_t i = 0; i < num_tables; ++i)
     if (!tables[i] || tables[i]->device != dev) return PFAC_E_ARG;
-    max_len = std::max(max_len, tables[i]->host.max_len);
-    max_states = std::max<uint64_t>(max_states, tables[i]->host.num_states);
-  }
   for (uint32_t s = 0; s < num_texts; ++s) {
     const pfac_text_desc& d = descs[s];
     if (d.n >= (1ull << 32) || d.table >= num_tables ||
@@ -926,50 +1088,105 @@ int pfac_match_batch(const pfac_table* const* tables, uint32_t num_tables,
       return PFAC_E_ARG;
   }
   hipStream_t stream = static_cast<hipStream_t>(stream_);
-  pfac_plan pl;
-  int rc = resolve_plan(plan, max_len, max_states, dev, &pl);
-  if (rc) return rc;
-  // hot rows only when every table fits
-  if (pl.hot_states != PFAC_HOT_NONE && pl.hot_states > 0) {
-    for (uint32_t i = 0; i < num_tables; ++i)
-      if (tables[i]->host.num_states > pl.hot_states) pl.hot_states = PFAC_HOT_NONE;
+  unsigned long long* counters = reinterpret_cast<unsigned long long*>(d_counters);
+  // one launch per table; each table gets its own plan
+  std::vector<pfac_plan> plans(num_tables);
+  for (uint32_t i = 0; i < num_tables; ++i) {
+    int rc = resolve_plan(plan, tables[i]->host, dev, &plans[i]);
+    if (rc) return rc;
   }
-  const uint64_t tile = (uint64_t)pl.block * kPPT;
-  uint64_t tiles = 0;
-  for (uint32_t s = 0; s < num_texts; ++s) tiles += (descs[s].n + tile - 1) / tile;
-  Workspace* ws = nullptr;
-  rc = get_workspace(dev, stream, tiles ? tiles : 1, num_texts ? num_texts : 1, num_tables, &ws);
+  // global tile numbering in text order; per table: its texts and local prefixes
+  std::vector<uint64_t> tile_prefix(num_texts + 1, 0);
+  for (uint32_t s = 0; s < num_texts; ++s)
+    tile_prefix[s + 1] = tile_prefix[s] + (descs[s].n + kTile - 1) / kTile;
+  const uint64_t tiles = tile_prefix[num_texts];
+  if (tiles == 0) {
+    hipLaunchKernelGGL(pfac_zero_kernel, dim3(1), dim3(256), 0, stream, counters,
+                       2u + 2u * num_texts);
+    return hipGetLastError() == hipSuccess ? PFAC_OK : PFAC_E_HIP;
+  }
+  std::vector<std::vector<uint32_t>> groups(num_tables);
+  for (uint32_t s = 0; s < num_texts; ++s)
+    if (descs[s].n) groups[descs[s].table].push_back(s);
+  // device copies: descs | tile_prefix | per group: text list, local prefix | table views
+  auto al = [](uint64_t x) { return (x + 255) / 256 * 256; };
+  uint64_t bytes = al(num_texts * sizeof(DevSeg)) + al((num_texts + 1) * 8);
+  for (uint32_t g = 0; g < num_tables; ++g)
+    bytes += al(groups[g].size() * 4) + al((groups[g].size() + 1) * 8);
+  bytes += al(num_tables * sizeof(DevTable));
+  Workspace* ws = get_workspace(dev, stream);
+  if (!ws) return PFAC_E_NOMEM;
+  int rc;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    rc = ensure_tiles(ws, tiles, stream);
+    if (!rc) rc = ensure_batch(ws, bytes, stream);
+  }
   if (rc) return rc;
-  const uint32_t K = (pl.variant == PFAC_VARIANT_GLOBAL || pl.jump_depth == PFAC_JUMP_OFF)
-                         ? 0 : pl.jump_depth;
+  uint8_t* host = ws->stage;
+  uint64_t off = 0;
+  auto put = [&](const void* src, uint64_t n) {
+    const uint64_t o = off;
+    if (n) memcpy(host + o, src, n);
+    off = al(off + n);
+    return o;
+  };
+  const uint64_t o_segs = put(descs, num_texts * sizeof(DevSeg));
+  const uint64_t o_tp = put(tile_prefix.data(), (num_texts + 1) * 8);
+  std::vector<uint64_t> o_gs(num_tables), o_gp(num_tables), gtiles(num_tables);
+  for (uint32_t g = 0; g < num_tables; ++g) {
+    std::vector<uint64_t> lp(groups[g].size() + 1, 0);
+    for (size_t i = 0; i < groups[g].size(); ++i)
+      lp[i + 1] = lp[i] + (descs[groups[g][i]].n + kTile - 1) / kTile;
+    gtiles[g] = lp.back();
+    o_gs[g] = put(groups[g].data(), groups[g].size() * 4);
+    o_gp[g] = put(lp.data(), lp.size() * 8);
+  }
   std::vector<DevTable> views(num_tables);
-  for (uint32_t i = 0; i < num_tables; ++i) views[i] = view_of(tables[i], K);
-  if (num_texts &&
-      hipMemcpyAsync(ws->segs, descs, num_texts * sizeof(DevSeg), hipMemcpyHostToDevice, stream) !=
-          hipSuccess)
+  for (uint32_t i = 0; i < num_tables; ++i) views[i] = tables[i]->dev;
+  const uint64_t o_tab = put(views.data(), num_tables * sizeof(DevTable));
+  if (hipMemcpyAsync(ws->batch, host, bytes, hipMemcpyHostToDevice, stream) != hipSuccess ||
+      hipEventRecord(ws->staged, stream) != hipSuccess)
     return PFAC_E_HIP;
-  if (hipMemcpyAsync(ws->tabs, views.data(), num_tables * sizeof(DevTable), hipMemcpyHostToDevice,
-                     stream) != hipSuccess)
-    return PFAC_E_HIP;
-  KParams kp;
-  memset(&kp, 0, sizeof(kp));
-  kp.single = 0;
-  kp.tables = ws->tabs;
-  kp.segs = ws->segs;
-  kp.tile_prefix = ws->tile_prefix;
-  kp.nsegs = num_texts;
-  kp.total_tiles = tiles;
-  kp.text = static_cast<const uint8_t*>(d_text_base);
-  kp.match = d_match_base;
-  kp.hits = d_hits;
-  kp.hit_cap = hit_cap;
-  kp.counters = reinterpret_cast<unsigned long long*>(d_counters);
-  kp.seg_counters = reinterpret_cast<unsigned long long*>(d_counters) + 2;
-  kp.ticket = ws->ticket;
-  kp.status = ws->status;
-  kp.epoch = ws->epoch;
-  return launch(kp, pl, halo_for(max_len), dev, stream, ws->segs, num_texts, ws->tile_prefix,
-                kp.seg_counters);
+  ws->staged_pending = true;
+  uint8_t* db = static_cast<uint8_t*>(ws->batch);
+  for (uint32_t g = 0; g < num_tables; ++g) {
+    if (gtiles[g] == 0) continue;
+    ScanParams sp;
+    memset(&sp, 0, sizeof(sp));
+    fill_table(sp, tables[g], plans[g]);
+    sp.halo = plans[g].variant == PFAC_VARIANT_TILED ? halo_for(tables[g]->host.max_len) : 0;
+    sp.single = 0;
+    sp.ngroup = (uint32_t)groups[g].size();
+    sp.segs = reinterpret_cast<const DevSeg*>(db + o_segs);
+    sp.group_segs = reinterpret_cast<const uint32_t*>(db + o_gs[g]);
+    sp.group_prefix = reinterpret_cast<const uint64_t*>(db + o_gp[g]);
+    sp.tile_prefix = reinterpret_cast<const uint64_t*>(db + o_tp);
+    sp.local_tiles = gtiles[g];
+    sp.text = static_cast<const uint8_t*>(d_text_base);
+    sp.match = d_match_base;
+    sp.tile_hits = ws->tile_hits;
+    sp.tile_occ = ws->tile_occ;
+    sp.slots = d_hits ? ws->slots : nullptr;
+    rc = launch_scan(sp, plans[g], dev, stream);
+    if (rc) return rc;
+  }
+  ScatterParams sc;
+  memset(&sc, 0, sizeof(sc));
+  sc.hits = d_hits;
+  sc.hit_cap = hit_cap;
+  sc.single = 0;
+  sc.nsegs = num_texts;
+  sc.segs = reinterpret_cast<const DevSeg*>(db + o_segs);
+  sc.tile_prefix = reinterpret_cast<const uint64_t*>(db + o_tp);
+  sc.text = static_cast<const uint8_t*>(d_text_base);
+  sc.match = d_match_base;
+  sc.tables = reinterpret_cast<const DevTable*>(db + o_tab);
+  rc = launch_tail(ws, tiles, counters, &sc, d_hits != nullptr && hit_cap > 0, stream);
+  if (rc) return rc;
+  hipLaunchKernelGGL(pfac_text_totals_kernel, dim3((num_texts + 3) / 4), dim3(256), 0, stream,
+                     ws->tile_hits, ws->tile_occ, sc.tile_prefix, num_texts, counters + 2);
+  return hipGetLastError() == hipSuccess ? PFAC_OK : PFAC_E_HIP;
 }
 
 }  // extern "C"

@@ -96,13 +96,13 @@ def test_packed_big_trie_reduced():
 
 PLANS = [
     dict(variant=pf.PFAC_VARIANT_GLOBAL),
-    dict(block=256, jump_depth=pf.PFAC_JUMP_OFF, hot_states=pf.PFAC_HOT_NONE),
-    dict(block=256, jump_depth=4, hot_states=pf.PFAC_HOT_NONE),
-    dict(block=512, jump_depth=5, hot_states=64),
-    dict(block=1024, jump_depth=6, hot_states=pf.PFAC_HOT_NONE),
-    dict(block=512, jump_depth=7, hot_states=pf.PFAC_HOT_NONE),
-    dict(block=256, jump_depth=7, hot_states=2000),
-    dict(block=1024, jump_depth=7, hot_states=2000, grid=3),
+    dict(block=256, depth=6),
+    dict(block=512, depth=7),
+    dict(block=1024, depth=8),
+    dict(block=512, depth=9),
+    dict(block=256, depth=10),
+    dict(block=1024, depth=9, grid=3),
+    dict(block=256, depth=6, grid=1),
 ]
 
 
@@ -127,7 +127,7 @@ def test_edge_sizes_and_ragged_tails():
               3 * 8192 - 1, 100_000]:
         text = W.uniform_ascii(n, g)
         print("n=%d" % n, flush=True)
-        for plan in (None, dict(block=256, jump_depth=7), dict(variant=pf.PFAC_VARIANT_GLOBAL)):
+        for plan in (None, dict(block=256, depth=10), dict(variant=pf.PFAC_VARIANT_GLOBAL)):
             res = _gpu(pats, text, plan=plan, table=tab)
             _check(res, pats, text)
             res = _gpu(pats, text, plan=plan, table=tab, enc="2bit")
@@ -154,7 +154,7 @@ def test_homopolymer_worst_case_walks():
     pats = [b"A" * L for L in range(1, 65)] + [b"C" * 64]
     text = np.full(70_001, ord("A"), dtype=np.uint8)
     text[40_000] = ord("C")
-    for plan in (None, dict(variant=pf.PFAC_VARIANT_GLOBAL), dict(block=256, jump_depth=4)):
+    for plan in (None, dict(variant=pf.PFAC_VARIANT_GLOBAL), dict(block=256, depth=6)):
         res = _gpu(pats, text, plan=plan)
         _check(res, pats, text)
 
@@ -216,7 +216,9 @@ def test_invalid_arguments_are_rejected():
     with pytest.raises(pf.PfacError):
         pf.match(tab, dt, plan=dict(block=300))
     with pytest.raises(pf.PfacError):
-        pf.match(tab, dt, plan=dict(jump_depth=9))
+        pf.match(tab, dt, plan=dict(depth=11))
+    with pytest.raises(pf.PfacError):
+        pf.match(tab, dt, plan=dict(depth=5))
 
 
 def test_batch_matches_per_text_oracle():
@@ -224,7 +226,7 @@ def test_batch_matches_per_text_oracle():
     print("batch: texts=%d bases=%d" % (wb.lengths.size, wb.total_bases), flush=True)
     tab = pf.Table(wb.patterns)
     base = torch.from_numpy(wb.buffer).to(DEV)
-    for plan in (None, dict(block=256, jump_depth=6), dict(variant=pf.PFAC_VARIANT_GLOBAL)):
+    for plan in (None, dict(block=256, depth=7), dict(variant=pf.PFAC_VARIANT_GLOBAL)):
         res = pf.match_batch([tab], base, wb.offsets, wb.lengths, plan=plan)
         torch.cuda.synchronize()
         m = res.match.cpu().numpy()

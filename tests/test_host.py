@@ -141,7 +141,7 @@ def test_walking_host_table_reproduces_oracle_workload():
     assert np.array_equal(m, mr) and total == tr
 
 
-@pytest.mark.parametrize("K", [4, 5, 6, 7])
+@pytest.mark.parametrize("K", [6, 7, 8])
 def test_root_jump_table_is_the_k_step_walk(K):
     g = W.rng(50 + K)
     pats = W.random_patterns(300, 1, 12, g) + [b"A" * 3, b"ACG", b"ACG"]
