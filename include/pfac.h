@@ -82,7 +82,7 @@ typedef struct {
 /* Launch shape of a match call.  Any field left 0 is chosen by the library.
  * Results never depend on the plan: every plan computes the same walks. */
 typedef struct {
-  uint32_t block;       /* threads per workgroup: 256, 512 or 1024 */
+  uint32_t block;       /* threads per workgroup: 256, 512, 768 or 1024 */
   uint32_t depth;       /* filter depth D, 6..10: every position first looks up its
                            D-base window in an LDS bitmap of 4^D bits; only windows
                            whose walk continues past depth D (or passes a final state
@@ -91,9 +91,17 @@ typedef struct {
   uint32_t variant;     /* PFAC_VARIANT_TILED (LDS text tile + filter bitmap) or
                            PFAC_VARIANT_GLOBAL (every walk from the root, text and
                            table read straight from global memory) */
+  uint32_t levels;      /* when every pattern is longer than D: trie levels from
+                           depth D down kept in LDS, found by rank from the filter
+                           bit (0 = as many as fit, possibly none); the walk goes on
+                           in the global next-state table below them.
+                           PFAC_LEVELS_NONE = filter bitmap only: surviving windows
+                           read the global depth-D jump table (always the case when
+                           some pattern has D bases or fewer) */
 } pfac_plan;
 
 enum { PFAC_VARIANT_TILED = 0, PFAC_VARIANT_GLOBAL = 1 };
+#define PFAC_LEVELS_NONE 0xFFFFFFFFu
 
 /* Per-text descriptor of a batched call (all offsets are from the bases the
  * call passes).  A text of ASCII encoding starting at a 16-byte aligned
@@ -175,7 +183,8 @@ int pfac_default_plan(const pfac_table* table, uint64_t n, int enc, pfac_plan* o
  *   pid      int32[cap]: smallest pattern ID ending at the state, 0 = none
  *   mult     uint32[cap]: number of pattern IDs ending at the state
  *   jump     uint32[4^D] or NULL, D = depth (6..10): for every D-base window
- *            (first base in the low bits) the state reached after D steps of
+ *            (key = sum of base_k * 4^(D-1-k), first base most significant;
+ *            A=0 C=1 G=2 T=3) the state reached after D steps of
  *            the walk (0 if it stopped earlier), bit 31 set if a final state was
  *            passed; jump_pid/jump_cnt (or NULL) receive the longest pattern
  *            passed and the occurrences passed within the D steps
@@ -186,6 +195,25 @@ int pfac_build_host(const char* const* patterns, const uint32_t* lengths, uint32
                     uint32_t* next, int32_t* pid, uint32_t* mult, uint64_t cap,
                     uint32_t depth, uint32_t* jump, int32_t* jump_pid, uint32_t* jump_cnt,
                     uint64_t* num_states, int64_t* bad_index);
+
+/*
+ * Host-only: the LDS image the scan kernel uses for filter depth D (6..10),
+ * for inspection and tests.  Layout of `words` (uint32): the 4^D-bit filter
+ * bitmap (bit x of word x/32 set iff the D-base window with key x leads to a
+ * trie node or passes a final state), then one word per 128 bitmap bits with
+ * the number of set bits before it, then for each trie level d = D, D+1, ...
+ * (`levels` of them) the node bytes of the level in breadth-first order (4
+ * per word, first node in the low byte; bits 0..3 = child A,C,G,T exists,
+ * bit 4 = final), padded to 16 nodes, followed by one word per 16 nodes with
+ * the number of child bits of the level before that group.
+ * meta[0] = levels, meta[1 + 3k .. 3 + 3k] = word offset of level D+k's node
+ * bytes, of its count words, and the image size in words up to that level.
+ * *num_words always receives the image size; words/meta are written only
+ * when it is <= cap (meta needs 1 + 3*8 entries).
+ */
+int pfac_build_host_image(const char* const* patterns, const uint32_t* lengths, uint32_t num,
+                          uint32_t depth, uint32_t* words, uint64_t cap, uint32_t* meta,
+                          uint64_t* num_words, int64_t* bad_index);
 
 /* Human-readable text of a status code (static storage). */
 const char* pfac_strerror(int status);

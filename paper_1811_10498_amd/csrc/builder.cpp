@@ -114,9 +114,18 @@ int build_host_table(const char* const* patterns, const uint32_t* lengths, uint3
       if (d < 32 && cnt == (1ull << (2 * d))) full = d; else break;
     }
     out->max_depth_full = full;
-    // 4. root jump tables of depth D: the result of the first D steps of the
-    //    walk for every D-base window, filled by a depth-first pass over the
-    //    trie (windows that leave the trie early share their entry)
+    // 4. node bytes: child mask and final flag of every state
+    out->node.assign(S, 0);
+    for (uint64_t i = 0; i < S; ++i) {
+      uint8_t v = out->out[i].pid ? 0x10 : 0;
+      for (int a = 0; a < 4; ++a)
+        if (out->next[i * 4 + a]) v |= (uint8_t)(1u << a);
+      out->node[i] = v;
+    }
+    // 5. root jump tables of depth D: the result of the first D steps of the
+    //    walk for every D-base window (first base most significant), filled by
+    //    a depth-first pass over the trie; windows that leave the trie early
+    //    form one contiguous key range each
     for (uint32_t D = kMinJump; D <= kMaxJump; ++D) {
       const uint64_t E = 1ull << (2 * D);
       out->jump[D].assign(E, 0);
@@ -135,13 +144,13 @@ int build_host_table(const char* const* patterns, const uint32_t* lengths, uint3
         }
         for (uint32_t a = 0; a < 4; ++a) {
           const uint32_t e = out->next[(uint64_t)f.s * 4 + a];
-          const uint64_t key = f.key | ((uint64_t)a << (2 * f.d));
+          const uint64_t key = (f.key << 2) | a;
           if (e == 0) {
-            // walk stops after d bases: every window with this prefix gets
-            // the finals passed so far (nothing if none)
+            // the walk stops after d bases: every window with this d+1 base
+            // prefix gets the finals passed so far (nothing if none)
             if (f.cnt) {
-              const uint64_t stride = 1ull << (2 * (f.d + 1));
-              for (uint64_t x = key; x < E; x += stride) {
+              const uint64_t span = 1ull << (2 * (D - f.d - 1));
+              for (uint64_t x = key * span; x < (key + 1) * span; ++x) {
                 out->jump[D][x] = kFinalBit;
                 out->jres[D][x] = OutEntry{f.best, f.cnt};
               }
@@ -159,6 +168,38 @@ int build_host_table(const char* const* patterns, const uint32_t* lengths, uint3
       }
       for (uint64_t x = 0; x < E; ++x)
         if (out->jump[D][x]) out->bitmap[D][x >> 5] |= 1u << (x & 31);
+      // LDS image: bitmap, its rank words, then node bytes and rank words of
+      // levels D, D+1, ... while the image stays within kImageMaxBytes
+      HostTable::Image& im = out->image[D];
+      im.words = out->bitmap[D];
+      uint32_t run = 0;
+      for (uint64_t g = 0; g < E / 128; ++g) {
+        im.words.push_back(run);
+        for (int k = 0; k < 4; ++k) run += (uint32_t)__builtin_popcount(out->bitmap[D][4 * g + k]);
+      }
+      im.levels = 0;
+      for (uint32_t k = 0; k < kImageLevels; ++k) {
+        const uint32_t d = D + k;
+        if (d + 1 >= depth_start.size()) break;
+        const uint64_t first = depth_start[d], count = depth_start[d + 1] - depth_start[d];
+        const uint64_t groups = (count + 15) / 16;
+        const uint64_t need = im.words.size() + groups * 4 + ((groups + 3) & ~3ull);
+        if (need * 4 > kImageMaxBytes) break;
+        im.byte_off[k] = (uint32_t)im.words.size();
+        std::vector<uint32_t> bytes(groups * 4, 0);
+        for (uint64_t i = 0; i < count; ++i)
+          bytes[i >> 2] |= (uint32_t)out->node[first + i] << (8 * (i & 3));
+        im.words.insert(im.words.end(), bytes.begin(), bytes.end());
+        im.pre_off[k] = (uint32_t)im.words.size();
+        uint32_t c = 0;
+        for (uint64_t g = 0; g < groups; ++g) {
+          im.words.push_back(c);
+          for (int w = 0; w < 4; ++w) c += (uint32_t)__builtin_popcount(bytes[4 * g + w] & 0x0F0F0F0Fu);
+        }
+        while (im.words.size() & 3) im.words.push_back(0);
+        im.upto[k] = (uint32_t)im.words.size();
+        im.levels = k + 1;
+      }
     }
   } catch (const std::bad_alloc&) {
     return PFAC_E_NOMEM;
@@ -192,6 +233,30 @@ extern "C" int pfac_build_host(const char* const* patterns, const uint32_t* leng
     for (uint64_t x = 0; x < E; ++x) {
       if (jump_pid) jump_pid[x] = h.jres[depth][x].pid;
       if (jump_cnt) jump_cnt[x] = h.jres[depth][x].mult;
+    }
+  }
+  return PFAC_OK;
+}
+
+extern "C" int pfac_build_host_image(const char* const* patterns, const uint32_t* lengths,
+                                     uint32_t num, uint32_t depth, uint32_t* words, uint64_t cap,
+                                     uint32_t* meta, uint64_t* num_words, int64_t* bad_index) {
+  using namespace pfac;
+  if (!num_words || depth < kMinJump || depth > kMaxJump) return PFAC_E_ARG;
+  HostTable h;
+  int rc = build_host_table(patterns, lengths, num, &h, bad_index);
+  if (rc != PFAC_OK) return rc;
+  const HostTable::Image& im = h.image[depth];
+  *num_words = im.words.size();
+  if (im.words.size() <= cap) {
+    if (words) memcpy(words, im.words.data(), im.words.size() * sizeof(uint32_t));
+    if (meta) {
+      meta[0] = im.levels;
+      for (uint32_t k = 0; k < kImageLevels; ++k) {
+        meta[1 + 3 * k] = k < im.levels ? im.byte_off[k] : 0;
+        meta[2 + 3 * k] = k < im.levels ? im.pre_off[k] : 0;
+        meta[3 + 3 * k] = k < im.levels ? im.upto[k] : 0;
+      }
     }
   }
   return PFAC_OK;

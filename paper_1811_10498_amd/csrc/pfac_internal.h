@@ -12,6 +12,8 @@ namespace pfac {
 // Root jump tables (and their LDS filter bitmaps) exist for these depths.
 constexpr uint32_t kMinJump = 6;
 constexpr uint32_t kMaxJump = 10;
+constexpr uint32_t kImageLevels = 8;      // trie levels an LDS image may hold
+constexpr uint32_t kImageMaxBytes = 160 * 1024;
 
 // Edge word of the next-state table: child state in bits 0..30 (0 = no edge,
 // the root is never a child), bit 31 set when the child is a final state.
@@ -25,7 +27,9 @@ struct OutEntry {
   uint32_t mult;
 };
 
-// Root jump entry for a D-base window x (first base in the low bits):
+// Window keys put the first base in the most significant bits, so keys of
+// one trie level sort exactly like the breadth-first numbering of that level.
+// Root jump entry for a D-base window x:
 // bits 0..30 = state reached after all D bases (0 if the walk stopped
 // earlier), bit 31 = at least one final state was passed within the D
 // steps; then jres[x] holds {longest such pattern ID, occurrences}.
@@ -44,6 +48,20 @@ struct HostTable {
   std::vector<uint32_t> jump[kMaxJump + 1];
   std::vector<OutEntry> jres[kMaxJump + 1];
   std::vector<uint32_t> bitmap[kMaxJump + 1];   // 4^D bits
+  std::vector<uint8_t> node;              // [S]: bits 0..3 child exists (A,C,G,T), bit 4 final
+  // LDS image per filter depth D: what the scan kernel copies into LDS.
+  //   words [0, 4^D/32)           filter bitmap
+  //   then 4^D/128 words          set bits before each 128-bit group (rank)
+  //   then for d = D .. D+levels-1: node bytes of level d (padded to 16 nodes),
+  //        then one word per 16 nodes: child bits of the level before the group
+  struct Image {
+    std::vector<uint32_t> words;
+    uint32_t levels = 0;                  // trie levels stored (D .. D+levels-1)
+    uint32_t byte_off[kImageLevels];      // word offset of level D+k's node bytes
+    uint32_t pre_off[kImageLevels];       // word offset of its rank words
+    uint32_t upto[kImageLevels];          // image words needed to hold levels D..D+k
+  };
+  Image image[kMaxJump + 1];
 };
 
 // Host build: validate, insert in input order, renumber breadth-first, pack.
@@ -56,7 +74,8 @@ struct DevTable {
   const OutEntry* out;
   const uint32_t* jump[kMaxJump + 1];
   const OutEntry* jres[kMaxJump + 1];
-  const uint32_t* bitmap[kMaxJump + 1];
+  const uint32_t* image[kMaxJump + 1];   // LDS image words (HostTable::Image)
+  const uint32_t* levels[kMaxJump + 1];  // per image level: {byte_off, pre_off, first state, 0}
   uint32_t num_states;
   uint32_t max_len;
 };

@@ -37,7 +37,7 @@
 namespace pfac {
 
 constexpr uint32_t kTile = 1024;       // start positions per wave tile
-constexpr uint32_t kSub = 256;         // positions per sub-chunk (4 per lane)
+constexpr uint32_t kQueue = 256;       // deep-walk queue entries per wave
 constexpr uint32_t kSlot = 16;         // hits parked per tile
 constexpr uint32_t kMaxHalo = 4096;    // longest halo staged in LDS (bases)
 constexpr uint32_t kRedTiles = 4096;   // tiles per reduce/scatter workgroup
@@ -65,7 +65,14 @@ struct ScanParams {
   const OutEntry* out;
   const uint32_t* jump;           // depth-D jump table (TILED)
   const OutEntry* jres;
-  const uint32_t* bitmap;         // 4^D bits (TILED)
+  const uint32_t* image;          // LDS image of depth D (TILED): filter bitmap, its
+                                  // rank words, node bytes of the levels below
+  uint32_t image_words;           // image words copied into LDS
+  uint32_t levels;                // trie levels held in LDS (D .. D+levels-1)
+  uint32_t lds_trie;              // 1: no pattern is D bases or shorter, so a set
+                                  // filter bit is a depth-D node found by rank
+  const u32x4* lvl;                  // per LDS level: image word offset of its node
+                                     // bytes, of its rank words, its first state
   uint32_t D;
   uint32_t halo;                  // staged bases past the tile, multiple of 64
   uint32_t single;                // 1: one text (seg0), tiles 0..local_tiles-1
@@ -89,16 +96,17 @@ __device__ __forceinline__ int ascii_code(uint32_t b) {
   return b == 'A' ? 0 : b == 'C' ? 1 : b == 'G' ? 2 : b == 'T' ? 3 : -1;
 }
 
-// Four ASCII bytes -> four 2-bit codes (low byte first, 8 bits) and a 4-bit
-// "not a base" mask.  code = ((b >> 1) ^ (b >> 2)) & 3 maps A,C,G,T to
-// 0,1,2,3; a byte is a base iff re-encoding its code gives the byte back.
+// Four ASCII bytes -> four 2-bit codes (first byte in the top two bits of
+// the 8-bit result) and a 4-bit "not a base" mask (first byte in bit 0).
+// code = ((b >> 1) ^ (b >> 2)) & 3 maps A,C,G,T to 0,1,2,3; a byte is a base
+// iff re-encoding its code gives the byte back.
 __device__ __forceinline__ void ascii4(uint32_t x, uint32_t& code8, uint32_t& inv4) {
   const uint32_t cb = ((x >> 1) ^ (x >> 2)) & 0x03030303u;
   const uint32_t expect = __builtin_amdgcn_perm(0u, 0x54474341u, cb);  // 'A','C','G','T'
   const uint32_t t = x ^ expect;
   const uint32_t nz = (((t & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | t) & 0x80808080u;
   inv4 = ((nz >> 7) * 0x01020408u) >> 24;
-  code8 = (cb * 0x01041040u) >> 24;
+  code8 = (cb * 0x40100401u) >> 24;
 }
 
 __device__ __forceinline__ void wave_sync() {
@@ -124,6 +132,23 @@ __device__ __forceinline__ uint32_t wave_excl(uint32_t v, uint32_t* total) {
   }
   *total = __shfl(inc, 63, 64);
   return inc - v;
+}
+
+// Exclusive prefix over the 64 lanes of a value below 2^BITS, without LDS:
+// each bit plane is a ballot, and a lane counts the set bits of the lanes
+// below it (mbcnt).  *total receives the wave sum.
+template <int BITS>
+__device__ __forceinline__ uint32_t wave_excl_small(uint32_t v, uint32_t* total) {
+  uint32_t pre = 0, tot = 0;
+  #pragma unroll
+  for (int k = 0; k < BITS; ++k) {
+    const uint64_t m = __ballot((v >> k) & 1u);
+    pre += __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u)) << k;
+    tot += (uint32_t)__popcll(m) << k;
+  }
+  *total = tot;
+  return pre;
 }
 
 // One base of a text in global memory (out of range = invalid).
@@ -153,7 +178,7 @@ __device__ __forceinline__ void walk(uint32_t s, uint64_t q, const uint32_t* __r
     } else {
       const uint32_t qq = (uint32_t)q;
       if ((iv[qq >> 5] >> (qq & 31)) & 1u) break;
-      c = (pk[qq >> 4] >> (2 * (qq & 15))) & 3u;
+      c = (pk[qq >> 4] >> (30 - 2 * (qq & 15))) & 3u;
     }
     const uint32_t e = next[(uint64_t)s * 4 + c];
     if (e == 0) break;
@@ -167,85 +192,230 @@ __device__ __forceinline__ void walk(uint32_t s, uint64_t q, const uint32_t* __r
   }
 }
 
-// Stage bases [t0, t0+span) of one text into a wave's LDS area: 2-bit codes
-// (16 per word) and an invalid bit per base (32 per word); bases past the
-// end of the text are invalid, and two sentinel words follow the span.
-__device__ __forceinline__ void stage_text(const uint8_t* __restrict__ t, uint64_t n,
-                                           uint32_t enc, uint64_t t0, uint32_t span,
-                                           uint32_t* pk, uint32_t* iv) {
-  const uint32_t lane = threadIdx.x & 63;
-  const uint32_t nwords = span / 16;
-  uint16_t* iv16 = reinterpret_cast<uint16_t*>(iv);
-  if (enc == PFAC_TEXT_ASCII) {
-    const bool aligned = ((reinterpret_cast<uintptr_t>(t) & 15) == 0);
-    for (uint32_t c = lane; c < nwords; c += 64) {
-      const uint64_t g = t0 + 16ull * c;
-      uint32_t w[4];
-      if (aligned && g + 16 <= n) {
-        const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(t + g));
-        w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
-      } else {
-        #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          uint32_t x = 0;
-          #pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            const uint64_t q = g + 4 * k + b;
-            x |= (uint32_t)(q < n ? t[q] : 0u) << (8 * b);
+// Set bits among the first t (0..15) node bytes of a 16-node group (child
+// bits only, the low nibble of each byte).
+__device__ __forceinline__ uint32_t children_before(const u32x4& g, uint32_t t) {
+  const uint32_t m = 0x0F0F0F0Fu;
+  const uint32_t wi = t >> 2;
+  const uint32_t part = (1u << (8 * (t & 3))) - 1u;   // bytes before t in its word
+  uint32_t c = 0;
+  c += __builtin_popcount(g.x & m & (wi > 0 ? ~0u : part));
+  c += __builtin_popcount(g.y & m & (wi > 1 ? ~0u : wi == 1 ? part : 0u));
+  c += __builtin_popcount(g.z & m & (wi > 2 ? ~0u : wi == 2 ? part : 0u));
+  c += __builtin_popcount(g.w & m & (wi == 3 ? part : 0u));
+  return c;
+}
+
+// One queued walk of the tiled kernel.  Entry e: tile index of the start
+// position in bits 0..14, bit 15 set when the position's D-base window holds
+// a non-base (then the walk starts at the root).  Otherwise the first D
+// bases are the key x of the window:
+//   * lds_trie: x names a depth-D node; its index within the level is the
+//     rank of x among the set filter bits.  The walk goes on through the
+//     trie levels held in LDS (a child's index = child bits of the level's
+//     earlier nodes + the node's own lower child bits), then hands over to
+//     the global next-state table at the last LDS level;
+//   * otherwise the global depth-D jump table gives the state reached and
+//     the finals passed within the first D bases.
+// Every route ends in the same global-table loop.
+__device__ __forceinline__ int32_t deep_walk(uint32_t e, uint32_t D, uint32_t lds_trie,
+                                             uint32_t levels, const uint32_t* lds,
+                                             const uint32_t* bmpre, const u32x4* __restrict__ lvl,
+                                             const uint32_t* __restrict__ pk,
+                                             const uint32_t* __restrict__ iv,
+                                             const uint32_t* __restrict__ next,
+                                             const OutEntry* __restrict__ out,
+                                             const uint32_t* __restrict__ jump,
+                                             const OutEntry* __restrict__ jres,
+                                             unsigned long long& occ) {
+  const uint32_t qt = e & 0x7FFFu;
+  int32_t best = 0;
+  uint32_t s = 0, q = qt;
+  if (!(e & 0x8000u)) {
+    const uint32_t x = (uint32_t)((((uint64_t)pk[qt >> 4] << 32) | pk[(qt >> 4) + 1])
+                                  << (2 * (qt & 15)) >> (64 - 2 * D));
+    q = qt + D;
+    if (lds_trie) {
+      const u32x4 bg = *reinterpret_cast<const u32x4*>(lds + ((x >> 7) << 2));
+      const uint32_t wi = (x >> 5) & 3u, part = (1u << (x & 31u)) - 1u;
+      uint32_t j = bmpre[x >> 7];
+      j += __builtin_popcount(bg.x & (wi > 0 ? ~0u : part));
+      j += __builtin_popcount(bg.y & (wi > 1 ? ~0u : wi == 1 ? part : 0u));
+      j += __builtin_popcount(bg.z & (wi > 2 ? ~0u : wi == 2 ? part : 0u));
+      j += __builtin_popcount(bg.w & (wi == 3 ? part : 0u));
+      // all active lanes move down one level per step: the level is uniform
+      u32x4 L = lvl[0];
+      if (levels) {
+        for (uint32_t k = 0;;) {
+          const u32x4 g = *reinterpret_cast<const u32x4*>(lds + L.x + ((j >> 4) << 2));
+          const uint32_t pre = lds[L.y + (j >> 4)];
+          const uint32_t t = j & 15u;
+          const uint32_t word = t < 4 ? g.x : t < 8 ? g.y : t < 12 ? g.z : g.w;
+          const uint32_t b = (word >> (8 * (t & 3))) & 0xFFu;
+          if (b & 0x10u) {
+            const OutEntry o = out[L.z + j];
+            best = o.pid;
+            occ += o.mult;
           }
-          w[k] = x;
+          if ((iv[q >> 5] >> (q & 31)) & 1u) return best;
+          const uint32_t c = (pk[q >> 4] >> (30 - 2 * (q & 15))) & 3u;
+          if (!((b >> c) & 1u)) return best;
+          if (++k == levels) break;                 // hand over below this node
+          j = pre + children_before(g, t) + __builtin_popcount(b & ((1u << c) - 1u));
+          ++q;
+          L = lvl[__builtin_amdgcn_readfirstlane(k)];
         }
       }
-      uint32_t packed = 0, inv = 0;
-      #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        uint32_t c8, i4;
-        ascii4(w[k], c8, i4);
-        packed |= c8 << (8 * k);
-        inv |= i4 << (4 * k);
+      s = L.z + j;
+    } else {
+      const uint32_t jj = jump[x];
+      if (jj & kFinalBit) {
+        const OutEntry o = jres[x];
+        best = o.pid;
+        occ += o.mult;
       }
-      pk[c] = packed;
-      iv16[c] = (uint16_t)inv;
-    }
-  } else {
-    const bool aligned = ((reinterpret_cast<uintptr_t>(t) & 15) == 0);
-    const uint32_t nchunks = span / 64;   // 16 bytes = 64 bases
-    for (uint32_t c = lane; c < nchunks; c += 64) {
-      const uint64_t g = t0 + 64ull * c;
-      uint32_t w[4];
-      uint32_t inv[4] = {0, 0, 0, 0};
-      if (aligned && g + 64 <= n) {
-        const u32x4 v = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(t + g / 4));
-        w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
-      } else {
-        #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          uint32_t x = 0, m = 0;
-          for (int b = 0; b < 16; ++b) {
-            const uint64_t q = g + 16 * k + b;
-            if (q < n) x |= (uint32_t)((t[q >> 2] >> (2 * (q & 3))) & 3u) << (2 * b);
-            else m |= 1u << b;
-          }
-          w[k] = x;
-          inv[k] = m;
-        }
-      }
-      #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        pk[4 * c + k] = w[k];
-        iv16[4 * c + k] = (uint16_t)inv[k];
-      }
+      s = jj & kStateMask;
+      if (!s) return best;
     }
   }
+  walk<false>(s, q, pk, iv, next, out, nullptr, 0, 0, best, occ);
+  return best;
+}
+
+// Text of one wave tile: bases [t0, t0+span) of one text, span = kTile + halo.
+// Staged into the wave's LDS area as 2-bit codes, 16 per word with the first
+// base in the top bits (a window of bases then reads as a key with its first
+// base most significant), and an invalid bit per base, 32 per word with the
+// first base in bit 0.  Bases past the end of the text are invalid; two
+// sentinel words follow the span.  Staging is split in two: fetch() issues
+// the 16-byte loads of the lane's chunks into registers (for the next tile,
+// while the current one is processed) and commit() converts them into LDS.
+struct TextRef {
+  const uint8_t* t;
+  uint64_t n;
+  uint64_t t0;
+  uint32_t enc;
+};
+
+struct Prefetch {
+  u32x4 a, b;          // chunks lane and lane+64
+  uint32_t fast;       // bit 0: a loaded, bit 1: b loaded
+};
+
+__device__ __forceinline__ uint32_t stage_chunks(uint32_t enc, uint32_t span) {
+  return enc == PFAC_TEXT_ASCII ? span / 16 : span / 64;   // 16-byte chunks
+}
+
+__device__ __forceinline__ Prefetch fetch(const TextRef& r, uint32_t span) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t nch = stage_chunks(r.enc, span);
+  const uint32_t per = r.enc == PFAC_TEXT_ASCII ? 16u : 64u;   // bases per chunk
+  const bool aligned = ((reinterpret_cast<uintptr_t>(r.t) & 15) == 0);
+  Prefetch f;
+  f.fast = 0;
+  f.a = u32x4{0, 0, 0, 0};
+  f.b = u32x4{0, 0, 0, 0};
+  const uint64_t ga = r.t0 + (uint64_t)per * lane;
+  if (aligned && lane < nch && ga + per <= r.n) {
+    f.a = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(r.t + ga * 16 / per));
+    f.fast |= 1u;
+  }
+  const uint64_t gb = ga + (uint64_t)per * 64;
+  if (aligned && lane + 64 < nch && gb + per <= r.n) {
+    f.b = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(r.t + gb * 16 / per));
+    f.fast |= 2u;
+  }
+  return f;
+}
+
+// One 16-byte ASCII chunk -> 16 codes (big-endian word) and 16 invalid bits.
+__device__ __forceinline__ void ascii_chunk(const u32x4& v, uint32_t& packed, uint32_t& inv) {
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+  uint32_t cb[4], t[4];
+  #pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    cb[k] = ((w[k] >> 1) ^ (w[k] >> 2)) & 0x03030303u;
+    t[k] = w[k] ^ __builtin_amdgcn_perm(0u, 0x54474341u, cb[k]);   // 0 where a base
+  }
+  packed = 0;
+  #pragma unroll
+  for (int k = 0; k < 4; ++k) packed |= ((cb[k] * 0x40100401u) >> 24) << (24 - 8 * k);
+  inv = 0;
+  if ((t[0] | t[1] | t[2] | t[3]) != 0) {
+    #pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t nz = (((t[k] & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | t[k]) & 0x80808080u;
+      inv |= (((nz >> 7) * 0x01020408u) >> 24) << (4 * k);
+    }
+  }
+}
+
+__device__ __forceinline__ void commit_chunk(const TextRef& r, uint32_t c, bool loaded,
+                                             const u32x4& v, uint32_t* pk, uint32_t* iv) {
+  uint16_t* iv16 = reinterpret_cast<uint16_t*>(iv);
+  if (r.enc == PFAC_TEXT_ASCII) {
+    u32x4 x = v;
+    if (!loaded) {              // misaligned text or a chunk crossing its end
+      const uint64_t g = r.t0 + 16ull * c;
+      uint32_t w[4];
+      #pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        uint32_t y = 0;
+        #pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const uint64_t q = g + 4 * k + b;
+          y |= (uint32_t)(q < r.n ? r.t[q] : 0u) << (8 * b);
+        }
+        w[k] = y;
+      }
+      x = u32x4{w[0], w[1], w[2], w[3]};
+    }
+    uint32_t packed, inv;
+    ascii_chunk(x, packed, inv);
+    pk[c] = packed;
+    iv16[c] = (uint16_t)inv;
+  } else {
+    uint32_t w[4] = {v.x, v.y, v.z, v.w};
+    uint32_t inv[4] = {0, 0, 0, 0};
+    if (!loaded) {
+      const uint64_t g = r.t0 + 64ull * c;
+      #pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        uint32_t y = 0, m = 0;
+        for (int b = 0; b < 16; ++b) {
+          const uint64_t q = g + 16 * k + b;
+          if (q < r.n) y |= (uint32_t)((r.t[q >> 2] >> (2 * (q & 3))) & 3u) << (2 * b);
+          else m |= 1u << b;
+        }
+        w[k] = y;
+        inv[k] = m;
+      }
+    }
+    #pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      // base b sits in bits 2b..2b+1: reverse the order of the 2-bit fields
+      const uint32_t rv = __builtin_bitreverse32(w[k]);
+      pk[4 * c + k] = ((rv >> 1) & 0x55555555u) | ((rv & 0x55555555u) << 1);
+      iv16[4 * c + k] = (uint16_t)inv[k];
+    }
+  }
+}
+
+__device__ __forceinline__ void commit(const TextRef& r, uint32_t span, const Prefetch& f,
+                                       uint32_t* pk, uint32_t* iv) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t nch = stage_chunks(r.enc, span);
+  if (lane < nch) commit_chunk(r, lane, f.fast & 1u, f.a, pk, iv);
+  if (lane + 64 < nch) commit_chunk(r, lane + 64, f.fast & 2u, f.b, pk, iv);
   if (lane < 2) {
-    pk[nwords + lane] = 0;
+    pk[span / 16 + lane] = 0;
     iv[span / 32 + lane] = 0xFFFFFFFFu;
   }
 }
 
 // LDS of one wave, in 32-bit words, each part a multiple of 4 words so the
 // 16-byte LDS accesses stay aligned: text codes (+2 sentinel words), invalid
-// bits (+2), output staging of a sub-chunk, queue of a sub-chunk (16-bit).
+// bits (+2), deep-walk results and deep-walk queue (16-bit entries).
 __host__ __device__ constexpr uint32_t round4(uint32_t x) { return (x + 3) & ~3u; }
 __host__ __device__ constexpr uint32_t pk_words(uint32_t halo) {
   return round4((kTile + halo) / 16 + 2);
@@ -254,167 +424,217 @@ __host__ __device__ constexpr uint32_t iv_words(uint32_t halo) {
   return round4((kTile + halo) / 32 + 2);
 }
 __host__ __device__ constexpr uint32_t wave_words(uint32_t halo) {
-  return pk_words(halo) + iv_words(halo) + kSub + kSub / 2;
+  return pk_words(halo) + iv_words(halo) + kQueue + kQueue / 2;
 }
 
-// Main scan.  Each wave takes whole 1024-position tiles (grid-stride).
+struct TileLoc {
+  DevSeg seg;
+  uint64_t ts;      // tile index within its text
+  uint64_t gtile;   // tile index in the call
+};
+
+__device__ __forceinline__ TileLoc locate(const ScanParams& p, uint64_t lt) {
+  TileLoc L;
+  if (p.single) {
+    L.seg = p.seg0;
+    L.ts = lt;
+    L.gtile = lt;
+  } else {
+    uint32_t lo = 0, hi = p.ngroup;   // prefix[lo] <= lt < prefix[hi]
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (p.group_prefix[mid] <= lt) lo = mid; else hi = mid;
+    }
+    const uint32_t si = p.group_segs[lo];
+    L.seg = p.segs[si];
+    L.ts = lt - p.group_prefix[lo];
+    L.gtile = p.tile_prefix[si] + L.ts;
+  }
+  return L;
+}
+
+// Main scan.  Each wave takes whole 1024-position tiles (grid-stride).  A
+// lane owns 16 positions of a tile, four groups of four consecutive ones:
+// q = g*256 + 4*lane + r.  Positions whose walk goes on past the filter are
+// queued and walked by all lanes together; their results come back through
+// a result slot per queue entry.
 template <int BLOCK, bool GLOBAL>
 __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
   extern __shared__ uint32_t lds[];
   const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const uint32_t D = GLOBAL ? 0u : p.D;
-  const uint32_t bm_words = GLOBAL ? 0u : (1u << (2 * D)) / 32;
-  uint32_t* bm = lds;
+  const uint32_t img_words = GLOBAL ? 0u : p.image_words;
+  uint32_t* bm = lds;                             // image: filter bitmap first
+  const uint32_t* bmpre = lds + (GLOBAL ? 0u : (1u << (2 * D)) / 32);
+  __shared__ int32_t g_res[GLOBAL ? BLOCK / 64 * kQueue : 1];
+  __shared__ uint16_t g_queue[GLOBAL ? BLOCK / 64 * kQueue : 1];
   const uint32_t span = kTile + p.halo;
-  uint32_t* pk = lds + bm_words + wave * (GLOBAL ? 0u : wave_words(p.halo));
+  uint32_t* pk = lds + img_words + wave * (GLOBAL ? 0u : wave_words(p.halo));
   uint32_t* iv = pk + pk_words(p.halo);
-  int32_t* outs = reinterpret_cast<int32_t*>(iv + iv_words(p.halo));
-  uint16_t* queue = reinterpret_cast<uint16_t*>(outs + kSub);
-  __shared__ int32_t g_outs[GLOBAL ? BLOCK / 64 * kSub : 1];
-  __shared__ uint16_t g_queue[GLOBAL ? BLOCK / 64 * kSub : 1];
+  int32_t* res = reinterpret_cast<int32_t*>(iv + iv_words(p.halo));
+  uint16_t* queue = reinterpret_cast<uint16_t*>(res + kQueue);
   if (GLOBAL) {
-    outs = g_outs + wave * kSub;
-    queue = g_queue + wave * kSub;
+    res = g_res + wave * kQueue;
+    queue = g_queue + wave * kQueue;
   }
 
   if (!GLOBAL) {
-    const u32x4* src = reinterpret_cast<const u32x4*>(p.bitmap);
+    const u32x4* src = reinterpret_cast<const u32x4*>(p.image);
     u32x4* dst = reinterpret_cast<u32x4*>(bm);
-    for (uint32_t i = threadIdx.x; i < bm_words / 4; i += BLOCK) dst[i] = src[i];
+    for (uint32_t i = threadIdx.x; i < img_words / 4; i += BLOCK) dst[i] = src[i];
     __syncthreads();
   }
 
   const uint32_t dmask = (1u << D) - 1u;
-  const uint32_t xmask = (uint32_t)((1ull << (2 * D)) - 1u);
+  const uint32_t gmask = (1u << (D + 3)) - 1u;   // bases of the 4 windows of a group
+  const uint32_t sh8 = 8u * (lane & 3u);          // bits before the lane's group in its word
+  const uint32_t sh4 = 4u * (lane & 7u);          // its bit in the invalid-bit word
   const uint64_t nwaves = (uint64_t)gridDim.x * (BLOCK / 64);
-  for (uint64_t lt = (uint64_t)blockIdx.x * (BLOCK / 64) + wave; lt < p.local_tiles;
-       lt += nwaves) {
-    // ---- which text and tile
-    DevSeg seg;
-    uint64_t ts, gtile;
-    if (p.single) {
-      seg = p.seg0;
-      ts = lt;
-      gtile = lt;
-    } else {
-      uint32_t lo = 0, hi = p.ngroup;   // prefix[lo] <= lt < prefix[hi]
-      while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (p.group_prefix[mid] <= lt) lo = mid; else hi = mid;
-      }
-      const uint32_t si = p.group_segs[lo];
-      seg = p.segs[si];
-      ts = lt - p.group_prefix[lo];
-      gtile = p.tile_prefix[si] + ts;
-    }
-    const uint64_t t0 = ts * kTile;
-    const uint64_t n = seg.n;
-    const uint8_t* text = p.text + seg.text_off;
-    int32_t* mrow = p.match ? p.match + seg.match_off : nullptr;
-    const bool maligned = mrow && ((reinterpret_cast<uintptr_t>(mrow) & 15) == 0);
+  uint64_t lt = (uint64_t)blockIdx.x * (BLOCK / 64) + wave;
+  if (lt >= p.local_tiles) return;
+  TileLoc cur = locate(p, lt);
+  Prefetch pf{};
+  if (!GLOBAL)
+    pf = fetch(TextRef{p.text + cur.seg.text_off, cur.seg.n, cur.ts * kTile, cur.seg.enc}, span);
+
+  for (;;) {
+    const uint64_t t0 = cur.ts * kTile;
+    const uint64_t n = cur.seg.n;
+    const uint32_t nt = (uint32_t)((n - t0) < kTile ? (n - t0) : kTile);  // positions in text
+    const bool full = nt == kTile;
+    const uint8_t* text = p.text + cur.seg.text_off;
+    const uint32_t enc = cur.seg.enc;
+    const uint64_t gtile = cur.gtile;
+    int32_t* mt = p.match ? p.match + cur.seg.match_off + t0 : nullptr;
+    const bool maligned = mt && ((reinterpret_cast<uintptr_t>(mt) & 15) == 0);
 
     if (!GLOBAL) {
-      stage_text(text, n, seg.enc, t0, span, pk, iv);
+      commit(TextRef{text, n, t0, enc}, span, pf, pk, iv);
       wave_sync();
     }
+    // next tile: locate it and start loading its text now
+    const uint64_t lt_next = lt + nwaves;
+    const bool more = lt_next < p.local_tiles;
+    TileLoc nxt = cur;
+    if (more) {
+      nxt = locate(p, lt_next);
+      if (!GLOBAL)
+        pf = fetch(TextRef{p.text + nxt.seg.text_off, nxt.seg.n, nxt.ts * kTile, nxt.seg.enc},
+                   span);
+    }
 
-    unsigned long long occ = 0;
-    uint32_t tile_hits = 0;
-    #pragma unroll 1
-    for (uint32_t sc = 0; sc < kTile / kSub; ++sc) {
-      // ---- classify this lane's 4 positions
-      const uint32_t q0 = sc * kSub + 4 * lane;          // tile-local index
-      const uint64_t pos0 = t0 + q0;                      // text index
-      uint32_t want = 0, slow = 0;
+    // ---- classify the lane's 16 positions: bit 4g+r of want / slow
+    uint32_t want = 0, slow = 0;
+    #pragma unroll
+    for (uint32_t g = 0; g < 4; ++g) {
+      const uint32_t q0 = g * 256 + 4 * lane;
+      const uint32_t vmask =
+          full ? 0xFu : (q0 >= nt ? 0u : (nt - q0 >= 4 ? 0xFu : (1u << (nt - q0)) - 1u));
+      uint32_t m4 = 0, s4 = 0;
       if (GLOBAL) {
-        #pragma unroll
-        for (uint32_t r = 0; r < 4; ++r)
-          if (pos0 + r < n) { want |= 1u << r; slow |= 1u << r; }
+        m4 = s4 = vmask;
       } else {
-        const uint64_t win =
-            ((uint64_t)pk[(q0 >> 4) + 1] << 32 | pk[q0 >> 4]) >> (2 * (q0 & 15));
-        const uint64_t ivw = ((uint64_t)iv[(q0 >> 5) + 1] << 32 | iv[q0 >> 5]) >> (q0 & 31);
+        const uint32_t wi = q0 >> 4, ii = q0 >> 5;
+        // 16 bases from q0, first base in the top bits
+        const uint32_t w = (uint32_t)((((uint64_t)pk[wi] << 32) | pk[wi + 1]) << sh8 >> 32);
+        const uint32_t inv = __builtin_amdgcn_alignbit(iv[ii + 1], iv[ii], sh4);
         #pragma unroll
         for (uint32_t r = 0; r < 4; ++r) {
-          if (pos0 + r >= n) continue;
-          if (((uint32_t)(ivw >> r) & dmask) != 0) {
-            want |= 1u << r;       // window not all bases: walk from the root
-            slow |= 1u << r;
-          } else {
-            const uint32_t x = (uint32_t)(win >> (2 * r)) & xmask;
-            if ((bm[x >> 5] >> (x & 31)) & 1u) want |= 1u << r;
-          }
+          const uint32_t x = __builtin_amdgcn_ubfe(w, 32 - 2 * r - 2 * D, 2 * D);
+          m4 |= __builtin_amdgcn_ubfe(bm[x >> 5], x & 31u, 1u) << r;
         }
+        if (inv & gmask) {
+          // a window holds a non-base: such positions walk from the root
+          #pragma unroll
+          for (uint32_t r = 0; r < 4; ++r)
+            if ((inv >> r) & dmask) s4 |= 1u << r;
+          m4 |= s4;
+        }
+        m4 &= vmask;
+        s4 &= vmask;
       }
-      *reinterpret_cast<i32x4*>(outs + 4 * lane) = i32x4{0, 0, 0, 0};
-      // ---- compact the surviving positions of the wave into the queue
-      uint32_t count = 0;
-      #pragma unroll
-      for (uint32_t r = 0; r < 4; ++r) {
-        const uint64_t m = __ballot((want >> r) & 1u);
-        if ((want >> r) & 1u) {
-          const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-          queue[count + rank] = (uint16_t)((4 * lane + r) | (((slow >> r) & 1u) << 15));
+      want |= m4 << (4 * g);
+      slow |= s4 << (4 * g);
+    }
+
+    // ---- queue the surviving positions (lane order, then position order):
+    //      one pass over the whole tile when the queue holds it, else one
+    //      pass per group of positions
+    unsigned long long occ = 0;
+    uint32_t tile_hits = 0;
+    uint32_t total;
+    const uint32_t base = wave_excl_small<5>(__builtin_popcount(want), &total);
+    const uint32_t passes = total <= kQueue ? 1u : 4u;
+    for (uint32_t pass = 0; pass < passes; ++pass) {
+      const uint32_t sel = passes == 1 ? 0xFFFFu : (0xFu << (4 * pass));
+      const uint32_t wsel = want & sel;
+      uint32_t pbase = base, ptotal = total;
+      if (passes != 1) pbase = wave_excl_small<5>(__builtin_popcount(wsel), &ptotal);
+      {
+        uint32_t m = wsel, k = pbase;
+        while (m) {
+          const uint32_t bit = __builtin_ctz(m);
+          m &= m - 1u;
+          const uint32_t q = (bit >> 2) * 256 + 4 * lane + (bit & 3);
+          queue[k++] = (uint16_t)(q | (((slow >> bit) & 1u) << 15));
         }
-        count += (uint32_t)__popcll(m);
       }
       wave_sync();
       // ---- walk the queued positions with all lanes
-      for (uint32_t i = lane; i < count; i += 64) {
+      #pragma unroll 1
+      for (uint32_t i = lane; i < ptotal; i += 64) {
         const uint32_t e = queue[i];
-        const uint32_t qs = e & 0x7FFFu;                 // sub-chunk index
-        const uint32_t qt = sc * kSub + qs;              // tile index
+        const uint32_t qt = e & 0x7FFFu;                 // index within the tile
         int32_t best = 0;
         if (GLOBAL) {
-          walk<true>(0u, t0 + qt, nullptr, nullptr, p.next, p.out, text, n, seg.enc, best, occ);
-        } else if (e & 0x8000u) {
-          walk<false>(0u, qt, pk, iv, p.next, p.out, nullptr, 0, 0, best, occ);
+          walk<true>(0u, t0 + qt, nullptr, nullptr, p.next, p.out, text, n, enc, best, occ);
         } else {
-          const uint64_t w =
-              ((uint64_t)pk[(qt >> 4) + 1] << 32 | pk[qt >> 4]) >> (2 * (qt & 15));
-          const uint32_t x = (uint32_t)w & xmask;
-          const uint32_t j = p.jump[x];
-          if (j & kFinalBit) {
-            const OutEntry o = p.jres[x];
-            best = o.pid;
-            occ += o.mult;
-          }
-          const uint32_t s = j & kStateMask;
-          if (s) walk<false>(s, qt + D, pk, iv, p.next, p.out, nullptr, 0, 0, best, occ);
+          best = deep_walk(e, D, p.lds_trie, p.levels, lds, bmpre, p.lvl, pk, iv, p.next, p.out,
+                           p.jump, p.jres, occ);
         }
-        if (best) outs[qs] = best;
+        res[i] = best;
       }
       wave_sync();
-      // ---- dense output: one 16-byte store per lane, 1 KB per wave
-      const i32x4 v = *reinterpret_cast<const i32x4*>(outs + 4 * lane);
-      if (mrow) {
-        if (maligned && pos0 + 4 <= n) {
-          __builtin_nontemporal_store(v, reinterpret_cast<i32x4*>(mrow + pos0));
-        } else {
-          if (pos0 < n) mrow[pos0] = v.x;
-          if (pos0 + 1 < n) mrow[pos0 + 1] = v.y;
-          if (pos0 + 2 < n) mrow[pos0 + 2] = v.z;
-          if (pos0 + 3 < n) mrow[pos0 + 3] = v.w;
+      // ---- the groups of this pass: pick up results, dense output, hits
+      #pragma unroll 1
+      for (uint32_t g = 0; g < 4; ++g) {
+        if (!((sel >> (4 * g)) & 1u)) continue;
+        const uint32_t q0 = g * 256 + 4 * lane;
+        int32_t vv[4];
+        #pragma unroll
+        for (uint32_t r = 0; r < 4; ++r) {
+          const uint32_t bit = 4 * g + r;
+          vv[r] = ((wsel >> bit) & 1u) ? res[pbase + __builtin_popcount(wsel & ((1u << bit) - 1u))]
+                                       : 0;
         }
-      }
-      // ---- hits of this sub-chunk, in position order, into the tile's slot
-      const uint32_t c = (v.x != 0) + (v.y != 0) + (v.z != 0) + (v.w != 0);
-      if (__ballot(c != 0)) {
-        uint32_t tot;
-        uint32_t o = tile_hits + wave_excl(c, &tot);
-        if (p.slots) {
-          Slot* sl = p.slots + gtile * kSlot;
-          const int32_t vv[4] = {v.x, v.y, v.z, v.w};
-          #pragma unroll
-          for (uint32_t r = 0; r < 4; ++r) {
-            if (vv[r]) {
-              if (o < kSlot) sl[o] = Slot{(uint32_t)(pos0 + r), vv[r]};
-              ++o;
-            }
+        const i32x4 v = {vv[0], vv[1], vv[2], vv[3]};
+        if (mt) {
+          if (maligned && q0 + 4 <= nt) {
+            __builtin_nontemporal_store(v, reinterpret_cast<i32x4*>(mt + q0));
+          } else {
+            if (q0 < nt) mt[q0] = v.x;
+            if (q0 + 1 < nt) mt[q0 + 1] = v.y;
+            if (q0 + 2 < nt) mt[q0 + 2] = v.z;
+            if (q0 + 3 < nt) mt[q0 + 3] = v.w;
           }
         }
-        tile_hits += tot;
+        const bool any = (vv[0] | vv[1] | vv[2] | vv[3]) != 0;
+        if (__ballot(any)) {
+          const uint32_t c = (vv[0] != 0) + (vv[1] != 0) + (vv[2] != 0) + (vv[3] != 0);
+          uint32_t tot;
+          uint32_t o = tile_hits + wave_excl_small<3>(c, &tot);
+          if (p.slots) {
+            Slot* sl = p.slots + gtile * kSlot;
+            #pragma unroll
+            for (uint32_t r = 0; r < 4; ++r) {
+              if (vv[r]) {
+                if (o < kSlot) sl[o] = Slot{(uint32_t)(t0 + q0 + r), vv[r]};
+                ++o;
+              }
+            }
+          }
+          tile_hits += tot;
+        }
       }
       wave_sync();
     }
@@ -423,6 +643,9 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
       p.tile_hits[gtile] = tile_hits;
       p.tile_occ[gtile] = tocc;
     }
+    if (!more) break;
+    lt = lt_next;
+    cur = nxt;
   }
 }
 
@@ -606,8 +829,8 @@ __global__ __launch_bounds__(1024) void pfac_scatter_kernel(ScatterParams p) {
     }
     const uint64_t t0 = ts * kTile;
     const uint8_t* tx = p.text + seg.text_off;
-    for (uint32_t sc = 0; sc < kTile / kSub; ++sc) {
-      const uint64_t pos0 = t0 + sc * kSub + 4 * lane;
+    for (uint32_t k = 0; k < kTile / 256; ++k) {   // 64 lanes x 4 positions per step
+      const uint64_t pos0 = t0 + k * 256 + 4 * lane;
       int32_t v[4] = {0, 0, 0, 0};
       #pragma unroll
       for (uint32_t r = 0; r < 4; ++r) {
@@ -788,8 +1011,17 @@ static uint32_t halo_for(uint32_t max_len) {
   return (h + 63) / 64 * 64;
 }
 
-static uint32_t scan_lds_bytes(uint32_t block, uint32_t D, uint32_t halo) {
-  return 4u * ((1u << (2 * D)) / 32 + (block / 64) * wave_words(halo));
+// Image words the scan kernel copies for depth D with `levels` trie levels
+// (lds_trie) or the bare filter bitmap (otherwise).
+static uint32_t image_words(const HostTable& h, uint32_t D, bool lds_trie, uint32_t levels) {
+  const uint32_t bits = (1u << (2 * D)) / 32;
+  if (!lds_trie) return bits;
+  if (levels == 0) return bits + bits / 4;
+  return h.image[D].upto[levels - 1];
+}
+
+static uint32_t scan_lds_bytes(uint32_t block, uint32_t img_words, uint32_t halo) {
+  return 4u * (img_words + (block / 64) * wave_words(halo));
 }
 
 using ScanFn = void (*)(ScanParams);
@@ -798,6 +1030,7 @@ static ScanFn pick_scan(uint32_t block, bool global) {
   switch (block) {
     case 256: return global ? pfac_scan_kernel<256, true> : pfac_scan_kernel<256, false>;
     case 512: return global ? pfac_scan_kernel<512, true> : pfac_scan_kernel<512, false>;
+    case 768: return global ? pfac_scan_kernel<768, true> : pfac_scan_kernel<768, false>;
     case 1024: return global ? pfac_scan_kernel<1024, true> : pfac_scan_kernel<1024, false>;
     default: return nullptr;
   }
@@ -819,30 +1052,51 @@ static uint32_t auto_depth(const HostTable& h) {
 static int resolve_plan(const pfac_plan* in, const HostTable& h, int dev, pfac_plan* out) {
   const DeviceInfo di = device_info(dev);
   if (!di.ok) return PFAC_E_NODEV;
-  pfac_plan p = in ? *in : pfac_plan{0, 0, 0, 0};
+  pfac_plan p = in ? *in : pfac_plan{0, 0, 0, 0, 0};
   if (p.variant != PFAC_VARIANT_TILED && p.variant != PFAC_VARIANT_GLOBAL) return PFAC_E_ARG;
   const uint32_t halo = halo_for(h.max_len);
   if (p.variant == PFAC_VARIANT_TILED && halo > kMaxHalo) {
     if (in && in->depth) return PFAC_E_ARG;
     p.variant = PFAC_VARIANT_GLOBAL;  // patterns too long to stage a halo in LDS
   }
-  if (p.block == 0) p.block = 512;
-  if (p.block != 256 && p.block != 512 && p.block != 1024) return PFAC_E_ARG;
+  if (p.block == 0) p.block = 1024;
+  if (p.block != 256 && p.block != 512 && p.block != 768 && p.block != 1024) return PFAC_E_ARG;
   if (p.variant == PFAC_VARIANT_GLOBAL) {
     p.depth = 0;
+    p.levels = PFAC_LEVELS_NONE;
     *out = p;
     return PFAC_OK;
   }
-  if (p.depth == 0) {
-    p.depth = auto_depth(h);
-    while (p.depth > kMinJump &&
-           scan_lds_bytes(p.block, p.depth, halo) > (uint32_t)di.lds_per_block)
-      --p.depth;
+  const uint32_t budget = (uint32_t)di.lds_per_block;
+  const bool auto_d = p.depth == 0;
+  if (auto_d) p.depth = auto_depth(h);
+  for (;;) {
+    if (p.depth < kMinJump || p.depth > kMaxJump) return PFAC_E_ARG;
+    const uint32_t D = p.depth;
+    // with every pattern longer than D, the image can carry rank words and
+    // trie levels; try the most levels asked for that fit, down to rank only
+    if (h.min_len > D && p.levels != PFAC_LEVELS_NONE) {
+      const uint32_t have = h.image[D].levels;
+      const uint32_t want = p.levels == 0 ? have : std::min(p.levels, have);
+      for (int32_t L = (int32_t)want; L >= 0; --L) {
+        if (scan_lds_bytes(p.block, image_words(h, D, true, (uint32_t)L), halo) <= budget) {
+          if (p.levels != 0 && (uint32_t)L < want) return PFAC_E_ARG;   // explicit, too big
+          p.levels = (uint32_t)L;
+          *out = p;
+          return PFAC_OK;
+        }
+      }
+      if (p.levels != 0) return PFAC_E_ARG;
+    }
+    // filter bitmap only; survivors read the global depth-D jump table
+    if (scan_lds_bytes(p.block, image_words(h, D, false, 0), halo) <= budget) {
+      p.levels = PFAC_LEVELS_NONE;
+      *out = p;
+      return PFAC_OK;
+    }
+    if (!auto_d || D == kMinJump) return PFAC_E_ARG;
+    --p.depth;
   }
-  if (p.depth < kMinJump || p.depth > kMaxJump) return PFAC_E_ARG;
-  if (scan_lds_bytes(p.block, p.depth, halo) > (uint32_t)di.lds_per_block) return PFAC_E_ARG;
-  *out = p;
-  return PFAC_OK;
 }
 
 static uint64_t grid_for(ScanFn fn, const pfac_plan& plan, uint32_t lds, int dev,
@@ -870,7 +1124,7 @@ static int launch_scan(const ScanParams& sp, const pfac_plan& plan, int dev, hip
   const bool global = plan.variant == PFAC_VARIANT_GLOBAL;
   ScanFn fn = pick_scan(plan.block, global);
   if (!fn) return PFAC_E_ARG;
-  const uint32_t lds = global ? 0u : scan_lds_bytes(plan.block, sp.D, sp.halo);
+  const uint32_t lds = global ? 0u : scan_lds_bytes(plan.block, sp.image_words, sp.halo);
   const uint64_t grid = grid_for(fn, plan, lds, dev, sp.local_tiles);
   hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(plan.block), lds, stream, sp);
   return hipGetLastError() == hipSuccess ? PFAC_OK : PFAC_E_HIP;
@@ -898,10 +1152,16 @@ static void fill_table(ScanParams& sp, const pfac_table* t, const pfac_plan& pl)
   sp.next = t->dev.next;
   sp.out = t->dev.out;
   if (pl.variant == PFAC_VARIANT_TILED) {
-    sp.D = pl.depth;
-    sp.jump = t->dev.jump[pl.depth];
-    sp.jres = t->dev.jres[pl.depth];
-    sp.bitmap = t->dev.bitmap[pl.depth];
+    const HostTable& h = t->host;
+    const uint32_t D = pl.depth;
+    sp.D = D;
+    sp.jump = t->dev.jump[D];
+    sp.jres = t->dev.jres[D];
+    sp.image = t->dev.image[D];
+    sp.lds_trie = (h.min_len > D && pl.levels != PFAC_LEVELS_NONE) ? 1u : 0u;
+    sp.levels = sp.lds_trie ? pl.levels : 0u;
+    sp.image_words = image_words(h, D, sp.lds_trie, sp.levels);
+    sp.lvl = reinterpret_cast<const u32x4*>(t->dev.levels[D]);
   }
 }
 
@@ -947,11 +1207,22 @@ int pfac_build_table(const char* const* patterns, const uint32_t* lengths, uint3
   uint64_t off = 0;
   const uint64_t o_next = off; off = align(off + h.next.size() * 4);
   const uint64_t o_out = off; off = align(off + h.out.size() * sizeof(OutEntry));
-  uint64_t o_jump[kMaxJump + 1] = {}, o_jres[kMaxJump + 1] = {}, o_bm[kMaxJump + 1] = {};
+  uint64_t o_jump[kMaxJump + 1] = {}, o_jres[kMaxJump + 1] = {}, o_im[kMaxJump + 1] = {};
+  uint64_t o_lv[kMaxJump + 1] = {};
+  std::vector<uint32_t> lvdesc[kMaxJump + 1];
   for (uint32_t D = kMinJump; D <= kMaxJump; ++D) {
     o_jump[D] = off; off = align(off + h.jump[D].size() * 4);
     o_jres[D] = off; off = align(off + h.jres[D].size() * sizeof(OutEntry));
-    o_bm[D] = off; off = align(off + h.bitmap[D].size() * 4);
+    o_im[D] = off; off = align(off + h.image[D].words.size() * 4);
+    lvdesc[D].assign(4 * kImageLevels, 0);
+    for (uint32_t k = 0; k < kImageLevels; ++k) {
+      if (k < h.image[D].levels) {
+        lvdesc[D][4 * k] = h.image[D].byte_off[k];
+        lvdesc[D][4 * k + 1] = h.image[D].pre_off[k];
+      }
+      if (D + k < h.depth_start.size()) lvdesc[D][4 * k + 2] = (uint32_t)h.depth_start[D + k];
+    }
+    o_lv[D] = off; off = align(off + lvdesc[D].size() * 4);
   }
   if (hipMalloc(&t->dmem, off) != hipSuccess) {
     delete t;
@@ -973,10 +1244,12 @@ int pfac_build_table(const char* const* patterns, const uint32_t* lengths, uint3
   for (uint32_t D = kMinJump; D <= kMaxJump; ++D) {
     ok = ok && put(o_jump[D], h.jump[D].data(), h.jump[D].size() * 4) &&
          put(o_jres[D], h.jres[D].data(), h.jres[D].size() * sizeof(OutEntry)) &&
-         put(o_bm[D], h.bitmap[D].data(), h.bitmap[D].size() * 4);
+         put(o_im[D], h.image[D].words.data(), h.image[D].words.size() * 4) &&
+         put(o_lv[D], lvdesc[D].data(), lvdesc[D].size() * 4);
+    v.levels[D] = reinterpret_cast<const uint32_t*>(base + o_lv[D]);
     v.jump[D] = reinterpret_cast<const uint32_t*>(base + o_jump[D]);
     v.jres[D] = reinterpret_cast<const OutEntry*>(base + o_jres[D]);
-    v.bitmap[D] = reinterpret_cast<const uint32_t*>(base + o_bm[D]);
+    v.image[D] = reinterpret_cast<const uint32_t*>(base + o_im[D]);
   }
   if (!ok) {
     (void)hipFree(t->dmem);

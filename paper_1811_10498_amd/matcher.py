@@ -16,6 +16,11 @@ from . import _lib as L
 
 ENCODINGS = {"ascii": L.PFAC_TEXT_ASCII, "2bit": L.PFAC_TEXT_2BIT}
 
+# numpy layout of pfac_text_desc (include/pfac.h)
+DESC_DTYPE = np.dtype([("text_offset", "<u8"), ("n", "<u8"), ("match_offset", "<u8"),
+                       ("table", "<u4"), ("enc", "<u4")])
+assert DESC_DTYPE.itemsize == ctypes.sizeof(L.PfacTextDesc)
+
 
 def _stream_handle(stream) -> Optional[int]:
     if stream is None:
@@ -180,13 +185,13 @@ def match_batch(tables: Sequence[Table], text_base: torch.Tensor, offsets, lengt
             if T else np.zeros(0, dtype=np.uint64)
     total = int(lengths.sum())
     dev = text_base.device
-    descs = (L.PfacTextDesc * max(1, T))()
-    for i in range(T):
-        descs[i].text_offset = int(offsets[i])
-        descs[i].n = int(lengths[i])
-        descs[i].match_offset = int(match_offsets[i])
-        descs[i].table = int(table_index[i])
-        descs[i].enc = int(encs[i])
+    descs = np.zeros(max(1, T), dtype=DESC_DTYPE)
+    if T:
+        descs["text_offset"][:T] = offsets
+        descs["n"][:T] = lengths
+        descs["match_offset"][:T] = match_offsets
+        descs["table"][:T] = table_index
+        descs["enc"][:T] = encs
     if dense and match_out is None:
         match_out = torch.empty(max(1, total), dtype=torch.int32, device=dev)
     cap = (total // 16 + 1024) if hit_cap is None else int(hit_cap)
@@ -195,7 +200,7 @@ def match_batch(tables: Sequence[Table], text_base: torch.Tensor, offsets, lengt
     tabs = (ctypes.c_void_p * len(tables))(*[t.handle.value for t in tables])
     p = _plan_struct(plan)
     rc = tables[0]._lib.pfac_match_batch(
-        ctypes.cast(tabs, ctypes.c_void_p), len(tables), ctypes.cast(descs, ctypes.c_void_p), T,
+        ctypes.cast(tabs, ctypes.c_void_p), len(tables), descs.ctypes.data, T,
         text_base.data_ptr(), match_out.data_ptr() if dense else None,
         h.data_ptr() if h is not None else None, cap if h is not None else 0, c.data_ptr(),
         ctypes.byref(p) if p is not None else None, _stream_handle(stream))

@@ -119,6 +119,32 @@ def test_every_plan_gives_identical_results(plan):
     _check(res, pats, text)
 
 
+LDS_PLANS = [
+    dict(block=256, depth=6, levels=1),
+    dict(block=512, depth=7, levels=2),
+    dict(block=768, depth=8, levels=3),
+    dict(block=1024, depth=9, levels=0),
+    dict(block=1024, depth=9, levels=pf.PFAC_LEVELS_NONE),
+    dict(block=256, depth=10, levels=pf.PFAC_LEVELS_NONE),
+    dict(block=512, depth=6, levels=8),
+]
+
+
+@pytest.mark.parametrize("plan", range(len(LDS_PLANS)))
+def test_lds_trie_levels_give_identical_results(plan):
+    """Patterns longer than the filter depth: the filter bit is a depth-D
+    node found by rank and the walk goes on through the trie levels held in
+    LDS, then the global table."""
+    w = W.plain_workload(1, n=1_500_007, num_patterns=4000)
+    extra = W.cut_patterns(w.text, 200, 11, 14, W.rng(77))      # ends inside LDS levels
+    pats = w.patterns + extra
+    text = w.text.copy()
+    text[5000:5003] = ord("N")
+    print("plan", LDS_PLANS[plan], flush=True)
+    res = _gpu(pats, text, plan=LDS_PLANS[plan])
+    _check(res, pats, text)
+
+
 def test_edge_sizes_and_ragged_tails():
     g = W.rng(32)
     pats = W.random_patterns(100, 1, 10, g) + [b"ACGTACGTACGTACGTACGT"]

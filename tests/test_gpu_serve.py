@@ -1,0 +1,108 @@
+"""GPU tests of the batched and served layers: every request's result is the
+same alone (plain single-text calls) and inside a mixed, overlapping batch,
+and agrees with the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1811_10498_amd as pf  # noqa: E402
+from paper_1811_10498_amd.serve import Request, Server, plain_per_request  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def _requests(count, seed, scale, ntables):
+    reqs = W.served_requests(count, rate_bases_per_s=5e9, seed=seed, num_tries=ntables,
+                             scale=scale)
+    out = []
+    for r in reqs:
+        k = r.kind
+        texts = r.texts()
+        if k == "reads":
+            texts = texts[: max(1, int(len(texts) * scale))]
+        out.append(Request(r.rid, r.trie, texts, r.arrival))
+    return out
+
+
+def test_served_results_match_alone_and_oracle():
+    tries = W.served_tries(seed=4, sizes=[300, 1200, 5000], pool_bases=2_000_000)
+    tables = [pf.Table(t) for t in tries]
+    reqs = _requests(40, seed=4, scale=0.02, ntables=3)
+    srv = Server(tables, budget_bytes=1 << 30, max_inflight=3)
+    stats = srv.run(reqs)
+    print(stats, "max inflight", srv.max_seen_inflight, "dispatch sizes", srv.dispatch_sizes,
+          flush=True)
+    assert stats["requests"] == len(reqs)
+    assert max(srv.dispatch_sizes) > 1          # requests were coalesced
+    for r in srv.done:
+        res = r.result
+        for i, t in enumerate(r.texts):
+            alone = pf.match(tables[r.table], torch.from_numpy(t).to(DEV), hit_cap=t.size + 16)
+            torch.cuda.synchronize()
+            m_mix = res.match[i].cpu().numpy()
+            assert np.array_equal(m_mix, alone.match.cpu().numpy()), (r.rid, i)
+            assert res.num_hits[i] == alone.num_hits() and res.occurrences[i] == alone.total()
+            h_mix = res.hits[res.hits[:, 0] == i][:, 1:].cpu().numpy().astype(np.int64)
+            assert np.array_equal(h_mix, alone.hit_list())
+        if r.rid % 7 == 0:                       # spot-check against the oracle
+            for i, t in enumerate(r.texts[:3]):
+                m_ref, tot = oracle.scan(tries[r.table], t)
+                assert np.array_equal(res.match[i].cpu().numpy(), m_ref)
+                assert res.occurrences[i] == tot
+
+
+def test_budget_limits_admission_under_load():
+    tries = W.served_tries(seed=5, sizes=[500], pool_bases=500_000)
+    tables = [pf.Table(t) for t in tries]
+    reqs = [Request(i, 0, [W.uniform_ascii(200_000, W.rng(100 + i))], 0.0) for i in range(12)]
+    one = reqs[0].device_bytes()
+    srv = Server(tables, budget_bytes=3 * one, max_inflight=4)
+    stats = srv.run(reqs)
+    assert stats["requests"] == 12
+    assert max(srv.dispatch_sizes) <= 3          # never more in flight than the budget allows
+
+
+def test_plain_per_request_baseline_agrees():
+    tries = W.served_tries(seed=6, sizes=[800], pool_bases=500_000)
+    tables = [pf.Table(t) for t in tries]
+    reqs = [Request(i, 0, [W.uniform_ascii(50_000, W.rng(200 + i))], 0.0) for i in range(5)]
+    stats = plain_per_request(tables, reqs)
+    assert stats["requests"] == 5
+
+
+def test_full_size_batch_against_oracle():
+    """The batched workload at full size (4,096 texts, ~200 Mbase, 50,000
+    patterns) in one call, every text compared with the oracle."""
+    wb = W.batch_workload()
+    print("texts", wb.lengths.size, "bases", wb.total_bases, flush=True)
+    tab = pf.Table(wb.patterns)
+    base = torch.from_numpy(wb.buffer).to(DEV)
+    res = pf.match_batch([tab], base, wb.offsets, wb.lengths, hit_cap=wb.total_bases // 16)
+    torch.cuda.synchronize()
+    m = res.match.cpu().numpy()
+    c = res.counters.cpu().numpy()
+    # the oracle scans all texts joined by one non-base byte (walks stop there)
+    sep = np.frombuffer(b"N", dtype=np.uint8)
+    parts, starts = [], []
+    cur = 0
+    for t in range(wb.lengths.size):
+        starts.append(cur)
+        parts.append(wb.text(t))
+        parts.append(sep)
+        cur += int(wb.lengths[t]) + 1
+    joined = np.concatenate(parts)
+    m_ref, _ = oracle.scan(wb.patterns, joined, threads=16)
+    for t in range(wb.lengths.size):
+        L = int(wb.lengths[t])
+        mr = m_ref[starts[t]:starts[t] + L]
+        o = int(res.match_offsets[t])
+        assert np.array_equal(m[o:o + L], mr), t
+        assert c[2 + 2 * t] == np.count_nonzero(mr)
+    assert c[0] == np.count_nonzero(m_ref)

@@ -150,7 +150,7 @@ def test_root_jump_table_is_the_k_step_walk(K):
     for x in range(4 ** K):
         s, best, cnt, alive, fin = 0, 0, 0, True, False
         for d in range(K):
-            e = int(nxt[s, (x >> (2 * d)) & 3])
+            e = int(nxt[s, (x >> (2 * (K - 1 - d))) & 3])
             if e == 0:
                 alive = False
                 break
@@ -180,3 +180,98 @@ def test_state_counts_of_workload_tries():
     w = W.plain_workload(0)
     rc, _, t = host_table(w.patterns)
     assert 2000 < t["S"] < 3500
+
+
+def host_image(patterns, D):
+    lib = _lib()
+    pats = [bytes(p) for p in patterns]
+    bufs = [ctypes.create_string_buffer(p, max(1, len(p))) for p in pats]
+    arr = (ctypes.c_void_p * len(pats))(*[ctypes.addressof(b) for b in bufs])
+    lens = (ctypes.c_uint32 * len(pats))(*[len(p) for p in pats])
+    nw = ctypes.c_uint64(0)
+    bad = ctypes.c_int64(-1)
+    rc = lib.pfac_build_host_image(ctypes.cast(arr, ctypes.c_void_p),
+                                   ctypes.cast(lens, ctypes.c_void_p), len(pats), D, None, 0,
+                                   None, ctypes.byref(nw), ctypes.byref(bad))
+    assert rc == 0
+    words = np.zeros(nw.value, dtype=np.uint32)
+    meta = np.zeros(1 + 3 * 8, dtype=np.uint32)
+    rc = lib.pfac_build_host_image(ctypes.cast(arr, ctypes.c_void_p),
+                                   ctypes.cast(lens, ctypes.c_void_p), len(pats), D,
+                                   words.ctypes.data, nw.value, meta.ctypes.data,
+                                   ctypes.byref(nw), ctypes.byref(bad))
+    assert rc == 0
+    return words, meta
+
+
+@pytest.mark.parametrize("D,npat,lmin,lmax", [(6, 400, 8, 20), (7, 3000, 9, 16), (8, 5000, 10, 24)])
+def test_lds_image_navigation_matches_next_table(D, npat, lmin, lmax):
+    """Rank-based navigation of the LDS image (filter bitmap rank -> level-D
+    node, child-bit counts -> deeper nodes) reaches exactly the states of the
+    breadth-first next-state table."""
+    g = W.rng(60 + D)
+    text = W.uniform_ascii(50_000, g)
+    pats = W.cut_patterns(text, npat // 2, lmin, lmax, g) + W.random_patterns(npat // 2, lmin, lmax, g)
+    _, _, t = host_table(pats)
+    words, meta = host_image(pats, D)
+    levels = int(meta[0])
+    assert levels >= 1
+    nxt = t["next"]
+    bm = words[:4 ** D // 32]
+    pre = words[4 ** D // 32: 4 ** D // 32 + 4 ** D // 128]
+    # depth of every state and the first state of each level (breadth-first)
+    depth = np.zeros(t["S"], dtype=np.int64)
+    for s in range(t["S"]):
+        for a in range(4):
+            e = int(nxt[s, a])
+            if e:
+                depth[e & MASK] = depth[s] + 1
+    first = {int(d): int(np.nonzero(depth == d)[0][0]) for d in np.unique(depth)}
+
+    def byte_of(k, j):
+        w = int(words[int(meta[1 + 3 * k]) + (j >> 2)])
+        return (w >> (8 * (j & 3))) & 0xFF
+
+    def child_index(k, j, c):
+        b = byte_of(k, j)
+        cnt = int(words[int(meta[2 + 3 * k]) + (j >> 4)])
+        for jj in range(j & ~15, j):
+            cnt += bin(byte_of(k, jj) & 15).count("1")
+        return cnt + bin(b & ((1 << c) - 1)).count("1")
+
+    checked = 0
+    for start in range(0, text.size - D - levels, 7):
+        win = text[start:start + D + levels]
+        codes = [b"ACGT".index(bytes([x])) for x in win]
+        x = 0
+        for c in codes[:D]:
+            x = (x << 2) | c
+        # reference: walk the next table
+        s = 0
+        ok = True
+        for c in codes[:D]:
+            e = int(nxt[s, c])
+            if e == 0:
+                ok = False
+                break
+            s = e & MASK
+        bit = (int(bm[x >> 5]) >> (x & 31)) & 1
+        assert bit == int(ok)
+        if not ok:
+            continue
+        j = int(pre[x >> 7]) + sum(bin(int(bm[(x >> 5) & ~3 | w])).count("1") for w in range((x >> 5) & 3))
+        j += bin(int(bm[x >> 5]) & ((1 << (x & 31)) - 1)).count("1")
+        assert first[D] + j == s
+        for k in range(levels - 1):
+            c = codes[D + k]
+            b = byte_of(k, j)
+            assert bool(b & 16) == bool(t["pid"][s])
+            e = int(nxt[s, c])
+            assert bool((b >> c) & 1) == bool(e)
+            if not e:
+                break
+            s = e & MASK
+            j = child_index(k, j, c)
+            assert first[D + k + 1] + j == s
+            checked += 1
+    assert checked > 50
