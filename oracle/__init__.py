@@ -38,6 +38,26 @@ def build(force: bool = True) -> str:
     return _LIB_PATH
 
 
+def build_mutant(k: int, out_dir: str) -> str:
+    """Compile the oracle with planted mistake k (tests only)."""
+    path = os.path.join(out_dir, "liboracle_mutant%d.so" % k)
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread",
+                           "-DORACLE_MUTANT=%d" % k, "-o", path, _SRC])
+    return path
+
+
+def _declare(lib):
+    P = ctypes.c_void_p
+    lib.oracle_scan.argtypes = [P, P, ctypes.c_uint32, P, ctypes.c_uint64, P, P, P]
+    lib.oracle_scan.restype = ctypes.c_int
+    lib.oracle_scan_mt.argtypes = [P, P, ctypes.c_uint32, P, ctypes.c_uint64, P, P, P,
+                                   ctypes.c_int]
+    lib.oracle_scan_mt.restype = ctypes.c_int
+    lib.oracle_goto.argtypes = [P, P, ctypes.c_uint32, P, P, ctypes.c_int64]
+    lib.oracle_goto.restype = ctypes.c_int64
+    return lib
+
+
 def _load():
     global _lib
     with _lock:
@@ -83,14 +103,15 @@ def _as_text(text) -> np.ndarray:
     return t
 
 
-def scan(patterns, text, threads: int = 1):
+def scan(patterns, text, threads: int = 1, lib=None):
     """Run the oracle.  Returns (match int32[n], total occurrences).
 
     ``patterns`` is a sequence of ASCII byte strings (IDs 1..P in order);
     ``text`` is ASCII bytes or a uint8 array.  ``threads`` > 1 uses the
-    chunked multi-threaded scan (identical result).
+    chunked multi-threaded scan (identical result).  ``lib`` selects another
+    build of the same source (the mutation tests).
     """
-    lib = _load()
+    lib = lib or _load()
     arr, lens, keep, num = _pattern_args(patterns)
     t = _as_text(text)
     n = int(t.size)

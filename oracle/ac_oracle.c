@@ -42,6 +42,14 @@
 #include <stdlib.h>
 #include <string.h>
 
+/* ORACLE_MUTANT (tests only): plants one plausible mistake so the pin tests
+ * can show they catch it.  1: no dictionary links; 2: ties go to the larger
+ * ID; 3: start position off by one; 4: non-bases read as 'A'; 5: shortest
+ * pattern wins; 6: failure links never followed. */
+#ifndef ORACLE_MUTANT
+#define ORACLE_MUTANT 0
+#endif
+
 #define OR_OK 0
 #define OR_E_ARG -1
 #define OR_E_PATTERN -2
@@ -56,6 +64,14 @@ static int sym(uint8_t b) {
     case 'T': return 3;
     default: return -1;
   }
+}
+
+static int text_sym(uint8_t b) {
+#if ORACLE_MUTANT == 4
+  return sym(b) < 0 ? 0 : sym(b);
+#else
+  return sym(b);
+#endif
 }
 
 typedef struct {
@@ -172,11 +188,21 @@ static int build_failure(machine *m) {
 /* Record keyword k of length l ending at text index j. */
 static void record(int32_t *match, uint32_t *bestlen, uint64_t *total,
                    uint64_t lo, uint64_t hi, uint64_t j, uint32_t k, uint32_t l) {
+#if ORACLE_MUTANT == 3
+  uint64_t s = j - l + (l > j ? 1 : 0);
+#else
   uint64_t s = j + 1 - l;
+#endif
   if (s < lo || s >= hi) return;
   *total += 1;
   int32_t id = (int32_t)k + 1;
+#if ORACLE_MUTANT == 2
+  if (l > bestlen[s] || (l == bestlen[s] && id > match[s])) {
+#elif ORACLE_MUTANT == 5
+  if (bestlen[s] == 0 || l < bestlen[s]) {
+#else
   if (l > bestlen[s] || (l == bestlen[s] && id < match[s])) {
+#endif
     bestlen[s] = l;
     match[s] = id;
   }
@@ -191,16 +217,24 @@ static void scan_range(const machine *m, const uint8_t *text, uint64_t n,
   if (end > n) end = n;
   int64_t s = 0;
   for (uint64_t j = lo; j < end; ++j) {
-    int a = sym(text[j]);
+    int a = text_sym(text[j]);
     if (a < 0) { s = 0; continue; }          /* no transition: restart at the root */
+#if ORACLE_MUTANT == 6
+    if (s != 0 && m->go[4 * s + a] < 0) s = 0;
+#else
     while (s != 0 && m->go[4 * s + a] < 0) s = m->fail[s];
+#endif
     int64_t nx = m->go[4 * s + a];
     s = nx >= 0 ? nx : 0;
     int64_t t = (m->out_head[s] >= 0) ? s : m->dict[s];
     while (t >= 0) {
       for (int64_t k = m->out_head[t]; k >= 0; k = m->out_next[k])
         record(match, bestlen, total, lo, hi, j, (uint32_t)k, m->kw_len[k]);
+#if ORACLE_MUTANT == 1
+      t = -1;
+#else
       t = m->dict[t];
+#endif
     }
   }
 }
