@@ -170,6 +170,30 @@ int pfac_match_batch(const pfac_table* const* tables, uint32_t num_tables,
                      int32_t* d_match_base, pfac_batch_hit* d_hits, uint64_t hit_cap,
                      uint64_t* d_counters, const pfac_plan* plan, void* stream);
 
+/*
+ * A prepared batch: pfac_batch_create does every host step of
+ * pfac_match_batch once (argument checks, plans, tile numbering, descriptor
+ * upload, scratch allocation; synchronous), and pfac_batch_launch then only
+ * enqueues kernels on `stream` -- no allocation, host copy or memset -- so
+ * it may be captured into a hipGraph and replayed.  The texts' sizes,
+ * offsets, tables and encodings are fixed at creation; the contents of the
+ * buffers passed to each launch may change.  Outputs and their meaning are
+ * those of pfac_match_batch.  A batch owns its scratch: launches of one batch
+ * must be ordered (one stream, or synchronised); different batches are
+ * independent.  pfac_batch_free synchronises the device first.
+ */
+typedef struct pfac_batch pfac_batch;
+
+int pfac_batch_create(const pfac_table* const* tables, uint32_t num_tables,
+                      const pfac_text_desc* descs, uint32_t num_texts, const pfac_plan* plan,
+                      pfac_batch** out);
+
+int pfac_batch_launch(pfac_batch* batch, const void* d_text_base, int32_t* d_match_base,
+                      pfac_batch_hit* d_hits, uint64_t hit_cap, uint64_t* d_counters,
+                      void* stream);
+
+void pfac_batch_free(pfac_batch* batch);
+
 /* The plan the library would use for `table` and a text of n bases (fields
  * filled in, none left 0). */
 int pfac_default_plan(const pfac_table* table, uint64_t n, int enc, pfac_plan* out);

@@ -7,9 +7,9 @@ starting there.  The matching runs in hand-written HIP kernels behind the C
 ABI of include/pfac.h (libpfac.so); this package is the Python binding.
 """
 from ._lib import PFAC_LEVELS_NONE, PFAC_VARIANT_GLOBAL, PFAC_VARIANT_TILED, PfacError, lib
-from .matcher import BatchResult, MatchResult, Table, match, match_batch, n_bases
+from .matcher import Batch, BatchResult, MatchResult, Table, match, match_batch, n_bases
 
 __all__ = [
-    "Table", "match", "match_batch", "MatchResult", "BatchResult", "PfacError", "lib",
+    "Table", "match", "match_batch", "Batch", "MatchResult", "BatchResult", "PfacError", "lib",
     "n_bases", "PFAC_VARIANT_TILED", "PFAC_VARIANT_GLOBAL", "PFAC_LEVELS_NONE",
 ]

@@ -16,7 +16,8 @@ PFAC_LEVELS_NONE = 0xFFFFFFFF
 
 EXPORTS = (
     "pfac_build_table", "pfac_table_info", "pfac_free_table", "pfac_match",
-    "pfac_match_batch", "pfac_default_plan", "pfac_build_host", "pfac_build_host_image", "pfac_strerror",
+    "pfac_match_batch", "pfac_batch_create", "pfac_batch_launch", "pfac_batch_free",
+    "pfac_default_plan", "pfac_build_host", "pfac_build_host_image", "pfac_strerror",
     "pfac_version",
 )
 
@@ -79,6 +80,13 @@ def lib():
             L.pfac_match_batch.argtypes = [P, u32, P, u32, P, P, P, u64, P,
                                            ctypes.POINTER(PfacPlan), P]
             L.pfac_match_batch.restype = ctypes.c_int
+            L.pfac_batch_create.argtypes = [P, u32, P, u32, ctypes.POINTER(PfacPlan),
+                                            ctypes.POINTER(P)]
+            L.pfac_batch_create.restype = ctypes.c_int
+            L.pfac_batch_launch.argtypes = [P, P, P, P, u64, P, P]
+            L.pfac_batch_launch.restype = ctypes.c_int
+            L.pfac_batch_free.argtypes = [P]
+            L.pfac_batch_free.restype = None
             L.pfac_default_plan.argtypes = [P, u64, ctypes.c_int, ctypes.POINTER(PfacPlan)]
             L.pfac_default_plan.restype = ctypes.c_int
             L.pfac_build_host.argtypes = [P, P, u32, P, P, P, u64, u32, P, P, P,

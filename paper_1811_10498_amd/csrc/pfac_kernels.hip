@@ -28,6 +28,7 @@
 
 #include <algorithm>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <utility>
 #include <vector>
@@ -1099,20 +1100,33 @@ static int resolve_plan(const pfac_plan* in, const HostTable& h, int dev, pfac_p
   }
 }
 
-static uint64_t grid_for(ScanFn fn, const pfac_plan& plan, uint32_t lds, int dev,
-                         uint64_t tiles) {
+// Resident workgroups per CU for (kernel, block, LDS bytes), cached: the
+// occupancy query and the LDS attribute are set once per combination.
+static int blocks_per_cu(ScanFn fn, uint32_t block, uint32_t lds) {
+  static std::map<std::tuple<void*, uint32_t, uint32_t>, int> cache;
+  std::lock_guard<std::mutex> lk(g_mu);
+  auto key = std::make_tuple(reinterpret_cast<void*>(fn), block, lds);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  // raise the kernel's dynamic-LDS limit to the largest any plan may ask for,
+  // so that a smaller request later never lowers it below a cached one
   if (lds > 48 * 1024)
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  uint64_t g = plan.grid;
-  if (g == 0) {
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn),
-                                                     (int)plan.block, lds) != hipSuccess ||
-        per_cu < 1)
-      per_cu = 1;
-    g = (uint64_t)per_cu * (uint64_t)device_info(dev).cus;
-  }
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)std::max<uint32_t>(lds, kImageMaxBytes));
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn),
+                                                   (int)block, lds) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  cache[key] = per_cu;
+  return per_cu;
+}
+
+static uint64_t grid_for(ScanFn fn, const pfac_plan& plan, uint32_t lds, int dev,
+                         uint64_t tiles) {
+  const int per_cu = blocks_per_cu(fn, plan.block, lds);
+  uint64_t g = plan.grid ? plan.grid : (uint64_t)per_cu * (uint64_t)device_info(dev).cus;
   const uint64_t waves = plan.block / 64;
   const uint64_t need = (tiles + waves - 1) / waves;
   if (g > need) g = need;
@@ -1344,104 +1358,120 @@ int pfac_match(const pfac_table* t, const void* d_text, uint64_t n, int enc, int
   return launch_tail(ws, tiles, counters, &sc, d_hits != nullptr && hit_cap > 0, stream);
 }
 
-int pfac_match_batch(const pfac_table* const* tables, uint32_t num_tables,
-                     const pfac_text_desc* descs, uint32_t num_texts, const void* d_text_base,
-                     int32_t* d_match_base, pfac_batch_hit* d_hits, uint64_t hit_cap,
-                     uint64_t* d_counters, const pfac_plan* plan, void* stream_) {
-  if (!tables || num_tables == 0 || !d_counters || (num_texts && !descs)) return PFAC_E_ARG;
-  if (d_hits == nullptr) hit_cap = 0;
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return PFAC_E_NODEV;
+}  // extern "C"
+
+namespace pfac {
+
+// Host-side layout of a batch: per-table plans, global tile numbering in
+// text order, per table its texts and their local tile prefixes, and the
+// byte layout of the device copy (descriptors | tile prefix | per table: text
+// list, local prefix | table views).
+struct BatchLayout {
+  std::vector<const pfac_table*> tables;
+  std::vector<pfac_plan> plans;
+  std::vector<DevSeg> segs;
+  std::vector<uint64_t> tile_prefix;
+  std::vector<std::vector<uint32_t>> groups;
+  std::vector<std::vector<uint64_t>> local_prefix;
+  std::vector<uint64_t> o_gs, o_gp;
+  uint64_t o_segs = 0, o_tp = 0, o_tab = 0, bytes = 0, tiles = 0;
+  uint32_t num_texts = 0;
+};
+
+static uint64_t al256(uint64_t x) { return (x + 255) / 256 * 256; }
+
+static int layout_batch(const pfac_table* const* tables, uint32_t num_tables,
+                        const pfac_text_desc* descs, uint32_t num_texts, const pfac_plan* plan,
+                        int dev, BatchLayout* L) {
+  if (!tables || num_tables == 0 || (num_texts && !descs)) return PFAC_E_ARG;
   for (uint32_t i = 0; i < num_tables; ++i)
     if (!tables[i] || tables[i]->device != dev) return PFAC_E_ARG;
   for (uint32_t s = 0; s < num_texts; ++s) {
     const pfac_text_desc& d = descs[s];
     if (d.n >= (1ull << 32) || d.table >= num_tables ||
-        (d.enc != PFAC_TEXT_ASCII && d.enc != PFAC_TEXT_2BIT) || (d.n && !d_text_base))
+        (d.enc != PFAC_TEXT_ASCII && d.enc != PFAC_TEXT_2BIT))
       return PFAC_E_ARG;
   }
-  hipStream_t stream = static_cast<hipStream_t>(stream_);
-  unsigned long long* counters = reinterpret_cast<unsigned long long*>(d_counters);
-  // one launch per table; each table gets its own plan
-  std::vector<pfac_plan> plans(num_tables);
+  L->tables.assign(tables, tables + num_tables);
+  L->plans.resize(num_tables);
   for (uint32_t i = 0; i < num_tables; ++i) {
-    int rc = resolve_plan(plan, tables[i]->host, dev, &plans[i]);
+    const int rc = resolve_plan(plan, tables[i]->host, dev, &L->plans[i]);
     if (rc) return rc;
   }
-  // global tile numbering in text order; per table: its texts and local prefixes
-  std::vector<uint64_t> tile_prefix(num_texts + 1, 0);
+  L->num_texts = num_texts;
+  L->segs.resize(num_texts);
+  if (num_texts) memcpy(L->segs.data(), descs, num_texts * sizeof(DevSeg));
+  L->tile_prefix.assign(num_texts + 1, 0);
   for (uint32_t s = 0; s < num_texts; ++s)
-    tile_prefix[s + 1] = tile_prefix[s] + (descs[s].n + kTile - 1) / kTile;
-  const uint64_t tiles = tile_prefix[num_texts];
-  if (tiles == 0) {
+    L->tile_prefix[s + 1] = L->tile_prefix[s] + (descs[s].n + kTile - 1) / kTile;
+  L->tiles = L->tile_prefix[num_texts];
+  L->groups.assign(num_tables, {});
+  for (uint32_t s = 0; s < num_texts; ++s)
+    if (descs[s].n) L->groups[descs[s].table].push_back(s);
+  L->local_prefix.assign(num_tables, {});
+  L->o_gs.assign(num_tables, 0);
+  L->o_gp.assign(num_tables, 0);
+  uint64_t off = 0;
+  L->o_segs = off; off = al256(off + num_texts * sizeof(DevSeg));
+  L->o_tp = off; off = al256(off + (num_texts + 1) * 8);
+  for (uint32_t g = 0; g < num_tables; ++g) {
+    std::vector<uint64_t>& lp = L->local_prefix[g];
+    lp.assign(L->groups[g].size() + 1, 0);
+    for (size_t i = 0; i < L->groups[g].size(); ++i)
+      lp[i + 1] = lp[i] + (descs[L->groups[g][i]].n + kTile - 1) / kTile;
+    L->o_gs[g] = off; off = al256(off + L->groups[g].size() * 4);
+    L->o_gp[g] = off; off = al256(off + lp.size() * 8);
+  }
+  L->o_tab = off; off = al256(off + num_tables * sizeof(DevTable));
+  L->bytes = off;
+  return PFAC_OK;
+}
+
+static void fill_batch(const BatchLayout& L, uint8_t* host) {
+  memset(host, 0, L.bytes);
+  if (L.num_texts) memcpy(host + L.o_segs, L.segs.data(), L.num_texts * sizeof(DevSeg));
+  memcpy(host + L.o_tp, L.tile_prefix.data(), L.tile_prefix.size() * 8);
+  for (size_t g = 0; g < L.tables.size(); ++g) {
+    if (!L.groups[g].empty())
+      memcpy(host + L.o_gs[g], L.groups[g].data(), L.groups[g].size() * 4);
+    memcpy(host + L.o_gp[g], L.local_prefix[g].data(), L.local_prefix[g].size() * 8);
+  }
+  for (size_t i = 0; i < L.tables.size(); ++i)
+    memcpy(host + L.o_tab + i * sizeof(DevTable), &L.tables[i]->dev, sizeof(DevTable));
+}
+
+// Enqueue the kernels of a batch whose layout is already on the device at
+// db: one scan launch per table, then reduce, scatter and per-text totals.
+// Kernel launches only (no allocation, copy or memset).
+static int enqueue_batch(const BatchLayout& L, const Workspace* ws, const uint8_t* db,
+                         const void* d_text_base, int32_t* d_match_base,
+                         pfac_batch_hit* d_hits, uint64_t hit_cap, unsigned long long* counters,
+                         int dev, hipStream_t stream) {
+  if (L.tiles == 0) {
     hipLaunchKernelGGL(pfac_zero_kernel, dim3(1), dim3(256), 0, stream, counters,
-                       2u + 2u * num_texts);
+                       2u + 2u * L.num_texts);
     return hipGetLastError() == hipSuccess ? PFAC_OK : PFAC_E_HIP;
   }
-  std::vector<std::vector<uint32_t>> groups(num_tables);
-  for (uint32_t s = 0; s < num_texts; ++s)
-    if (descs[s].n) groups[descs[s].table].push_back(s);
-  // device copies: descs | tile_prefix | per group: text list, local prefix | table views
-  auto al = [](uint64_t x) { return (x + 255) / 256 * 256; };
-  uint64_t bytes = al(num_texts * sizeof(DevSeg)) + al((num_texts + 1) * 8);
-  for (uint32_t g = 0; g < num_tables; ++g)
-    bytes += al(groups[g].size() * 4) + al((groups[g].size() + 1) * 8);
-  bytes += al(num_tables * sizeof(DevTable));
-  Workspace* ws = get_workspace(dev, stream);
-  if (!ws) return PFAC_E_NOMEM;
-  int rc;
-  {
-    std::lock_guard<std::mutex> lk(g_mu);
-    rc = ensure_tiles(ws, tiles, stream);
-    if (!rc) rc = ensure_batch(ws, bytes, stream);
-  }
-  if (rc) return rc;
-  uint8_t* host = ws->stage;
-  uint64_t off = 0;
-  auto put = [&](const void* src, uint64_t n) {
-    const uint64_t o = off;
-    if (n) memcpy(host + o, src, n);
-    off = al(off + n);
-    return o;
-  };
-  const uint64_t o_segs = put(descs, num_texts * sizeof(DevSeg));
-  const uint64_t o_tp = put(tile_prefix.data(), (num_texts + 1) * 8);
-  std::vector<uint64_t> o_gs(num_tables), o_gp(num_tables), gtiles(num_tables);
-  for (uint32_t g = 0; g < num_tables; ++g) {
-    std::vector<uint64_t> lp(groups[g].size() + 1, 0);
-    for (size_t i = 0; i < groups[g].size(); ++i)
-      lp[i + 1] = lp[i] + (descs[groups[g][i]].n + kTile - 1) / kTile;
-    gtiles[g] = lp.back();
-    o_gs[g] = put(groups[g].data(), groups[g].size() * 4);
-    o_gp[g] = put(lp.data(), lp.size() * 8);
-  }
-  std::vector<DevTable> views(num_tables);
-  for (uint32_t i = 0; i < num_tables; ++i) views[i] = tables[i]->dev;
-  const uint64_t o_tab = put(views.data(), num_tables * sizeof(DevTable));
-  if (hipMemcpyAsync(ws->batch, host, bytes, hipMemcpyHostToDevice, stream) != hipSuccess ||
-      hipEventRecord(ws->staged, stream) != hipSuccess)
-    return PFAC_E_HIP;
-  ws->staged_pending = true;
-  uint8_t* db = static_cast<uint8_t*>(ws->batch);
-  for (uint32_t g = 0; g < num_tables; ++g) {
-    if (gtiles[g] == 0) continue;
+  for (size_t g = 0; g < L.tables.size(); ++g) {
+    const uint64_t gt = L.local_prefix[g].back();
+    if (gt == 0) continue;
     ScanParams sp;
     memset(&sp, 0, sizeof(sp));
-    fill_table(sp, tables[g], plans[g]);
-    sp.halo = plans[g].variant == PFAC_VARIANT_TILED ? halo_for(tables[g]->host.max_len) : 0;
+    fill_table(sp, L.tables[g], L.plans[g]);
+    sp.halo = L.plans[g].variant == PFAC_VARIANT_TILED ? halo_for(L.tables[g]->host.max_len) : 0;
     sp.single = 0;
-    sp.ngroup = (uint32_t)groups[g].size();
-    sp.segs = reinterpret_cast<const DevSeg*>(db + o_segs);
-    sp.group_segs = reinterpret_cast<const uint32_t*>(db + o_gs[g]);
-    sp.group_prefix = reinterpret_cast<const uint64_t*>(db + o_gp[g]);
-    sp.tile_prefix = reinterpret_cast<const uint64_t*>(db + o_tp);
-    sp.local_tiles = gtiles[g];
+    sp.ngroup = (uint32_t)L.groups[g].size();
+    sp.segs = reinterpret_cast<const DevSeg*>(db + L.o_segs);
+    sp.group_segs = reinterpret_cast<const uint32_t*>(db + L.o_gs[g]);
+    sp.group_prefix = reinterpret_cast<const uint64_t*>(db + L.o_gp[g]);
+    sp.tile_prefix = reinterpret_cast<const uint64_t*>(db + L.o_tp);
+    sp.local_tiles = gt;
     sp.text = static_cast<const uint8_t*>(d_text_base);
     sp.match = d_match_base;
     sp.tile_hits = ws->tile_hits;
     sp.tile_occ = ws->tile_occ;
     sp.slots = d_hits ? ws->slots : nullptr;
-    rc = launch_scan(sp, plans[g], dev, stream);
+    const int rc = launch_scan(sp, L.plans[g], dev, stream);
     if (rc) return rc;
   }
   ScatterParams sc;
@@ -1449,17 +1479,132 @@ int pfac_match_batch(const pfac_table* const* tables, uint32_t num_tables,
   sc.hits = d_hits;
   sc.hit_cap = hit_cap;
   sc.single = 0;
-  sc.nsegs = num_texts;
-  sc.segs = reinterpret_cast<const DevSeg*>(db + o_segs);
-  sc.tile_prefix = reinterpret_cast<const uint64_t*>(db + o_tp);
+  sc.nsegs = L.num_texts;
+  sc.segs = reinterpret_cast<const DevSeg*>(db + L.o_segs);
+  sc.tile_prefix = reinterpret_cast<const uint64_t*>(db + L.o_tp);
   sc.text = static_cast<const uint8_t*>(d_text_base);
   sc.match = d_match_base;
-  sc.tables = reinterpret_cast<const DevTable*>(db + o_tab);
-  rc = launch_tail(ws, tiles, counters, &sc, d_hits != nullptr && hit_cap > 0, stream);
+  sc.tables = reinterpret_cast<const DevTable*>(db + L.o_tab);
+  const int rc = launch_tail(const_cast<Workspace*>(ws), L.tiles, counters, &sc,
+                             d_hits != nullptr && hit_cap > 0, stream);
   if (rc) return rc;
-  hipLaunchKernelGGL(pfac_text_totals_kernel, dim3((num_texts + 3) / 4), dim3(256), 0, stream,
-                     ws->tile_hits, ws->tile_occ, sc.tile_prefix, num_texts, counters + 2);
+  hipLaunchKernelGGL(pfac_text_totals_kernel, dim3((L.num_texts + 3) / 4), dim3(256), 0, stream,
+                     ws->tile_hits, ws->tile_occ, sc.tile_prefix, L.num_texts, counters + 2);
   return hipGetLastError() == hipSuccess ? PFAC_OK : PFAC_E_HIP;
+}
+
+static bool text_base_ok(const BatchLayout& L, const void* d_text_base) {
+  if (d_text_base) return true;
+  for (const DevSeg& d : L.segs)
+    if (d.n) return false;
+  return true;
+}
+
+static void free_workspace(Workspace* ws) {
+  if (ws->mem) (void)hipFree(ws->mem);
+  if (ws->batch) (void)hipFree(ws->batch);
+  if (ws->stage) (void)hipHostFree(ws->stage);
+  if (ws->staged) (void)hipEventDestroy(ws->staged);
+  *ws = Workspace();
+}
+
+}  // namespace pfac
+
+struct pfac_batch {
+  int device = 0;
+  pfac::BatchLayout layout;
+  pfac::Workspace ws;      // owned scratch and device copy of the layout
+};
+
+extern "C" {
+
+int pfac_match_batch(const pfac_table* const* tables, uint32_t num_tables,
+                     const pfac_text_desc* descs, uint32_t num_texts, const void* d_text_base,
+                     int32_t* d_match_base, pfac_batch_hit* d_hits, uint64_t hit_cap,
+                     uint64_t* d_counters, const pfac_plan* plan, void* stream_) {
+  if (!d_counters) return PFAC_E_ARG;
+  if (d_hits == nullptr) hit_cap = 0;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return PFAC_E_NODEV;
+  BatchLayout L;
+  int rc = layout_batch(tables, num_tables, descs, num_texts, plan, dev, &L);
+  if (rc) return rc;
+  if (!text_base_ok(L, d_text_base)) return PFAC_E_ARG;
+  hipStream_t stream = static_cast<hipStream_t>(stream_);
+  unsigned long long* counters = reinterpret_cast<unsigned long long*>(d_counters);
+  if (L.tiles == 0) return enqueue_batch(L, nullptr, nullptr, d_text_base, d_match_base, d_hits,
+                                         hit_cap, counters, dev, stream);
+  Workspace* ws = get_workspace(dev, stream);
+  if (!ws) return PFAC_E_NOMEM;
+  {
+    std::lock_guard<std::mutex> lk(g_mu);
+    rc = ensure_tiles(ws, L.tiles, stream);
+    if (!rc) rc = ensure_batch(ws, L.bytes, stream);
+  }
+  if (rc) return rc;
+  fill_batch(L, ws->stage);
+  if (hipMemcpyAsync(ws->batch, ws->stage, L.bytes, hipMemcpyHostToDevice, stream) !=
+          hipSuccess ||
+      hipEventRecord(ws->staged, stream) != hipSuccess)
+    return PFAC_E_HIP;
+  ws->staged_pending = true;
+  return enqueue_batch(L, ws, static_cast<const uint8_t*>(ws->batch), d_text_base, d_match_base,
+                       d_hits, hit_cap, counters, dev, stream);
+}
+
+int pfac_batch_create(const pfac_table* const* tables, uint32_t num_tables,
+                      const pfac_text_desc* descs, uint32_t num_texts, const pfac_plan* plan,
+                      pfac_batch** out) {
+  if (!out) return PFAC_E_ARG;
+  *out = nullptr;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return PFAC_E_NODEV;
+  pfac_batch* b = new (std::nothrow) pfac_batch();
+  if (!b) return PFAC_E_NOMEM;
+  b->device = dev;
+  int rc = layout_batch(tables, num_tables, descs, num_texts, plan, dev, &b->layout);
+  if (!rc && b->layout.tiles) {
+    rc = ensure_tiles(&b->ws, b->layout.tiles, nullptr);
+    if (!rc) rc = ensure_batch(&b->ws, b->layout.bytes, nullptr);
+    if (!rc) {
+      fill_batch(b->layout, b->ws.stage);
+      if (hipMemcpy(b->ws.batch, b->ws.stage, b->layout.bytes, hipMemcpyHostToDevice) !=
+          hipSuccess)
+        rc = PFAC_E_HIP;
+    }
+  }
+  if (rc) {
+    free_workspace(&b->ws);
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return PFAC_OK;
+}
+
+int pfac_batch_launch(pfac_batch* b, const void* d_text_base, int32_t* d_match_base,
+                      pfac_batch_hit* d_hits, uint64_t hit_cap, uint64_t* d_counters,
+                      void* stream) {
+  if (!b || !d_counters) return PFAC_E_ARG;
+  if (d_hits == nullptr) hit_cap = 0;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return PFAC_E_NODEV;
+  if (dev != b->device || !text_base_ok(b->layout, d_text_base)) return PFAC_E_ARG;
+  return enqueue_batch(b->layout, &b->ws, static_cast<const uint8_t*>(b->ws.batch), d_text_base,
+                       d_match_base, d_hits, hit_cap,
+                       reinterpret_cast<unsigned long long*>(d_counters), dev,
+                       static_cast<hipStream_t>(stream));
+}
+
+void pfac_batch_free(pfac_batch* b) {
+  if (!b) return;
+  int cur = 0;
+  (void)hipGetDevice(&cur);
+  (void)hipSetDevice(b->device);
+  (void)hipDeviceSynchronize();
+  free_workspace(&b->ws);
+  (void)hipSetDevice(cur);
+  delete b;
 }
 
 }  // extern "C"

@@ -162,16 +162,7 @@ class BatchResult:
         return c[2::2], c[3::2]
 
 
-def match_batch(tables: Sequence[Table], text_base: torch.Tensor, offsets, lengths,
-                table_index=None, enc="ascii", dense: bool = True, hits: bool = True,
-                hit_cap: Optional[int] = None, plan=None, stream=None,
-                match_out: Optional[torch.Tensor] = None,
-                match_offsets=None) -> BatchResult:
-    """Match many texts stored in one device buffer in one persistent launch.
-
-    ``offsets`` are byte offsets of each text in ``text_base``, ``lengths``
-    their base counts, ``table_index`` the table of each text (default 0),
-    ``enc`` one encoding name or one per text."""
+def _descriptors(offsets, lengths, table_index, enc, match_offsets):
     offsets = np.asarray(offsets, dtype=np.uint64)
     lengths = np.asarray(lengths, dtype=np.uint64)
     T = int(lengths.size)
@@ -183,8 +174,6 @@ def match_batch(tables: Sequence[Table], text_base: torch.Tensor, offsets, lengt
     if match_offsets is None:
         match_offsets = np.concatenate([[0], np.cumsum(lengths)[:-1]]).astype(np.uint64) \
             if T else np.zeros(0, dtype=np.uint64)
-    total = int(lengths.sum())
-    dev = text_base.device
     descs = np.zeros(max(1, T), dtype=DESC_DTYPE)
     if T:
         descs["text_offset"][:T] = offsets
@@ -192,6 +181,75 @@ def match_batch(tables: Sequence[Table], text_base: torch.Tensor, offsets, lengt
         descs["match_offset"][:T] = match_offsets
         descs["table"][:T] = table_index
         descs["enc"][:T] = encs
+    return descs, T, int(lengths.sum()), np.asarray(match_offsets, dtype=np.uint64)
+
+
+class Batch:
+    """A batch prepared once (``pfac_batch_create``) and launched many times
+    (``pfac_batch_launch``).  A launch only enqueues kernels, so it may run
+    inside ``torch.cuda.graph`` capture.  Text sizes, offsets, tables and
+    encodings are fixed here; ``launch`` writes into the output tensors made
+    here (or given), which the caller reads after the stream has passed."""
+
+    def __init__(self, tables: Sequence[Table], offsets, lengths, table_index=None,
+                 enc="ascii", dense: bool = True, hits: bool = True,
+                 hit_cap: Optional[int] = None, plan=None, device=None,
+                 match_offsets=None):
+        self.tables = list(tables)
+        self._lib = self.tables[0]._lib
+        self.descs, self.num_texts, total, self.match_offsets = _descriptors(
+            offsets, lengths, table_index, enc, match_offsets)
+        dev = torch.device(device or "cuda")
+        self.match = torch.empty(max(1, total), dtype=torch.int32, device=dev) if dense else None
+        self.hit_cap = (total // 16 + 1024) if hit_cap is None else int(hit_cap)
+        self.hits = (torch.empty((self.hit_cap, 3), dtype=torch.int32, device=dev)
+                     if hits else None)
+        self.counters = torch.empty(2 + 2 * self.num_texts, dtype=torch.int64, device=dev)
+        tabs = (ctypes.c_void_p * len(self.tables))(*[t.handle.value for t in self.tables])
+        p = _plan_struct(plan)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(dev):
+            rc = self._lib.pfac_batch_create(
+                ctypes.cast(tabs, ctypes.c_void_p), len(self.tables), self.descs.ctypes.data,
+                self.num_texts, ctypes.byref(p) if p is not None else None, ctypes.byref(h))
+        L.check(rc, "pfac_batch_create")
+        self.handle = h
+
+    def launch(self, text_base: torch.Tensor, stream=None) -> BatchResult:
+        rc = self._lib.pfac_batch_launch(
+            self.handle, text_base.data_ptr(),
+            self.match.data_ptr() if self.match is not None else None,
+            self.hits.data_ptr() if self.hits is not None else None,
+            self.hit_cap if self.hits is not None else 0, self.counters.data_ptr(),
+            _stream_handle(stream))
+        L.check(rc, "pfac_batch_launch")
+        return BatchResult(self.match, self.hits, self.counters, self.match_offsets)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self._lib.pfac_batch_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def match_batch(tables: Sequence[Table], text_base: torch.Tensor, offsets, lengths,
+                table_index=None, enc="ascii", dense: bool = True, hits: bool = True,
+                hit_cap: Optional[int] = None, plan=None, stream=None,
+                match_out: Optional[torch.Tensor] = None,
+                match_offsets=None) -> BatchResult:
+    """Match many texts stored in one device buffer in one persistent launch.
+
+    ``offsets`` are byte offsets of each text in ``text_base``, ``lengths``
+    their base counts, ``table_index`` the table of each text (default 0),
+    ``enc`` one encoding name or one per text."""
+    descs, T, total, match_offsets = _descriptors(offsets, lengths, table_index, enc,
+                                                  match_offsets)
+    dev = text_base.device
     if dense and match_out is None:
         match_out = torch.empty(max(1, total), dtype=torch.int32, device=dev)
     cap = (total // 16 + 1024) if hit_cap is None else int(hit_cap)

@@ -315,3 +315,84 @@ def test_batch_several_tables_and_encodings():
         o = int(res.match_offsets[i])
         assert np.array_equal(m[o:o + L], m_ref), i
         assert c[3 + 2 * i] == total_ref
+
+
+def _batch_check(res, patterns_of, texts, sample):
+    """Per-text oracle check of a batched result on the text indices in `sample`."""
+    m = res.match.cpu().numpy()
+    c = res.counters.cpu().numpy()
+    for t in sample:
+        txt = texts[t]
+        m_ref, total_ref = oracle.scan(patterns_of[t], txt)
+        o = int(res.match_offsets[t])
+        assert np.array_equal(m[o:o + txt.size], m_ref), t
+        assert c[2 + 2 * t] == np.count_nonzero(m_ref) and c[3 + 2 * t] == total_ref, t
+
+
+def test_prepared_batch_replays_in_a_graph():
+    """pfac_batch_launch enqueues kernels only: captured once into a graph, every
+    replay over new text contents (same sizes) matches the eager batched call
+    and the oracle, with eager work and synchronisation between replays."""
+    wb = W.batch_workload(num_texts=120, num_patterns=2000, median=2000.0, hi=40_000, seed=41)
+    g = W.rng(42)
+    sets = [wb.patterns, W.random_patterns(300, 6, 14, g)]
+    tabs = [pf.Table(s) for s in sets]
+    tid = np.arange(wb.lengths.size) % 2
+    base = torch.from_numpy(wb.buffer.copy()).to(DEV)
+    b = pf.Batch(tabs, wb.offsets, wb.lengths, table_index=tid, device=DEV)
+    print("prepared batch: texts=%d bases=%d" % (wb.lengths.size, wb.total_bases), flush=True)
+    res = b.launch(base)
+    torch.cuda.synchronize()
+    ref = pf.match_batch(tabs, base, wb.offsets, wb.lengths, table_index=tid)
+    torch.cuda.synchronize()
+    assert torch.equal(res.match, ref.match) and torch.equal(res.counters, ref.counters)
+    nh = int(ref.counters[0])
+    assert torch.equal(res.hits[:nh], ref.hits[:nh])
+
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        b.launch(base, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        b.launch(base, stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    acgt = np.frombuffer(b"ACGT", dtype=np.uint8)
+    for k in range(3):
+        # new contents: permute the bases (gaps stay), eager copy, then replay
+        perm = g.permutation(4)
+        lut = np.arange(256, dtype=np.uint8)
+        lut[acgt] = acgt[perm]
+        buf = lut[wb.buffer]
+        base.copy_(torch.from_numpy(buf))
+        torch.cuda.synchronize()
+        b.match.fill_(-7)
+        b.counters.fill_(-7)
+        graph.replay()
+        torch.cuda.synchronize()
+        ref = pf.match_batch(tabs, base, wb.offsets, wb.lengths, table_index=tid)
+        torch.cuda.synchronize()
+        assert torch.equal(b.match, ref.match), k
+        assert torch.equal(b.counters, ref.counters), k
+        nh = int(ref.counters[0])
+        assert torch.equal(b.hits[:nh], ref.hits[:nh]), k
+        texts = [buf[int(o):int(o) + int(n)] for o, n in zip(wb.offsets, wb.lengths)]
+        sample = list(range(0, wb.lengths.size, 7))
+        _batch_check(ref, [sets[i] for i in tid], texts, sample)
+    b.close()
+
+
+def test_prepared_batch_empty_and_rejections():
+    tab = pf.Table([b"ACGT"])
+    b = pf.Batch([tab], [0, 16], [0, 0], device=DEV)
+    base = torch.zeros(32, dtype=torch.uint8, device=DEV)
+    res = b.launch(base)
+    torch.cuda.synchronize()
+    assert res.counters.cpu().numpy().tolist() == [0] * 6
+    b.close()
+    with pytest.raises(pf.PfacError):
+        pf.Batch([tab], [0], [5], table_index=[1], device=DEV)
+    with pytest.raises(pf.PfacError):
+        pf.Batch([tab], [0], [5], plan=dict(block=300), device=DEV)

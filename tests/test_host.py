@@ -32,7 +32,8 @@ def test_library_exports_every_declared_symbol():
             src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
             declared |= set(re.findall(r"^\s*(?:const\s+)?[\w ]+\*?\s*\b(pfac_\w+)\s*\(", src,
                                        flags=re.M))
-    assert {"pfac_build_table", "pfac_match", "pfac_match_batch"} <= declared
+    assert {"pfac_build_table", "pfac_match", "pfac_match_batch", "pfac_batch_create",
+            "pfac_batch_launch", "pfac_batch_free"} <= declared
     for sym in sorted(declared):
         assert hasattr(lib, sym), sym
     assert lib.pfac_version().decode().startswith("pfac")
