@@ -98,10 +98,17 @@ typedef struct {
                            PFAC_LEVELS_NONE = filter bitmap only: surviving windows
                            read the global depth-D jump table (always the case when
                            some pattern has D bases or fewer) */
+  uint32_t hash_bits;   /* second filter for the positions that pass the first one,
+                           used when every pattern has more than D bases: their first
+                           K = min(shortest pattern, 16) bases hashed into an LDS
+                           bitmap of 2^hash_bits bits (12..17); only windows whose bit
+                           is set (or that hold a non-base) walk on.  0 = library
+                           choice, PFAC_HASH_NONE = no second filter */
 } pfac_plan;
 
 enum { PFAC_VARIANT_TILED = 0, PFAC_VARIANT_GLOBAL = 1 };
 #define PFAC_LEVELS_NONE 0xFFFFFFFFu
+#define PFAC_HASH_NONE 0xFFFFFFFFu
 
 /* Per-text descriptor of a batched call (all offsets are from the bases the
  * call passes).  A text of ASCII encoding starting at a 16-byte aligned
@@ -238,6 +245,18 @@ int pfac_build_host(const char* const* patterns, const uint32_t* lengths, uint32
 int pfac_build_host_image(const char* const* patterns, const uint32_t* lengths, uint32_t num,
                           uint32_t depth, uint32_t* words, uint64_t cap, uint32_t* meta,
                           uint64_t* num_words, int64_t* bad_index);
+
+/*
+ * Host-only: the second-filter bitmap of 2^bits bits (bits = 12..17) the
+ * scan kernel uses, for inspection and tests.  K = min(shortest pattern, 16);
+ * the key of a K-base window is sum of base_k * 4^(15-k) for k < K (first
+ * base most significant, left-aligned in 32 bits, lower bits 0); its bit is
+ * h = (key * 0x9E3779B1 mod 2^32) >> (32 - bits), and bit h of word h/32 is
+ * set for the first K bases of every pattern.  *k receives K; `words`
+ * (uint32[2^bits / 32], caller-owned) is written when non-NULL.
+ */
+int pfac_build_host_hash(const char* const* patterns, const uint32_t* lengths, uint32_t num,
+                         uint32_t bits, uint32_t* words, uint32_t* k, int64_t* bad_index);
 
 /* Human-readable text of a status code (static storage). */
 const char* pfac_strerror(int status);

@@ -6,10 +6,11 @@ a failure-link-free goto trie over {A,C,G,T} and reports the longest pattern
 starting there.  The matching runs in hand-written HIP kernels behind the C
 ABI of include/pfac.h (libpfac.so); this package is the Python binding.
 """
-from ._lib import PFAC_LEVELS_NONE, PFAC_VARIANT_GLOBAL, PFAC_VARIANT_TILED, PfacError, lib
+from ._lib import (PFAC_HASH_NONE, PFAC_LEVELS_NONE, PFAC_VARIANT_GLOBAL, PFAC_VARIANT_TILED,
+                   PfacError, lib)
 from .matcher import Batch, BatchResult, MatchResult, Table, match, match_batch, n_bases
 
 __all__ = [
     "Table", "match", "match_batch", "Batch", "MatchResult", "BatchResult", "PfacError", "lib",
-    "n_bases", "PFAC_VARIANT_TILED", "PFAC_VARIANT_GLOBAL", "PFAC_LEVELS_NONE",
+    "n_bases", "PFAC_VARIANT_TILED", "PFAC_VARIANT_GLOBAL", "PFAC_LEVELS_NONE", "PFAC_HASH_NONE",
 ]

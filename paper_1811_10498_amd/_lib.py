@@ -13,11 +13,13 @@ PFAC_TEXT_2BIT = 1
 PFAC_VARIANT_TILED = 0
 PFAC_VARIANT_GLOBAL = 1
 PFAC_LEVELS_NONE = 0xFFFFFFFF
+PFAC_HASH_NONE = 0xFFFFFFFF
 
 EXPORTS = (
     "pfac_build_table", "pfac_table_info", "pfac_free_table", "pfac_match",
     "pfac_match_batch", "pfac_batch_create", "pfac_batch_launch", "pfac_batch_free",
-    "pfac_default_plan", "pfac_build_host", "pfac_build_host_image", "pfac_strerror",
+    "pfac_default_plan", "pfac_build_host", "pfac_build_host_image", "pfac_build_host_hash",
+    "pfac_strerror",
     "pfac_version",
 )
 
@@ -25,7 +27,7 @@ EXPORTS = (
 class PfacPlan(ctypes.Structure):
     _fields_ = [("block", ctypes.c_uint32), ("depth", ctypes.c_uint32),
                 ("grid", ctypes.c_uint32), ("variant", ctypes.c_uint32),
-                ("levels", ctypes.c_uint32)]
+                ("levels", ctypes.c_uint32), ("hash_bits", ctypes.c_uint32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -95,6 +97,9 @@ def lib():
             L.pfac_build_host_image.argtypes = [P, P, u32, u32, P, u64, P, ctypes.POINTER(u64),
                                                 ctypes.POINTER(i64)]
             L.pfac_build_host_image.restype = ctypes.c_int
+            L.pfac_build_host_hash.argtypes = [P, P, u32, u32, P, ctypes.POINTER(u32),
+                                               ctypes.POINTER(i64)]
+            L.pfac_build_host_hash.restype = ctypes.c_int
             L.pfac_strerror.argtypes = [ctypes.c_int]
             L.pfac_strerror.restype = ctypes.c_char_p
             L.pfac_version.argtypes = []

@@ -1,6 +1,7 @@
 """Launch-plan autotuner.
 
-A plan (threads per workgroup, filter depth D, trie levels kept in LDS) never
+A plan (threads per workgroup, filter depth D, trie levels kept in LDS, size
+of the second filter) never
 changes results, only speed.  The tuner times every candidate plan the
 library accepts on a sample of the caller's own text and keeps the fastest,
 cached per (table, encoding, size class).  Timing uses HIP events on the
@@ -21,14 +22,16 @@ from .matcher import Table, match, n_bases
 BLOCKS = (256, 512, 768, 1024)
 DEPTHS = (7, 8, 9, 10)
 LEVELS = (0, L.PFAC_LEVELS_NONE)
+HASHES = (0, L.PFAC_HASH_NONE)
 
 
-def candidate_plans(blocks=BLOCKS, depths=DEPTHS, levels=LEVELS) -> List[dict]:
+def candidate_plans(blocks=BLOCKS, depths=DEPTHS, levels=LEVELS, hashes=HASHES) -> List[dict]:
     out = []
     for b in blocks:
         for d in depths:
             for lv in levels:
-                out.append(dict(block=b, depth=d, levels=lv))
+                for hb in hashes:
+                    out.append(dict(block=b, depth=d, levels=lv, hash_bits=hb))
     return out
 
 

@@ -201,6 +201,32 @@ int build_host_table(const char* const* patterns, const uint32_t* lengths, uint3
         im.levels = k + 1;
       }
     }
+    // 6. second filter: hash of the first K bases of every pattern, one
+    //    bitmap per size; a smaller one is the OR of adjacent bits of the
+    //    largest (the hash of `bits` bits is the top bits of the product)
+    out->hash_k = num ? std::min(minl, kHashK) : 0;
+    if (out->hash_k) {
+      std::vector<uint32_t>& big = out->hash[kHashMaxBits];
+      big.assign((1u << kHashMaxBits) / 32, 0);
+      const uint32_t K = out->hash_k;
+      for (uint32_t i = 0; i < num; ++i) {
+        uint32_t key = 0;
+        for (uint32_t k = 0; k < K; ++k)
+          key |= (uint32_t)base_code((uint8_t)patterns[i][k]) << (30 - 2 * k);
+        const uint32_t h = (key * kHashMul) >> (32 - kHashMaxBits);
+        big[h >> 5] |= 1u << (h & 31);
+      }
+      for (uint32_t b = kHashMinBits; b < kHashMaxBits; ++b) {
+        std::vector<uint32_t>& v = out->hash[b];
+        v.assign((1u << b) / 32, 0);
+        const uint32_t fold = kHashMaxBits - b;
+        for (uint32_t h = 0; h < (1u << kHashMaxBits); ++h)
+          if ((big[h >> 5] >> (h & 31)) & 1u) {
+            const uint32_t g = h >> fold;
+            v[g >> 5] |= 1u << (g & 31);
+          }
+      }
+    }
   } catch (const std::bad_alloc&) {
     return PFAC_E_NOMEM;
   }
@@ -258,6 +284,22 @@ extern "C" int pfac_build_host_image(const char* const* patterns, const uint32_t
         meta[3 + 3 * k] = k < im.levels ? im.upto[k] : 0;
       }
     }
+  }
+  return PFAC_OK;
+}
+
+extern "C" int pfac_build_host_hash(const char* const* patterns, const uint32_t* lengths,
+                                    uint32_t num, uint32_t bits, uint32_t* words, uint32_t* k,
+                                    int64_t* bad_index) {
+  using namespace pfac;
+  if (bits < kHashMinBits || bits > kHashMaxBits) return PFAC_E_ARG;
+  HostTable h;
+  int rc = build_host_table(patterns, lengths, num, &h, bad_index);
+  if (rc != PFAC_OK) return rc;
+  if (k) *k = h.hash_k;
+  if (words) {
+    if (h.hash_k) memcpy(words, h.hash[bits].data(), h.hash[bits].size() * sizeof(uint32_t));
+    else memset(words, 0, ((size_t)1 << bits) / 8);
   }
   return PFAC_OK;
 }

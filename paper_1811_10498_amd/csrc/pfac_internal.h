@@ -15,6 +15,14 @@ constexpr uint32_t kMaxJump = 10;
 constexpr uint32_t kImageLevels = 8;      // trie levels an LDS image may hold
 constexpr uint32_t kImageMaxBytes = 160 * 1024;
 
+// Second filter: the first K = min(shortest pattern, kHashK) bases of a
+// window, left-aligned in 32 bits (first base most significant), hashed
+// multiplicatively to `bits` bits (kHashMinBits..kHashMaxBits).
+constexpr uint32_t kHashK = 16;
+constexpr uint32_t kHashMinBits = 12;
+constexpr uint32_t kHashMaxBits = 17;
+constexpr uint32_t kHashMul = 0x9E3779B1u;
+
 // Edge word of the next-state table: child state in bits 0..30 (0 = no edge,
 // the root is never a child), bit 31 set when the child is a final state.
 constexpr uint32_t kFinalBit = 0x80000000u;
@@ -62,6 +70,8 @@ struct HostTable {
     uint32_t upto[kImageLevels];          // image words needed to hold levels D..D+k
   };
   Image image[kMaxJump + 1];
+  uint32_t hash_k = 0;                      // K of the second filter
+  std::vector<uint32_t> hash[kHashMaxBits + 1];   // 2^bits-bit bitmaps
 };
 
 // Host build: validate, insert in input order, renumber breadth-first, pack.
@@ -76,6 +86,7 @@ struct DevTable {
   const OutEntry* jres[kMaxJump + 1];
   const uint32_t* image[kMaxJump + 1];   // LDS image words (HostTable::Image)
   const uint32_t* levels[kMaxJump + 1];  // per image level: {byte_off, pre_off, first state, 0}
+  const uint32_t* hash[kHashMaxBits + 1]; // second-filter bitmaps
   uint32_t num_states;
   uint32_t max_len;
 };

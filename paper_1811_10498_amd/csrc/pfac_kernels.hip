@@ -75,6 +75,12 @@ struct ScanParams {
   const u32x4* lvl;                  // per LDS level: image word offset of its node
                                      // bytes, of its rank words, its first state
   uint32_t D;
+  const uint32_t* hash;           // second-filter bitmap (hash_on)
+  uint32_t hash_on;               // 1: queued windows pass the second filter first
+  uint32_t hash_words;            // its words, copied into LDS after the image
+  uint32_t hash_shift;            // 32 - bits
+  uint32_t hash_kmask;            // key bits of the K-base window (top 2K bits)
+  uint32_t hash_imask;            // invalid bits of the K-base window ((1 << K) - 1)
   uint32_t halo;                  // staged bases past the tile, multiple of 64
   uint32_t single;                // 1: one text (seg0), tiles 0..local_tiles-1
   uint32_t ngroup;                // batch: texts handled by this launch
@@ -97,6 +103,16 @@ __device__ __forceinline__ int ascii_code(uint32_t b) {
   return b == 'A' ? 0 : b == 'C' ? 1 : b == 'G' ? 2 : b == 'T' ? 3 : -1;
 }
 
+// (x << s) | y as one VALU instruction.  Written as an instruction so that
+// the compiler cannot merge a chain of such steps on bit-disjoint operands
+// into a quarter-rate 32-bit multiply.
+template <int S>
+__device__ __forceinline__ uint32_t shl_or(uint32_t x, uint32_t y) {
+  uint32_t r;
+  asm("v_lshl_or_b32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "i"(S), "v"(y));
+  return r;
+}
+
 // Four ASCII bytes -> four 2-bit codes (first byte in the top two bits of
 // the 8-bit result) and a 4-bit "not a base" mask (first byte in bit 0).
 // code = ((b >> 1) ^ (b >> 2)) & 3 maps A,C,G,T to 0,1,2,3; a byte is a base
@@ -107,7 +123,8 @@ __device__ __forceinline__ void ascii4(uint32_t x, uint32_t& code8, uint32_t& in
   const uint32_t t = x ^ expect;
   const uint32_t nz = (((t & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | t) & 0x80808080u;
   inv4 = ((nz >> 7) * 0x01020408u) >> 24;
-  code8 = (cb * 0x40100401u) >> 24;
+  const uint32_t t1 = shl_or<10>(cb, cb);   // as in ascii_chunk
+  code8 = shl_or<20>(t1, t1) >> 24;
 }
 
 __device__ __forceinline__ void wave_sync() {
@@ -135,21 +152,25 @@ __device__ __forceinline__ uint32_t wave_excl(uint32_t v, uint32_t* total) {
   return inc - v;
 }
 
-// Exclusive prefix over the 64 lanes of a value below 2^BITS, without LDS:
-// each bit plane is a ballot, and a lane counts the set bits of the lanes
-// below it (mbcnt).  *total receives the wave sum.
-template <int BITS>
-__device__ __forceinline__ uint32_t wave_excl_small(uint32_t v, uint32_t* total) {
-  uint32_t pre = 0, tot = 0;
-  #pragma unroll
-  for (int k = 0; k < BITS; ++k) {
-    const uint64_t m = __ballot((v >> k) & 1u);
-    pre += __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u)) << k;
-    tot += (uint32_t)__popcll(m) << k;
-  }
-  *total = tot;
-  return pre;
+// Inclusive prefix sum over the 64 lanes with DPP lane moves (no LDS): lane
+// shifts of 1, 2, 4 and 8 within each row of 16 lanes, then the running total
+// of lane 15 carried into rows 1 and 3 and that of lane 31 into rows 2 and 3.
+// Every lane of the wave must be active.
+__device__ __forceinline__ uint32_t wave_incl_dpp(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);  // row_shr:1
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);  // row_shr:2
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);  // row_shr:4
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);  // row_shr:8
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);  // row_bcast:31
+  return v;
+}
+
+// Exclusive prefix over the 64 lanes; *total receives the wave sum (uniform).
+__device__ __forceinline__ uint32_t wave_excl_dpp(uint32_t v, uint32_t* total) {
+  const uint32_t inc = wave_incl_dpp(v);
+  *total = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
+  return inc - v;
 }
 
 // One base of a text in global memory (out of range = invalid).
@@ -221,7 +242,7 @@ __device__ __forceinline__ uint32_t children_before(const u32x4& g, uint32_t t) 
 // Every route ends in the same global-table loop.
 __device__ __forceinline__ int32_t deep_walk(uint32_t e, uint32_t D, uint32_t lds_trie,
                                              uint32_t levels, const uint32_t* lds,
-                                             const uint32_t* bmpre, const u32x4* __restrict__ lvl,
+                                             const uint32_t* bmpre, const u32x4* lvl,
                                              const uint32_t* __restrict__ pk,
                                              const uint32_t* __restrict__ iv,
                                              const uint32_t* __restrict__ next,
@@ -283,6 +304,26 @@ __device__ __forceinline__ int32_t deep_walk(uint32_t e, uint32_t D, uint32_t ld
   return best;
 }
 
+// Second filter for one queued entry (see deep_walk for the entry format):
+// true when the walk must go on -- the window holds a non-base within its
+// first K bases, or the hash of its first K bases has its bit set.  A window
+// whose first K bases are no pattern's first K bases can only fail the test
+// (every pattern has at least K bases), so a cleared bit proves the walk
+// reports nothing.
+__device__ __forceinline__ bool hash_pass(uint32_t e, const uint32_t* __restrict__ pk,
+                                          const uint32_t* __restrict__ iv,
+                                          const uint32_t* __restrict__ hl, uint32_t kmask,
+                                          uint32_t imask, uint32_t shift) {
+  if (e & 0x8000u) return true;
+  const uint32_t qt = e & 0x7FFFu;
+  if (__builtin_amdgcn_alignbit(iv[(qt >> 5) + 1], iv[qt >> 5], qt & 31u) & imask) return true;
+  const uint32_t wi = qt >> 4;
+  const uint32_t key =
+      (uint32_t)(((((uint64_t)pk[wi] << 32) | pk[wi + 1]) << (2 * (qt & 15u))) >> 32) & kmask;
+  const uint32_t h = (key * kHashMul) >> shift;
+  return (hl[h >> 5] >> (h & 31u)) & 1u;
+}
+
 // Text of one wave tile: bases [t0, t0+span) of one text, span = kTile + halo.
 // Staged into the wave's LDS area as 2-bit codes, 16 per word with the first
 // base in the top bits (a window of bases then reads as a key with its first
@@ -299,32 +340,44 @@ struct TextRef {
 };
 
 struct Prefetch {
-  u32x4 a, b;          // chunks lane and lane+64
-  uint32_t fast;       // bit 0: a loaded, bit 1: b loaded
+  u32x4 a, b;          // ASCII: the lane's 16-byte chunk of the tile (a);
+                       // 2-bit: chunks lane and lane+64 (a, b)
+  uint32_t h;          // ASCII: the lane's 4-byte piece of the halo
+  uint32_t fast;       // bit 0: a loaded, bit 1: b loaded, bit 2: h loaded
 };
 
-__device__ __forceinline__ uint32_t stage_chunks(uint32_t enc, uint32_t span) {
-  return enc == PFAC_TEXT_ASCII ? span / 16 : span / 64;   // 16-byte chunks
-}
-
-__device__ __forceinline__ Prefetch fetch(const TextRef& r, uint32_t span) {
+__device__ __forceinline__ Prefetch fetch(const TextRef& r, uint32_t halo) {
   const uint32_t lane = threadIdx.x & 63;
-  const uint32_t nch = stage_chunks(r.enc, span);
-  const uint32_t per = r.enc == PFAC_TEXT_ASCII ? 16u : 64u;   // bases per chunk
-  const bool aligned = ((reinterpret_cast<uintptr_t>(r.t) & 15) == 0);
+  const uintptr_t addr = reinterpret_cast<uintptr_t>(r.t);
   Prefetch f;
   f.fast = 0;
   f.a = u32x4{0, 0, 0, 0};
   f.b = u32x4{0, 0, 0, 0};
-  const uint64_t ga = r.t0 + (uint64_t)per * lane;
-  if (aligned && lane < nch && ga + per <= r.n) {
-    f.a = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(r.t + ga * 16 / per));
-    f.fast |= 1u;
-  }
-  const uint64_t gb = ga + (uint64_t)per * 64;
-  if (aligned && lane + 64 < nch && gb + per <= r.n) {
-    f.b = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(r.t + gb * 16 / per));
-    f.fast |= 2u;
+  f.h = 0;
+  if (r.enc == PFAC_TEXT_ASCII) {
+    const uint64_t ga = r.t0 + 16ull * lane;
+    if ((addr & 15) == 0 && ga + 16 <= r.n) {
+      f.a = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(r.t + ga));
+      f.fast |= 1u;
+    }
+    const uint64_t gh = r.t0 + kTile + 4ull * lane;
+    if ((addr & 3) == 0 && lane < halo / 4 && gh + 4 <= r.n) {
+      f.h = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(r.t + gh));
+      f.fast |= 4u;
+    }
+  } else {
+    const uint32_t nch = (kTile + halo) / 64;   // 64 bases per 16-byte chunk
+    const bool al = (addr & 15) == 0;
+    const uint64_t ga = r.t0 + 64ull * lane;
+    if (al && lane < nch && ga + 64 <= r.n) {
+      f.a = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(r.t + ga / 4));
+      f.fast |= 1u;
+    }
+    const uint64_t gb = ga + 64ull * 64;
+    if (al && lane + 64 < nch && gb + 64 <= r.n) {
+      f.b = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(r.t + gb / 4));
+      f.fast |= 2u;
+    }
   }
   return f;
 }
@@ -338,9 +391,16 @@ __device__ __forceinline__ void ascii_chunk(const u32x4& v, uint32_t& packed, ui
     cb[k] = ((w[k] >> 1) ^ (w[k] >> 2)) & 0x03030303u;
     t[k] = w[k] ^ __builtin_amdgcn_perm(0u, 0x54474341u, cb[k]);   // 0 where a base
   }
-  packed = 0;
+  // code byte of word k (first base in the top bits) in bits 24..31 of
+  // top[k]: cb | cb << 10 | cb << 20 | cb << 30, no two terms overlap there
+  uint32_t top[4];
   #pragma unroll
-  for (int k = 0; k < 4; ++k) packed |= ((cb[k] * 0x40100401u) >> 24) << (24 - 8 * k);
+  for (int k = 0; k < 4; ++k) {
+    const uint32_t t1 = shl_or<10>(cb[k], cb[k]);
+    top[k] = shl_or<20>(t1, t1);
+  }
+  packed = __builtin_amdgcn_perm(top[0], top[1], 0x07030C0Cu) |
+           __builtin_amdgcn_perm(top[2], top[3], 0x0C0C0703u);
   inv = 0;
   if ((t[0] | t[1] | t[2] | t[3]) != 0) {
     #pragma unroll
@@ -351,63 +411,96 @@ __device__ __forceinline__ void ascii_chunk(const u32x4& v, uint32_t& packed, ui
   }
 }
 
-__device__ __forceinline__ void commit_chunk(const TextRef& r, uint32_t c, bool loaded,
-                                             const u32x4& v, uint32_t* pk, uint32_t* iv) {
+// ASCII bytes [g, g+16) of the text (misaligned or crossing its end: byte
+// loads, 0 past the end, which reads as a non-base).
+__device__ __forceinline__ u32x4 gather16(const TextRef& r, uint64_t g) {
+  uint32_t w[4];
+  #pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    uint32_t y = 0;
+    #pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const uint64_t q = g + 4 * k + b;
+      y |= (uint32_t)(q < r.n ? r.t[q] : 0u) << (8 * b);
+    }
+    w[k] = y;
+  }
+  return u32x4{w[0], w[1], w[2], w[3]};
+}
+
+__device__ __forceinline__ uint32_t gather4(const TextRef& r, uint64_t g) {
+  uint32_t y = 0;
+  #pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const uint64_t q = g + b;
+    y |= (uint32_t)(q < r.n ? r.t[q] : 0u) << (8 * b);
+  }
+  return y;
+}
+
+// 2-bit chunk c (64 bases) -> four code words and 64 invalid bits.
+__device__ __forceinline__ void commit_2bit_chunk(const TextRef& r, uint32_t c, bool loaded,
+                                                  const u32x4& v, uint32_t* pk, uint32_t* iv) {
   uint16_t* iv16 = reinterpret_cast<uint16_t*>(iv);
-  if (r.enc == PFAC_TEXT_ASCII) {
-    u32x4 x = v;
-    if (!loaded) {              // misaligned text or a chunk crossing its end
-      const uint64_t g = r.t0 + 16ull * c;
-      uint32_t w[4];
-      #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        uint32_t y = 0;
-        #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const uint64_t q = g + 4 * k + b;
-          y |= (uint32_t)(q < r.n ? r.t[q] : 0u) << (8 * b);
-        }
-        w[k] = y;
-      }
-      x = u32x4{w[0], w[1], w[2], w[3]};
-    }
-    uint32_t packed, inv;
-    ascii_chunk(x, packed, inv);
-    pk[c] = packed;
-    iv16[c] = (uint16_t)inv;
-  } else {
-    uint32_t w[4] = {v.x, v.y, v.z, v.w};
-    uint32_t inv[4] = {0, 0, 0, 0};
-    if (!loaded) {
-      const uint64_t g = r.t0 + 64ull * c;
-      #pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        uint32_t y = 0, m = 0;
-        for (int b = 0; b < 16; ++b) {
-          const uint64_t q = g + 16 * k + b;
-          if (q < r.n) y |= (uint32_t)((r.t[q >> 2] >> (2 * (q & 3))) & 3u) << (2 * b);
-          else m |= 1u << b;
-        }
-        w[k] = y;
-        inv[k] = m;
-      }
-    }
+  uint32_t w[4] = {v.x, v.y, v.z, v.w};
+  uint32_t inv[4] = {0, 0, 0, 0};
+  if (!loaded) {
+    const uint64_t g = r.t0 + 64ull * c;
     #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      // base b sits in bits 2b..2b+1: reverse the order of the 2-bit fields
-      const uint32_t rv = __builtin_bitreverse32(w[k]);
-      pk[4 * c + k] = ((rv >> 1) & 0x55555555u) | ((rv & 0x55555555u) << 1);
-      iv16[4 * c + k] = (uint16_t)inv[k];
+      uint32_t y = 0, m = 0;
+      for (int b = 0; b < 16; ++b) {
+        const uint64_t q = g + 16 * k + b;
+        if (q < r.n) y |= (uint32_t)((r.t[q >> 2] >> (2 * (q & 3))) & 3u) << (2 * b);
+        else m |= 1u << b;
+      }
+      w[k] = y;
+      inv[k] = m;
     }
+  }
+  #pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    // base b sits in bits 2b..2b+1: reverse the order of the 2-bit fields
+    const uint32_t rv = __builtin_bitreverse32(w[k]);
+    pk[4 * c + k] = ((rv >> 1) & 0x55555555u) | ((rv & 0x55555555u) << 1);
+    iv16[4 * c + k] = (uint16_t)inv[k];
   }
 }
 
-__device__ __forceinline__ void commit(const TextRef& r, uint32_t span, const Prefetch& f,
+// Convert the prefetched text of a tile into the wave's LDS area.  ASCII:
+// every lane converts its 16-byte chunk of the tile; the halo is converted
+// in 4-byte pieces, one per lane (one byte of codes and four invalid bits
+// each; two neighbouring lanes join their invalid bits into one byte).
+__device__ __forceinline__ void commit(const TextRef& r, uint32_t halo, const Prefetch& f,
                                        uint32_t* pk, uint32_t* iv) {
   const uint32_t lane = threadIdx.x & 63;
-  const uint32_t nch = stage_chunks(r.enc, span);
-  if (lane < nch) commit_chunk(r, lane, f.fast & 1u, f.a, pk, iv);
-  if (lane + 64 < nch) commit_chunk(r, lane + 64, f.fast & 2u, f.b, pk, iv);
+  const uint32_t span = kTile + halo;
+  if (r.enc == PFAC_TEXT_ASCII) {
+    uint32_t packed, inv;
+    ascii_chunk((f.fast & 1u) ? f.a : gather16(r, r.t0 + 16ull * lane), packed, inv);
+    pk[lane] = packed;
+    reinterpret_cast<uint16_t*>(iv)[lane] = (uint16_t)inv;
+    uint8_t* pk8 = reinterpret_cast<uint8_t*>(pk);
+    uint8_t* iv8 = reinterpret_cast<uint8_t*>(iv);
+    const uint32_t npieces = halo / 4;
+    for (uint32_t p0 = 0; p0 < npieces; p0 += 64) {
+      const uint32_t pc = p0 + lane;
+      const uint32_t v = (p0 == 0 && (f.fast & 4u)) ? f.h : gather4(r, r.t0 + kTile + 4ull * pc);
+      uint32_t code8, inv4;
+      ascii4(v, code8, inv4);
+      // invalid bits of lane ^ 1 (quad permutation 1,0,3,2)
+      const uint32_t other = (uint32_t)__builtin_amdgcn_mov_dpp((int)inv4, 0xB1, 0xF, 0xF, false);
+      if (pc < npieces) {
+        // bases kTile+4pc .. +3: byte 3 - (pc & 3) of code word kTile/16 + pc/4
+        pk8[4 * (kTile / 16 + (pc >> 2)) + 3 - (pc & 3)] = (uint8_t)code8;
+        if (!(pc & 1u)) iv8[(kTile + 4 * pc) / 8] = (uint8_t)(inv4 | (other << 4));
+      }
+    }
+  } else {
+    const uint32_t nch = span / 64;
+    if (lane < nch) commit_2bit_chunk(r, lane, f.fast & 1u, f.a, pk, iv);
+    if (lane + 64 < nch) commit_2bit_chunk(r, lane + 64, f.fast & 2u, f.b, pk, iv);
+  }
   if (lane < 2) {
     pk[span / 16 + lane] = 0;
     iv[span / 32 + lane] = 0xFFFFFFFFu;
@@ -416,7 +509,8 @@ __device__ __forceinline__ void commit(const TextRef& r, uint32_t span, const Pr
 
 // LDS of one wave, in 32-bit words, each part a multiple of 4 words so the
 // 16-byte LDS accesses stay aligned: text codes (+2 sentinel words), invalid
-// bits (+2), deep-walk results and deep-walk queue (16-bit entries).
+// bits (+2), deep-walk results, deep-walk queue and the list of queue entries
+// that pass the second filter (16-bit entries).
 __host__ __device__ constexpr uint32_t round4(uint32_t x) { return (x + 3) & ~3u; }
 __host__ __device__ constexpr uint32_t pk_words(uint32_t halo) {
   return round4((kTile + halo) / 16 + 2);
@@ -424,8 +518,12 @@ __host__ __device__ constexpr uint32_t pk_words(uint32_t halo) {
 __host__ __device__ constexpr uint32_t iv_words(uint32_t halo) {
   return round4((kTile + halo) / 32 + 2);
 }
+// LDS of one wave of the global-memory variant: results and queue.
+constexpr uint32_t kGlobalWaveWords = kQueue + kQueue / 2;
+// Trie-level descriptors copied into LDS after the image and the second filter.
+constexpr uint32_t kLvlWords = 4 * kImageLevels;
 __host__ __device__ constexpr uint32_t wave_words(uint32_t halo) {
-  return pk_words(halo) + iv_words(halo) + kQueue + kQueue / 2;
+  return pk_words(halo) + iv_words(halo) + kQueue + kQueue / 2 + kQueue / 2;
 }
 
 struct TileLoc {
@@ -434,9 +532,10 @@ struct TileLoc {
   uint64_t gtile;   // tile index in the call
 };
 
+template <bool SINGLE>
 __device__ __forceinline__ TileLoc locate(const ScanParams& p, uint64_t lt) {
   TileLoc L;
-  if (p.single) {
+  if (SINGLE) {
     L.seg = p.seg0;
     L.ts = lt;
     L.gtile = lt;
@@ -459,44 +558,67 @@ __device__ __forceinline__ TileLoc locate(const ScanParams& p, uint64_t lt) {
 // q = g*256 + 4*lane + r.  Positions whose walk goes on past the filter are
 // queued and walked by all lanes together; their results come back through
 // a result slot per queue entry.
-template <int BLOCK, bool GLOBAL>
+template <int BLOCK, bool GLOBAL, int DT, bool SINGLE>
 __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
   extern __shared__ uint32_t lds[];
-  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const uint32_t D = GLOBAL ? 0u : p.D;
+  // the wave index is uniform across the wave: keep it (and every tile
+  // index and text offset derived from it) in scalar registers
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  constexpr uint32_t D = GLOBAL ? 0u : (uint32_t)DT;   // filter depth (compile time)
   const uint32_t img_words = GLOBAL ? 0u : p.image_words;
   uint32_t* bm = lds;                             // image: filter bitmap first
   const uint32_t* bmpre = lds + (GLOBAL ? 0u : (1u << (2 * D)) / 32);
-  __shared__ int32_t g_res[GLOBAL ? BLOCK / 64 * kQueue : 1];
-  __shared__ uint16_t g_queue[GLOBAL ? BLOCK / 64 * kQueue : 1];
-  const uint32_t span = kTile + p.halo;
-  uint32_t* pk = lds + img_words + wave * (GLOBAL ? 0u : wave_words(p.halo));
-  uint32_t* iv = pk + pk_words(p.halo);
-  int32_t* res = reinterpret_cast<int32_t*>(iv + iv_words(p.halo));
-  uint16_t* queue = reinterpret_cast<uint16_t*>(res + kQueue);
+  // all LDS is dynamic (no static arrays), so its base is the constant 0
+  const bool hashed = !GLOBAL && p.hash_on;
+  const uint32_t* hl = lds + img_words;           // second-filter bitmap
+  uint32_t* pk = nullptr;
+  uint32_t* iv = nullptr;
+  int32_t* res;
+  uint16_t* queue;
+  uint16_t* queue2 = nullptr;
   if (GLOBAL) {
-    res = g_res + wave * kQueue;
-    queue = g_queue + wave * kQueue;
+    res = reinterpret_cast<int32_t*>(lds + wave * kGlobalWaveWords);
+    queue = reinterpret_cast<uint16_t*>(res + kQueue);
+  } else {
+    pk = lds + img_words + (hashed ? p.hash_words : 0u) + kLvlWords + wave * wave_words(p.halo);
+    iv = pk + pk_words(p.halo);
+    res = reinterpret_cast<int32_t*>(iv + iv_words(p.halo));
+    queue = reinterpret_cast<uint16_t*>(res + kQueue);
+    queue2 = queue + kQueue;
   }
 
   if (!GLOBAL) {
     const u32x4* src = reinterpret_cast<const u32x4*>(p.image);
     u32x4* dst = reinterpret_cast<u32x4*>(bm);
     for (uint32_t i = threadIdx.x; i < img_words / 4; i += BLOCK) dst[i] = src[i];
+    if (hashed) {
+      const u32x4* hs = reinterpret_cast<const u32x4*>(p.hash);
+      u32x4* hd = reinterpret_cast<u32x4*>(bm + img_words);
+      for (uint32_t i = threadIdx.x; i < p.hash_words / 4; i += BLOCK) hd[i] = hs[i];
+    }
+    if (p.lds_trie && threadIdx.x < kLvlWords / 4)
+      reinterpret_cast<u32x4*>(bm + img_words + (hashed ? p.hash_words : 0u))[threadIdx.x] =
+          p.lvl[threadIdx.x];
     __syncthreads();
   }
+  const u32x4* lvl = reinterpret_cast<const u32x4*>(lds + img_words +
+                                                    (hashed ? p.hash_words : 0u));
 
   const uint32_t dmask = (1u << D) - 1u;
   const uint32_t gmask = (1u << (D + 3)) - 1u;   // bases of the 4 windows of a group
-  const uint32_t sh8 = 8u * (lane & 3u);          // bits before the lane's group in its word
+  // byte selector of the 4 bases the lane's group starts at within a pair of
+  // code words {first, second}: bytes 7-k .. 4-k of the pair, k = lane & 3
+  const uint32_t k8 = lane & 3u;
+  const uint32_t bsel = ((7u - k8) << 24) | ((6u - k8) << 16) | ((5u - k8) << 8) | (4u - k8);
   const uint32_t sh4 = 4u * (lane & 7u);          // its bit in the invalid-bit word
   const uint64_t nwaves = (uint64_t)gridDim.x * (BLOCK / 64);
   uint64_t lt = (uint64_t)blockIdx.x * (BLOCK / 64) + wave;
   if (lt >= p.local_tiles) return;
-  TileLoc cur = locate(p, lt);
+  TileLoc cur = locate<SINGLE>(p, lt);
   Prefetch pf{};
   if (!GLOBAL)
-    pf = fetch(TextRef{p.text + cur.seg.text_off, cur.seg.n, cur.ts * kTile, cur.seg.enc}, span);
+    pf = fetch(TextRef{p.text + cur.seg.text_off, cur.seg.n, cur.ts * kTile, cur.seg.enc}, p.halo);
 
   for (;;) {
     const uint64_t t0 = cur.ts * kTile;
@@ -510,7 +632,7 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
     const bool maligned = mt && ((reinterpret_cast<uintptr_t>(mt) & 15) == 0);
 
     if (!GLOBAL) {
-      commit(TextRef{text, n, t0, enc}, span, pf, pk, iv);
+      commit(TextRef{text, n, t0, enc}, p.halo, pf, pk, iv);
       wave_sync();
     }
     // next tile: locate it and start loading its text now
@@ -518,10 +640,10 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
     const bool more = lt_next < p.local_tiles;
     TileLoc nxt = cur;
     if (more) {
-      nxt = locate(p, lt_next);
+      nxt = locate<SINGLE>(p, lt_next);
       if (!GLOBAL)
         pf = fetch(TextRef{p.text + nxt.seg.text_off, nxt.seg.n, nxt.ts * kTile, nxt.seg.enc},
-                   span);
+                   p.halo);
     }
 
     // ---- classify the lane's 16 positions: bit 4g+r of want / slow
@@ -537,12 +659,16 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
       } else {
         const uint32_t wi = q0 >> 4, ii = q0 >> 5;
         // 16 bases from q0, first base in the top bits
-        const uint32_t w = (uint32_t)((((uint64_t)pk[wi] << 32) | pk[wi + 1]) << sh8 >> 32);
+        const uint32_t w = __builtin_amdgcn_perm(pk[wi], pk[wi + 1], bsel);
         const uint32_t inv = __builtin_amdgcn_alignbit(iv[ii + 1], iv[ii], sh4);
         #pragma unroll
         for (uint32_t r = 0; r < 4; ++r) {
-          const uint32_t x = __builtin_amdgcn_ubfe(w, 32 - 2 * r - 2 * D, 2 * D);
-          m4 |= __builtin_amdgcn_ubfe(bm[x >> 5], x & 31u, 1u) << r;
+          // window key x = bits [o, o+2D) of w: its bitmap word is bits
+          // [o+5, o+2D) and its bit within the word bits [o, o+5) (a bit-field
+          // offset uses the low 5 bits of its operand)
+          const uint32_t o = 32 - 2 * r - 2 * D;
+          const uint32_t word = bm[__builtin_amdgcn_ubfe(w, o + 5, 2 * D - 5)];
+          m4 |= __builtin_amdgcn_ubfe(word, w >> o, 1u) << r;
         }
         if (inv & gmask) {
           // a window holds a non-base: such positions walk from the root
@@ -564,13 +690,13 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
     unsigned long long occ = 0;
     uint32_t tile_hits = 0;
     uint32_t total;
-    const uint32_t base = wave_excl_small<5>(__builtin_popcount(want), &total);
+    const uint32_t base = wave_excl_dpp(__builtin_popcount(want), &total);
     const uint32_t passes = total <= kQueue ? 1u : 4u;
     for (uint32_t pass = 0; pass < passes; ++pass) {
       const uint32_t sel = passes == 1 ? 0xFFFFu : (0xFu << (4 * pass));
       const uint32_t wsel = want & sel;
       uint32_t pbase = base, ptotal = total;
-      if (passes != 1) pbase = wave_excl_small<5>(__builtin_popcount(wsel), &ptotal);
+      if (passes != 1) pbase = wave_excl_dpp(__builtin_popcount(wsel), &ptotal);
       {
         uint32_t m = wsel, k = pbase;
         while (m) {
@@ -581,26 +707,67 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
         }
       }
       wave_sync();
-      // ---- walk the queued positions with all lanes
+      // ---- second filter: queue entries that must walk on, listed in queue2
+      uint32_t nwalk = ptotal;
+      if (hashed) {
+        nwalk = 0;
+        #pragma unroll 1
+        for (uint32_t i0 = 0; i0 < ptotal; i0 += 64) {
+          const uint32_t i = i0 + lane;
+          bool go = false;
+          if (i < ptotal) {
+            res[i] = 0;
+            go = hash_pass(queue[i], pk, iv, hl, p.hash_kmask, p.hash_imask, p.hash_shift);
+          }
+          const uint64_t m = __ballot(go);
+          if (go)
+            queue2[nwalk + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] =
+                (uint16_t)i;
+          nwalk += (uint32_t)__popcll(m);
+        }
+        wave_sync();
+      }
+      // ---- walk them with all lanes
+      uint32_t nz = 0;
       #pragma unroll 1
-      for (uint32_t i = lane; i < ptotal; i += 64) {
+      for (uint32_t j = lane; j < nwalk; j += 64) {
+        const uint32_t i = hashed ? (uint32_t)queue2[j] : j;
         const uint32_t e = queue[i];
         const uint32_t qt = e & 0x7FFFu;                 // index within the tile
         int32_t best = 0;
         if (GLOBAL) {
           walk<true>(0u, t0 + qt, nullptr, nullptr, p.next, p.out, text, n, enc, best, occ);
         } else {
-          best = deep_walk(e, D, p.lds_trie, p.levels, lds, bmpre, p.lvl, pk, iv, p.next, p.out,
+          best = deep_walk(e, D, p.lds_trie, p.levels, lds, bmpre, lvl, pk, iv, p.next, p.out,
                            p.jump, p.jres, occ);
         }
         res[i] = best;
+        nz |= (uint32_t)best;
       }
+      // almost every pass ends with no walk reporting a pattern: then the
+      // dense output of its positions is all zero and it has no hits
+      const bool any = __ballot(nz != 0) != 0;
       wave_sync();
       // ---- the groups of this pass: pick up results, dense output, hits
       #pragma unroll 1
       for (uint32_t g = 0; g < 4; ++g) {
         if (!((sel >> (4 * g)) & 1u)) continue;
         const uint32_t q0 = g * 256 + 4 * lane;
+        if (!any) {
+          if (mt) {
+            const i32x4 z = {0, 0, 0, 0};
+            if (maligned && q0 + 4 <= nt) {
+              __builtin_nontemporal_store(z, reinterpret_cast<i32x4*>(mt + q0));
+            } else {
+              if (q0 < nt) mt[q0] = 0;
+              if (q0 + 1 < nt) mt[q0 + 1] = 0;
+              if (q0 + 2 < nt) mt[q0 + 2] = 0;
+              if (q0 + 3 < nt) mt[q0 + 3] = 0;
+            }
+          }
+          continue;
+        }
         int32_t vv[4];
         #pragma unroll
         for (uint32_t r = 0; r < 4; ++r) {
@@ -623,7 +790,7 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
         if (__ballot(any)) {
           const uint32_t c = (vv[0] != 0) + (vv[1] != 0) + (vv[2] != 0) + (vv[3] != 0);
           uint32_t tot;
-          uint32_t o = tile_hits + wave_excl_small<3>(c, &tot);
+          uint32_t o = tile_hits + wave_excl_dpp(c, &tot);
           if (p.slots) {
             Slot* sl = p.slots + gtile * kSlot;
             #pragma unroll
@@ -639,7 +806,7 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
       }
       wave_sync();
     }
-    const unsigned long long tocc = wave_sum(occ);
+    const unsigned long long tocc = __ballot(occ != 0) ? wave_sum(occ) : 0ull;
     if (lane == 0) {
       p.tile_hits[gtile] = tile_hits;
       p.tile_occ[gtile] = tocc;
@@ -1022,17 +1189,39 @@ static uint32_t image_words(const HostTable& h, uint32_t D, bool lds_trie, uint3
 }
 
 static uint32_t scan_lds_bytes(uint32_t block, uint32_t img_words, uint32_t halo) {
-  return 4u * (img_words + (block / 64) * wave_words(halo));
+  return 4u * (img_words + kLvlWords + (block / 64) * wave_words(halo));
 }
 
 using ScanFn = void (*)(ScanParams);
 
-static ScanFn pick_scan(uint32_t block, bool global) {
+template <int BLOCK, bool SINGLE>
+static ScanFn pick_depth(uint32_t D) {
+  switch (D) {
+    case 6: return pfac_scan_kernel<BLOCK, false, 6, SINGLE>;
+    case 7: return pfac_scan_kernel<BLOCK, false, 7, SINGLE>;
+    case 8: return pfac_scan_kernel<BLOCK, false, 8, SINGLE>;
+    case 9: return pfac_scan_kernel<BLOCK, false, 9, SINGLE>;
+    case 10: return pfac_scan_kernel<BLOCK, false, 10, SINGLE>;
+    default: return nullptr;
+  }
+}
+
+// One instantiation per (workgroup size, filter depth, one text or a batch):
+// the depth fixes every window shift at compile time, and a one-text launch
+// carries none of the batch bookkeeping.
+template <int BLOCK>
+static ScanFn pick_block(bool global, uint32_t D, bool single) {
+  if (global)
+    return single ? pfac_scan_kernel<BLOCK, true, 0, true> : pfac_scan_kernel<BLOCK, true, 0, false>;
+  return single ? pick_depth<BLOCK, true>(D) : pick_depth<BLOCK, false>(D);
+}
+
+static ScanFn pick_scan(uint32_t block, bool global, uint32_t D, bool single) {
   switch (block) {
-    case 256: return global ? pfac_scan_kernel<256, true> : pfac_scan_kernel<256, false>;
-    case 512: return global ? pfac_scan_kernel<512, true> : pfac_scan_kernel<512, false>;
-    case 768: return global ? pfac_scan_kernel<768, true> : pfac_scan_kernel<768, false>;
-    case 1024: return global ? pfac_scan_kernel<1024, true> : pfac_scan_kernel<1024, false>;
+    case 256: return pick_block<256>(global, D, single);
+    case 512: return pick_block<512>(global, D, single);
+    case 768: return pick_block<768>(global, D, single);
+    case 1024: return pick_block<1024>(global, D, single);
     default: return nullptr;
   }
 }
@@ -1050,10 +1239,48 @@ static uint32_t auto_depth(const HostTable& h) {
   return D;
 }
 
+// Second-filter size the library picks: the smallest bitmap with at most
+// one bit in 16 set by the patterns, else the largest one while at most 40 %
+// of it is set (beyond that it passes too much to pay for its lookups).
+static uint32_t auto_hash_bits(const HostTable& h) {
+  for (uint32_t b = kHashMinBits; b <= kHashMaxBits; ++b)
+    if ((uint64_t)h.num_patterns * 16 <= (1ull << b)) return b;
+  if ((double)h.num_patterns <= 0.4 * (double)(1u << kHashMaxBits)) return kHashMaxBits;
+  return PFAC_HASH_NONE;
+}
+
+constexpr int kNoFit = 1;
+
+// Place the depth-D image in LDS next to `hw` words of second filter: with
+// every pattern longer than D, rank words and as many trie levels as asked
+// for (levels 0 = as many as fit); otherwise, or with PFAC_LEVELS_NONE, the
+// bare filter bitmap.  Sets p->levels on success; kNoFit when it does not fit.
+static int place_image(const HostTable& h, uint32_t D, uint32_t hw, uint32_t halo,
+                       uint32_t budget, pfac_plan* p) {
+  if (h.min_len > D && p->levels != PFAC_LEVELS_NONE) {
+    const uint32_t have = h.image[D].levels;
+    const uint32_t want = p->levels == 0 ? have : std::min(p->levels, have);
+    for (int32_t L = (int32_t)want; L >= 0; --L) {
+      if (scan_lds_bytes(p->block, image_words(h, D, true, (uint32_t)L) + hw, halo) <= budget) {
+        if (p->levels != 0 && (uint32_t)L < want) return kNoFit;   // explicit, too big
+        p->levels = (uint32_t)L;
+        return PFAC_OK;
+      }
+    }
+    if (p->levels != 0) return kNoFit;
+  }
+  // filter bitmap only; survivors read the global depth-D jump table
+  if (scan_lds_bytes(p->block, image_words(h, D, false, 0) + hw, halo) <= budget) {
+    p->levels = PFAC_LEVELS_NONE;
+    return PFAC_OK;
+  }
+  return kNoFit;
+}
+
 static int resolve_plan(const pfac_plan* in, const HostTable& h, int dev, pfac_plan* out) {
   const DeviceInfo di = device_info(dev);
   if (!di.ok) return PFAC_E_NODEV;
-  pfac_plan p = in ? *in : pfac_plan{0, 0, 0, 0, 0};
+  pfac_plan p = in ? *in : pfac_plan{0, 0, 0, 0, 0, 0};
   if (p.variant != PFAC_VARIANT_TILED && p.variant != PFAC_VARIANT_GLOBAL) return PFAC_E_ARG;
   const uint32_t halo = halo_for(h.max_len);
   if (p.variant == PFAC_VARIANT_TILED && halo > kMaxHalo) {
@@ -1065,35 +1292,37 @@ static int resolve_plan(const pfac_plan* in, const HostTable& h, int dev, pfac_p
   if (p.variant == PFAC_VARIANT_GLOBAL) {
     p.depth = 0;
     p.levels = PFAC_LEVELS_NONE;
+    p.hash_bits = PFAC_HASH_NONE;
     *out = p;
     return PFAC_OK;
   }
   const uint32_t budget = (uint32_t)di.lds_per_block;
   const bool auto_d = p.depth == 0;
+  const bool auto_h = p.hash_bits == 0;
+  if (!auto_h && p.hash_bits != PFAC_HASH_NONE &&
+      (p.hash_bits < kHashMinBits || p.hash_bits > kHashMaxBits))
+    return PFAC_E_ARG;
   if (auto_d) p.depth = auto_depth(h);
   for (;;) {
     if (p.depth < kMinJump || p.depth > kMaxJump) return PFAC_E_ARG;
     const uint32_t D = p.depth;
-    // with every pattern longer than D, the image can carry rank words and
-    // trie levels; try the most levels asked for that fit, down to rank only
-    if (h.min_len > D && p.levels != PFAC_LEVELS_NONE) {
-      const uint32_t have = h.image[D].levels;
-      const uint32_t want = p.levels == 0 ? have : std::min(p.levels, have);
-      for (int32_t L = (int32_t)want; L >= 0; --L) {
-        if (scan_lds_bytes(p.block, image_words(h, D, true, (uint32_t)L), halo) <= budget) {
-          if (p.levels != 0 && (uint32_t)L < want) return PFAC_E_ARG;   // explicit, too big
-          p.levels = (uint32_t)L;
-          *out = p;
-          return PFAC_OK;
-        }
+    // the second filter only helps when every pattern is longer than D;
+    // when the image does not fit beside it, the library's choice drops it
+    // before it drops trie levels or depth
+    uint32_t hb = PFAC_HASH_NONE;
+    if (h.hash_k > D && p.hash_bits != PFAC_HASH_NONE)
+      hb = auto_h ? auto_hash_bits(h) : p.hash_bits;
+    for (;;) {
+      const uint32_t hw = hb == PFAC_HASH_NONE ? 0u : (1u << hb) / 32;
+      const int rc = place_image(h, D, hw, halo, budget, &p);
+      if (rc == PFAC_OK) {
+        p.hash_bits = hb;
+        *out = p;
+        return PFAC_OK;
       }
-      if (p.levels != 0) return PFAC_E_ARG;
-    }
-    // filter bitmap only; survivors read the global depth-D jump table
-    if (scan_lds_bytes(p.block, image_words(h, D, false, 0), halo) <= budget) {
-      p.levels = PFAC_LEVELS_NONE;
-      *out = p;
-      return PFAC_OK;
+      if (rc != kNoFit) return rc;
+      if (hb == PFAC_HASH_NONE || !auto_h) break;
+      hb = PFAC_HASH_NONE;
     }
     if (!auto_d || D == kMinJump) return PFAC_E_ARG;
     --p.depth;
@@ -1136,9 +1365,12 @@ static uint64_t grid_for(ScanFn fn, const pfac_plan& plan, uint32_t lds, int dev
 static int launch_scan(const ScanParams& sp, const pfac_plan& plan, int dev, hipStream_t stream) {
   if (sp.local_tiles == 0) return PFAC_OK;
   const bool global = plan.variant == PFAC_VARIANT_GLOBAL;
-  ScanFn fn = pick_scan(plan.block, global);
+  ScanFn fn = pick_scan(plan.block, global, sp.D, sp.single != 0);
   if (!fn) return PFAC_E_ARG;
-  const uint32_t lds = global ? 0u : scan_lds_bytes(plan.block, sp.image_words, sp.halo);
+  const uint32_t lds =
+      global ? 4u * (plan.block / 64) * kGlobalWaveWords
+             : scan_lds_bytes(plan.block, sp.image_words + (sp.hash_on ? sp.hash_words : 0u),
+                              sp.halo);
   const uint64_t grid = grid_for(fn, plan, lds, dev, sp.local_tiles);
   hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(plan.block), lds, stream, sp);
   return hipGetLastError() == hipSuccess ? PFAC_OK : PFAC_E_HIP;
@@ -1176,6 +1408,15 @@ static void fill_table(ScanParams& sp, const pfac_table* t, const pfac_plan& pl)
     sp.levels = sp.lds_trie ? pl.levels : 0u;
     sp.image_words = image_words(h, D, sp.lds_trie, sp.levels);
     sp.lvl = reinterpret_cast<const u32x4*>(t->dev.levels[D]);
+    if (pl.hash_bits != PFAC_HASH_NONE) {
+      const uint32_t b = pl.hash_bits, K = h.hash_k;
+      sp.hash_on = 1;
+      sp.hash = t->dev.hash[b];
+      sp.hash_words = (1u << b) / 32;
+      sp.hash_shift = 32 - b;
+      sp.hash_kmask = K >= 16 ? 0xFFFFFFFFu : ~((1u << (32 - 2 * K)) - 1u);
+      sp.hash_imask = (1u << K) - 1u;
+    }
   }
 }
 
@@ -1238,6 +1479,10 @@ int pfac_build_table(const char* const* patterns, const uint32_t* lengths, uint3
     }
     o_lv[D] = off; off = align(off + lvdesc[D].size() * 4);
   }
+  uint64_t o_hash[kHashMaxBits + 1] = {};
+  for (uint32_t b = kHashMinBits; b <= kHashMaxBits; ++b) {
+    o_hash[b] = off; off = align(off + h.hash[b].size() * 4);
+  }
   if (hipMalloc(&t->dmem, off) != hipSuccess) {
     delete t;
     return PFAC_E_NOMEM;
@@ -1264,6 +1509,10 @@ int pfac_build_table(const char* const* patterns, const uint32_t* lengths, uint3
     v.jump[D] = reinterpret_cast<const uint32_t*>(base + o_jump[D]);
     v.jres[D] = reinterpret_cast<const OutEntry*>(base + o_jres[D]);
     v.image[D] = reinterpret_cast<const uint32_t*>(base + o_im[D]);
+  }
+  for (uint32_t b = kHashMinBits; b <= kHashMaxBits; ++b) {
+    if (!h.hash[b].empty()) ok = ok && put(o_hash[b], h.hash[b].data(), h.hash[b].size() * 4);
+    v.hash[b] = reinterpret_cast<const uint32_t*>(base + o_hash[b]);
   }
   if (!ok) {
     (void)hipFree(t->dmem);

@@ -9,16 +9,19 @@ device so new requests join the next launch while earlier ones still run.
 A request completes when the event recorded after its dispatch has passed;
 its results are views into the dispatch's output buffers.
 
-Texts are either host arrays (copied into a pinned staging buffer and then
-to the device on the dispatch's stream: the end-to-end path) or device
-tensors already resident (the matching path alone).
+Texts are host arrays (copied through a pinned staging buffer to the device
+on the dispatch's stream: the end-to-end path) or device tensors already
+resident (the matching path alone).  Many small texts (a batch of reads) are
+given as one ``TextBatch``: a buffer plus per-text offsets and lengths, so a
+request of 10,000 reads costs a few array operations, not 10,000 Python
+objects.
 """
 from __future__ import annotations
 
 import collections
 import time
-from dataclasses import dataclass, field
-from typing import Dict, List, Optional, Sequence
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
 
 import numpy as np
 import torch
@@ -29,39 +32,85 @@ ALIGN = 16
 
 
 @dataclass
+class TextBatch:
+    """Many texts inside one uint8 buffer (host array or device tensor)."""
+    base: object                     # np.ndarray or torch.Tensor (uint8)
+    offsets: np.ndarray              # byte offset of each text in `base`
+    lengths: np.ndarray              # bases of each text
+
+    def __post_init__(self):
+        self.offsets = np.asarray(self.offsets, dtype=np.int64)
+        self.lengths = np.asarray(self.lengths, dtype=np.int64)
+
+    def __len__(self) -> int:
+        return int(self.lengths.size)
+
+    def text(self, i: int):
+        o, n = int(self.offsets[i]), int(self.lengths[i])
+        return self.base[o:o + n]
+
+
+def _nbytes(t) -> int:
+    return int(t.numel() if torch.is_tensor(t) else t.size)
+
+
+@dataclass
 class Request:
     rid: int
     table: int
-    texts: list                      # host uint8 arrays, or device uint8 tensors
+    texts: object                    # list of host arrays / device tensors, or a TextBatch
     arrival: float = 0.0             # seconds, relative to the server clock
     admitted: float = -1.0
     dispatched: float = -1.0
     completed: float = -1.0
     result: Optional["RequestResult"] = None
 
+    def segments(self):
+        """(buffer, offsets, lengths) runs of the request's texts, in order."""
+        if isinstance(self.texts, TextBatch):
+            return [(self.texts.base, self.texts.offsets, self.texts.lengths)]
+        return [(t, np.zeros(1, dtype=np.int64), np.array([_nbytes(t)], dtype=np.int64))
+                for t in self.texts]
+
     @property
-    def lengths(self) -> List[int]:
-        return [int(t.numel() if torch.is_tensor(t) else t.size) for t in self.texts]
+    def lengths(self) -> np.ndarray:
+        if isinstance(self.texts, TextBatch):
+            return self.texts.lengths
+        return np.array([_nbytes(t) for t in self.texts], dtype=np.int64)
+
+    @property
+    def num_texts(self) -> int:
+        return len(self.texts)
+
+    def text(self, i: int):
+        return self.texts.text(i) if isinstance(self.texts, TextBatch) else self.texts[i]
 
     @property
     def bases(self) -> int:
-        return sum(self.lengths)
+        return int(self.lengths.sum())
 
     def device_bytes(self) -> int:
         """What the request holds on the device while admitted: its texts
         (padded), its dense match arrays, its share of the hit buffer and
         counters."""
         L = self.lengths
-        text = sum((x + ALIGN - 1) // ALIGN * ALIGN for x in L)
-        return text + 4 * sum(L) + 12 * (sum(L) // 16 + 64) + 16 * (len(L) + 1)
+        text = int(((L + ALIGN - 1) // ALIGN * ALIGN).sum())
+        total = int(L.sum())
+        return text + 4 * total + 12 * (total // 16 + 64) + 16 * (L.size + 1)
 
 
 @dataclass
 class RequestResult:
-    match: List[torch.Tensor]        # int32 per text (views into the dispatch buffer)
+    match: torch.Tensor              # int32, the texts' dense outputs back to back
+    offsets: np.ndarray              # start of each text's run in `match`
+    lengths: np.ndarray
     hits: torch.Tensor               # int32 (k, 3): text index within the request, pos, pid
     num_hits: np.ndarray             # per text
     occurrences: np.ndarray          # per text
+
+    def text_match(self, i: int) -> torch.Tensor:
+        o = int(self.offsets[i])
+        return self.match[o:o + int(self.lengths[i])]
 
 
 class Admission:
@@ -105,8 +154,10 @@ class _Dispatch:
     res: object
     first_text: List[int]
     staging: Optional[torch.Tensor]
-    dev_text: Optional[torch.Tensor]
-    res_offsets: Optional[np.ndarray] = None
+    dev_text: torch.Tensor
+    offsets: np.ndarray
+    lengths: np.ndarray
+    tids: np.ndarray
 
 
 class Server:
@@ -124,6 +175,8 @@ class Server:
         self.admitted: collections.deque = collections.deque()  # admitted, not dispatched
         self.inflight: collections.deque = collections.deque()
         self.done: List[Request] = []
+        self.max_seen_inflight = 0
+        self.dispatch_sizes: List[int] = []
         self.t0 = time.perf_counter()
 
     def now(self) -> float:
@@ -140,6 +193,43 @@ class Server:
             self.admitted.append(r)
 
     # ------------------------------------------------------------ dispatch
+    def _place(self, segs):
+        """Device buffer and per-text byte offsets for the dispatch's texts:
+        in place when every text already lives in one device allocation,
+        else copied (host texts through pinned staging), each run of texts
+        as one copy at a 16-byte aligned destination."""
+        bufs = [b for b, _, _ in segs]
+        if all(torch.is_tensor(b) and b.is_cuda and b.dtype == torch.uint8 and b.is_contiguous()
+               for b in bufs):
+            if len({b.untyped_storage().data_ptr() for b in bufs}) == 1:
+                dev = torch.empty(0, dtype=torch.uint8, device=self.device).set_(
+                    bufs[0].untyped_storage())
+                offs = np.concatenate([b.storage_offset() + o for b, o, _ in segs])
+                return dev, offs, None
+        spans, cur = [], 0
+        for b, o, L in segs:
+            lo = int(o.min()) if o.size else 0
+            hi = int((o + L).max()) if o.size else 0
+            spans.append((cur, lo, hi))
+            cur += (hi - lo + ALIGN - 1) // ALIGN * ALIGN
+        total = max(ALIGN, cur)
+        dev = torch.empty(total, dtype=torch.uint8, device=self.device)
+        staging = None
+        if any(not torch.is_tensor(b) for b in bufs):
+            # host runs: fill a pinned buffer, one host-to-device copy
+            staging = torch.empty(total, dtype=torch.uint8, pin_memory=True)
+            sv = staging.numpy()
+            for b, (dst, lo, hi) in zip(bufs, spans):
+                if not torch.is_tensor(b) and hi > lo:
+                    sv[dst:dst + hi - lo] = b[lo:hi]
+            dev.copy_(staging, non_blocking=True)
+        # device runs: copied after it on the same stream
+        for b, (dst, lo, hi) in zip(bufs, spans):
+            if torch.is_tensor(b) and hi > lo:
+                dev[dst:dst + hi - lo].copy_(b[lo:hi], non_blocking=True)
+        offs = np.concatenate([dst + (o - lo) for (_, o, _), (dst, lo, _) in zip(segs, spans)])
+        return dev, offs, staging
+
     def _dispatch(self):
         if not self.admitted or len(self.inflight) >= self.max_inflight:
             return
@@ -149,51 +239,30 @@ class Server:
             r = self.admitted.popleft()
             reqs.append(r)
             bases += r.bases
-        texts, tids, first = [], [], []
+        segs, tids, first = [], [], []
+        ntext = 0
         for r in reqs:
-            first.append(len(texts))
-            texts += list(r.texts)
-            tids += [r.table] * len(r.texts)
-        lengths = np.array([int(t.numel() if torch.is_tensor(t) else t.size) for t in texts],
-                           dtype=np.int64)
-        padded = (lengths + ALIGN - 1) // ALIGN * ALIGN
-        offsets = np.concatenate([[0], np.cumsum(padded)[:-1]]).astype(np.int64)
-        total = int(padded.sum())
-        staging = None
-        shared = None
-        if texts and all(torch.is_tensor(t) for t in texts):
-            ptrs = {t.untyped_storage().data_ptr() for t in texts}
-            if len(ptrs) == 1 and all(t.is_contiguous() and t.dtype == torch.uint8 for t in texts):
-                shared = texts[0].untyped_storage()
+            first.append(ntext)
+            for s in r.segments():
+                segs.append(s)
+                ntext += int(s[2].size)
+            tids.append(np.full(r.num_texts, r.table, dtype=np.uint32))
+        lengths = np.concatenate([s[2] for s in segs]).astype(np.int64)
+        tids = np.concatenate(tids)
         with torch.cuda.stream(self.stream):
-            if shared is not None:
-                # texts are views of one device buffer: match them in place
-                dev = torch.empty(0, dtype=torch.uint8, device=self.device).set_(shared)
-                offsets = np.array([t.storage_offset() for t in texts], dtype=np.int64)
-            else:
-                dev = torch.empty(max(ALIGN, total), dtype=torch.uint8, device=self.device)
-            if shared is not None:
-                pass
-            elif texts and not torch.is_tensor(texts[0]):
-                staging = torch.empty(max(ALIGN, total), dtype=torch.uint8, pin_memory=True)
-                sv = staging.numpy()
-                for t, o in zip(texts, offsets):
-                    sv[o:o + t.size] = t
-                dev.copy_(staging, non_blocking=True)
-            else:
-                for t, o in zip(texts, offsets):
-                    dev[o:o + t.numel()].copy_(t, non_blocking=True)
+            dev, offsets, staging = self._place(segs)
             res = match_batch(self.tables, dev, offsets, lengths, table_index=tids,
                               plan=self.plan, stream=self.stream,
-                              hit_cap=int(lengths.sum()) // 16 + 64 * len(texts))
+                              hit_cap=int(lengths.sum()) // 16 + 64 * ntext)
             ev = torch.cuda.Event()
             ev.record(self.stream)
         t = self.now()
         for r in reqs:
             r.dispatched = t
-        self.inflight.append(_Dispatch(reqs, ev, res, first, staging, dev, offsets))
-        self.max_seen_inflight = max(getattr(self, "max_seen_inflight", 0), len(self.inflight))
-        self.dispatch_sizes = getattr(self, "dispatch_sizes", []) + [len(reqs)]
+        self.inflight.append(_Dispatch(reqs, ev, res, first, staging, dev, offsets, lengths,
+                                       tids))
+        self.max_seen_inflight = max(self.max_seen_inflight, len(self.inflight))
+        self.dispatch_sizes.append(len(reqs))
 
     # ------------------------------------------------------------ completion
     def _complete(self):
@@ -204,25 +273,24 @@ class Server:
             if d.res.hits is not None and counters[0] > d.res.hits.shape[0]:
                 # the hit buffer was too small: redo this dispatch with room for all
                 with torch.cuda.stream(self.stream):
-                    lengths = [n for r in d.reqs for n in r.lengths]
-                    offs = d.res_offsets
-                    tids = [r.table for r in d.reqs for _ in r.texts]
-                    d.res = match_batch(self.tables, d.dev_text, offs, lengths,
-                                        table_index=tids, plan=self.plan, stream=self.stream,
+                    d.res = match_batch(self.tables, d.dev_text, d.offsets, d.lengths,
+                                        table_index=d.tids, plan=self.plan, stream=self.stream,
                                         hit_cap=int(counters[0]) + 64)
                 self.stream.synchronize()
                 counters = d.res.counters.cpu().numpy()
             per_hits, per_occ = counters[2::2], counters[3::2]
             hit_start = np.concatenate([[0], np.cumsum(per_hits)]).astype(np.int64)
+            mo = np.asarray(d.res.match_offsets, dtype=np.int64)
             for r, f in zip(d.reqs, d.first_text):
-                k = len(r.texts)
-                mats = [d.res.match[int(d.res.match_offsets[f + i]):
-                                    int(d.res.match_offsets[f + i]) + r.lengths[i]]
-                        for i in range(k)]
+                k = r.num_texts
+                L = d.lengths[f:f + k]
+                m0 = int(mo[f]) if k else 0
+                mats = d.res.match[m0:m0 + int(L.sum())]
                 h0, h1 = int(hit_start[f]), int(hit_start[f + k])
                 h = d.res.hits[h0:h1].clone()
                 h[:, 0] -= f
-                r.result = RequestResult(mats, h, per_hits[f:f + k].copy(), per_occ[f:f + k].copy())
+                r.result = RequestResult(mats, mo[f:f + k] - m0, L, h,
+                                         per_hits[f:f + k].copy(), per_occ[f:f + k].copy())
                 r.completed = t
                 self.gate.release(r)
                 self.done.append(r)
@@ -283,8 +351,9 @@ def plain_per_request(tables: Sequence[Table], requests: Sequence[Request], devi
     for r in sorted(requests, key=lambda r: r.arrival):
         while clock() < r.arrival:
             time.sleep(50e-6)
-        for t in r.texts:
-            dt = t if torch.is_tensor(t) else torch.from_numpy(t).to(device)
+        for i in range(r.num_texts):
+            t = r.text(i)
+            dt = t if torch.is_tensor(t) else torch.from_numpy(np.ascontiguousarray(t)).to(device)
             match(tables[r.table], dt, plan=plan, hit_cap=int(dt.numel()) // 16 + 64)
         torch.cuda.synchronize()
         r.completed = clock()

@@ -145,6 +145,46 @@ def test_lds_trie_levels_give_identical_results(plan):
     _check(res, pats, text)
 
 
+HASH_PLANS = [
+    dict(block=1024, depth=9, hash_bits=12),
+    dict(block=512, depth=8, hash_bits=17, levels=pf.PFAC_LEVELS_NONE),
+    dict(block=1024, depth=9, hash_bits=pf.PFAC_HASH_NONE),
+    dict(block=256, depth=7, hash_bits=14, levels=2),
+    dict(block=256, depth=10, hash_bits=16, levels=pf.PFAC_LEVELS_NONE),
+]
+
+
+@pytest.mark.parametrize("plan", range(len(HASH_PLANS)))
+def test_second_filter_gives_identical_results(plan):
+    """Every pattern has 16 or more bases: queued windows first test the hash
+    of their first 16 bases.  Non-bases planted 10..15 bases after the start
+    of pattern occurrences (inside the hashed window, past the first filter)
+    must still walk."""
+    w = W.plain_workload(1, n=2_000_003, num_patterns=3000)
+    pats = w.patterns
+    text = w.text.copy()
+    m0, _ = oracle.scan(pats, text, threads=8)
+    occ = np.nonzero(m0)[0]
+    g = W.rng(78)
+    for q in g.choice(occ, size=min(40, occ.size), replace=False):
+        off = int(g.integers(10, 16))
+        if q + off < text.size:
+            text[q + off] = ord("N")
+    print("plan", HASH_PLANS[plan], "occurrences", occ.size, flush=True)
+    res = _gpu(pats, text, plan=HASH_PLANS[plan])
+    _check(res, pats, text)
+
+
+def test_default_plan_uses_second_filter_when_patterns_are_long():
+    tab = pf.Table(W.random_patterns(5000, 16, 40, W.rng(79)))
+    p = tab.default_plan(1 << 20)
+    assert 12 <= p["hash_bits"] <= 17
+    short = pf.Table([b"ACG"] + W.random_patterns(100, 16, 40, W.rng(80)))
+    assert short.default_plan(1 << 20)["hash_bits"] == pf.PFAC_HASH_NONE
+    with pytest.raises(pf.PfacError):
+        pf.match(tab, torch.zeros(64, dtype=torch.uint8, device=DEV), plan=dict(hash_bits=18))
+
+
 def test_edge_sizes_and_ragged_tails():
     g = W.rng(32)
     pats = W.random_patterns(100, 1, 10, g) + [b"ACGTACGTACGTACGTACGT"]

@@ -13,28 +13,49 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
 import paper_1811_10498_amd as pf  # noqa: E402
-from paper_1811_10498_amd.serve import Request, Server, plain_per_request  # noqa: E402
+from paper_1811_10498_amd.serve import (Request, Server, TextBatch,  # noqa: E402
+                                       plain_per_request)
 
 DEV = torch.device("cuda:0")
 
 
-def _requests(count, seed, scale, ntables):
+def _requests(count, seed, scale, ntables, device_reads=None):
+    """Scaled request stream.  Reads requests are TextBatches (many texts in
+    one buffer, 16-byte aligned slots); with `device_reads` they live in that
+    device tensor, else in host memory; other requests are host texts."""
     reqs = W.served_requests(count, rate_bases_per_s=5e9, seed=seed, num_tries=ntables,
                              scale=scale)
     out = []
     for r in reqs:
-        k = r.kind
-        texts = r.texts()
-        if k == "reads":
-            texts = texts[: max(1, int(len(texts) * scale))]
-        out.append(Request(r.rid, r.trie, texts, r.arrival))
+        if r.kind == "reads":
+            nreads = max(1, int(r.lengths.size * scale))
+            L = int(r.lengths[0])
+            g = W.rng(r.seed)
+            if device_reads is not None:
+                slot = (L + 15) // 16 * 16
+                start = int(g.integers(0, device_reads.numel() // slot - nreads)) * slot
+                offs = start + slot * np.arange(nreads)
+                tb = TextBatch(device_reads, offs, np.full(nreads, L))
+            else:
+                buf = W.uniform_ascii(nreads * (L + 3), g)
+                tb = TextBatch(buf, (L + 3) * np.arange(nreads), np.full(nreads, L))
+            out.append(Request(r.rid, r.trie, tb, r.arrival))
+        else:
+            out.append(Request(r.rid, r.trie, r.texts(), r.arrival))
     return out
 
 
-def test_served_results_match_alone_and_oracle():
+def _host(t):
+    return t.cpu().numpy() if torch.is_tensor(t) else np.asarray(t)
+
+
+@pytest.mark.parametrize("device_reads", [False, True])
+def test_served_results_match_alone_and_oracle(device_reads):
     tries = W.served_tries(seed=4, sizes=[300, 1200, 5000], pool_bases=2_000_000)
     tables = [pf.Table(t) for t in tries]
-    reqs = _requests(40, seed=4, scale=0.02, ntables=3)
+    pool = (torch.from_numpy(W.uniform_ascii(4 << 20, W.rng(9))).to(DEV) if device_reads
+            else None)
+    reqs = _requests(40, seed=4, scale=0.02, ntables=3, device_reads=pool)
     srv = Server(tables, budget_bytes=1 << 30, max_inflight=3)
     stats = srv.run(reqs)
     print(stats, "max inflight", srv.max_seen_inflight, "dispatch sizes", srv.dispatch_sizes,
@@ -43,18 +64,22 @@ def test_served_results_match_alone_and_oracle():
     assert max(srv.dispatch_sizes) > 1          # requests were coalesced
     for r in srv.done:
         res = r.result
-        for i, t in enumerate(r.texts):
-            alone = pf.match(tables[r.table], torch.from_numpy(t).to(DEV), hit_cap=t.size + 16)
+        assert res.match.numel() == r.bases
+        step = max(1, r.num_texts // 25)         # reads requests: every 25th read
+        for i in range(0, r.num_texts, step):
+            t = r.text(i)
+            dt = t if torch.is_tensor(t) else torch.from_numpy(np.ascontiguousarray(t)).to(DEV)
+            alone = pf.match(tables[r.table], dt, hit_cap=int(dt.numel()) + 16)
             torch.cuda.synchronize()
-            m_mix = res.match[i].cpu().numpy()
+            m_mix = res.text_match(i).cpu().numpy()
             assert np.array_equal(m_mix, alone.match.cpu().numpy()), (r.rid, i)
             assert res.num_hits[i] == alone.num_hits() and res.occurrences[i] == alone.total()
             h_mix = res.hits[res.hits[:, 0] == i][:, 1:].cpu().numpy().astype(np.int64)
             assert np.array_equal(h_mix, alone.hit_list())
         if r.rid % 7 == 0:                       # spot-check against the oracle
-            for i, t in enumerate(r.texts[:3]):
-                m_ref, tot = oracle.scan(tries[r.table], t)
-                assert np.array_equal(res.match[i].cpu().numpy(), m_ref)
+            for i in range(min(3, r.num_texts)):
+                m_ref, tot = oracle.scan(tries[r.table], _host(r.text(i)))
+                assert np.array_equal(res.text_match(i).cpu().numpy(), m_ref)
                 assert res.occurrences[i] == tot
 
 

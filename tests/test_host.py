@@ -75,6 +75,14 @@ def host_table(patterns, K=None):
 CODE = {ord("A"): 0, ord("C"): 1, ord("G"): 2, ord("T"): 3}
 
 
+def _pattern_arrays(patterns):
+    pats = [bytes(p) for p in patterns]
+    bufs = [ctypes.create_string_buffer(p, max(1, len(p))) for p in pats]
+    arr = (ctypes.c_void_p * len(pats))(*[ctypes.addressof(b) for b in bufs])
+    lens = (ctypes.c_uint32 * len(pats))(*[len(p) for p in pats])
+    return ctypes.cast(arr, ctypes.c_void_p), ctypes.cast(lens, ctypes.c_void_p), bufs
+
+
 def walk_all(t, text):
     """PFAC walk (paper Sec. IV) over the host table, every start position."""
     text = bytes(text)
@@ -276,3 +284,58 @@ def test_lds_image_navigation_matches_next_table(D, npat, lmin, lmax):
             assert first[D + k + 1] + j == s
             checked += 1
     assert checked > 50
+
+
+@pytest.mark.parametrize("bits", [12, 14, 17])
+def test_second_filter_bitmap_holds_every_pattern_prefix(bits):
+    """The hash bitmap (its definition is part of the public header) has the
+    bit of the first K bases of every pattern; smaller bitmaps are the OR-fold
+    of the largest; random windows pass at about the fraction of set bits."""
+    import ctypes
+    from paper_1811_10498_amd import _lib as L
+    lib = L.lib()
+    g = W.rng(81)
+    pats = W.random_patterns(3000, 16, 40, g) + [b"ACGTACGTACGTACGTA"]
+    arr, lens, keep = _pattern_arrays(pats)
+    def get(b):
+        words = np.zeros((1 << b) // 32, dtype=np.uint32)
+        k = ctypes.c_uint32(0)
+        bad = ctypes.c_int64(-1)
+        rc = lib.pfac_build_host_hash(arr, lens, len(pats), b, words.ctypes.data,
+                                      ctypes.byref(k), ctypes.byref(bad))
+        assert rc == 0
+        return words, k.value
+    words, K = get(bits)
+    assert K == 16
+    def h(key, b):
+        return ((key * 0x9E3779B1) & 0xFFFFFFFF) >> (32 - b)
+    code = {ord("A"): 0, ord("C"): 1, ord("G"): 2, ord("T"): 3}
+    for p in pats:
+        key = 0
+        for i in range(K):
+            key |= code[p[i]] << (30 - 2 * i)
+        x = h(key, bits)
+        assert (words[x >> 5] >> (x & 31)) & 1
+    big, _ = get(17)
+    bigbits = np.unpackbits(big.view(np.uint8), bitorder="little").astype(bool)
+    folded = bigbits.reshape(1 << bits, 1 << (17 - bits)).any(axis=1)
+    mine = np.unpackbits(words.view(np.uint8), bitorder="little").astype(bool)
+    assert np.array_equal(folded, mine)
+    keys = g.integers(0, 1 << 32, size=20000, dtype=np.uint64)
+    xs = ((keys * np.uint64(0x9E3779B1)) & np.uint64(0xFFFFFFFF)) >> np.uint64(32 - bits)
+    rate = mine[xs.astype(np.int64)].mean()
+    assert abs(rate - mine.mean()) < 0.03
+
+
+def test_second_filter_k_is_shortest_pattern_capped_at_16():
+    import ctypes
+    from paper_1811_10498_amd import _lib as L
+    lib = L.lib()
+    for pats, want in [([b"ACGTACGTACGT", b"ACGTACGTACGTACGTACGT"], 12),
+                       ([b"A" * 30, b"C" * 20], 16)]:
+        arr, lens, keep = _pattern_arrays(pats)
+        k = ctypes.c_uint32(0)
+        bad = ctypes.c_int64(-1)
+        assert lib.pfac_build_host_hash(arr, lens, len(pats), 12, None, ctypes.byref(k),
+                                        ctypes.byref(bad)) == 0
+        assert k.value == want
