@@ -16,7 +16,7 @@
 //     LDS queue and walked by all 64 lanes together: one global read of the
 //     depth-D jump table, then the breadth-first numbered next-state table
 //     (L2 / Infinity Cache resident), one base per step.
-//   * Text: each wave stages its 1024-position tile plus a halo of
+//   * Text: each wave stages its tile (2048 positions, 1024 in a batch) plus a halo of
 //     max_len-1 bases with 16-byte loads, as 2-bit codes plus an "invalid"
 //     bit per base (bytes other than A,C,G,T, and everything past the end).
 //   * Outputs: the dense int32 array leaves through LDS with 16-byte
@@ -37,9 +37,13 @@
 
 namespace pfac {
 
-constexpr uint32_t kTile = 1024;       // start positions per wave tile
+// Start positions per wave tile: one text per launch takes 2048 (the fixed
+// cost of a tile -- staging, locating, one round of deep walks -- spread over
+// more positions); a batch takes 1024 (short texts waste less of a tile).
+constexpr uint32_t kTileSingle = 2048;
+constexpr uint32_t kTileBatch = 1024;
 constexpr uint32_t kQueue = 256;       // deep-walk queue entries per wave
-constexpr uint32_t kSlot = 16;         // hits parked per tile
+constexpr uint32_t kSlot = 32;         // hits parked per tile
 constexpr uint32_t kMaxHalo = 4096;    // longest halo staged in LDS (bases)
 constexpr uint32_t kRedTiles = 4096;   // tiles per reduce/scatter workgroup
 
@@ -324,7 +328,7 @@ __device__ __forceinline__ bool hash_pass(uint32_t e, const uint32_t* __restrict
   return (hl[h >> 5] >> (h & 31u)) & 1u;
 }
 
-// Text of one wave tile: bases [t0, t0+span) of one text, span = kTile + halo.
+// Text of one wave tile: bases [t0, t0+span) of one text, span = TILE + halo.
 // Staged into the wave's LDS area as 2-bit codes, 16 per word with the first
 // base in the top bits (a window of bases then reads as a key with its first
 // base most significant), and an invalid bit per base, 32 per word with the
@@ -346,6 +350,7 @@ struct Prefetch {
   uint32_t fast;       // bit 0: a loaded, bit 1: b loaded, bit 2: h loaded
 };
 
+template <uint32_t TILE>
 __device__ __forceinline__ Prefetch fetch(const TextRef& r, uint32_t halo) {
   const uint32_t lane = threadIdx.x & 63;
   const uintptr_t addr = reinterpret_cast<uintptr_t>(r.t);
@@ -360,13 +365,20 @@ __device__ __forceinline__ Prefetch fetch(const TextRef& r, uint32_t halo) {
       f.a = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(r.t + ga));
       f.fast |= 1u;
     }
-    const uint64_t gh = r.t0 + kTile + 4ull * lane;
+    if (TILE == 2048) {
+      const uint64_t gb = ga + 1024;
+      if ((addr & 15) == 0 && gb + 16 <= r.n) {
+        f.b = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(r.t + gb));
+        f.fast |= 2u;
+      }
+    }
+    const uint64_t gh = r.t0 + TILE + 4ull * lane;
     if ((addr & 3) == 0 && lane < halo / 4 && gh + 4 <= r.n) {
       f.h = __builtin_nontemporal_load(reinterpret_cast<const uint32_t*>(r.t + gh));
       f.fast |= 4u;
     }
   } else {
-    const uint32_t nch = (kTile + halo) / 64;   // 64 bases per 16-byte chunk
+    const uint32_t nch = (TILE + halo) / 64;   // 64 bases per 16-byte chunk
     const bool al = (addr & 15) == 0;
     const uint64_t ga = r.t0 + 64ull * lane;
     if (al && lane < nch && ga + 64 <= r.n) {
@@ -471,29 +483,35 @@ __device__ __forceinline__ void commit_2bit_chunk(const TextRef& r, uint32_t c, 
 // every lane converts its 16-byte chunk of the tile; the halo is converted
 // in 4-byte pieces, one per lane (one byte of codes and four invalid bits
 // each; two neighbouring lanes join their invalid bits into one byte).
+template <uint32_t TILE>
 __device__ __forceinline__ void commit(const TextRef& r, uint32_t halo, const Prefetch& f,
                                        uint32_t* pk, uint32_t* iv) {
   const uint32_t lane = threadIdx.x & 63;
-  const uint32_t span = kTile + halo;
+  const uint32_t span = TILE + halo;
   if (r.enc == PFAC_TEXT_ASCII) {
     uint32_t packed, inv;
     ascii_chunk((f.fast & 1u) ? f.a : gather16(r, r.t0 + 16ull * lane), packed, inv);
     pk[lane] = packed;
     reinterpret_cast<uint16_t*>(iv)[lane] = (uint16_t)inv;
+    if (TILE == 2048) {
+      ascii_chunk((f.fast & 2u) ? f.b : gather16(r, r.t0 + 1024 + 16ull * lane), packed, inv);
+      pk[64 + lane] = packed;
+      reinterpret_cast<uint16_t*>(iv)[64 + lane] = (uint16_t)inv;
+    }
     uint8_t* pk8 = reinterpret_cast<uint8_t*>(pk);
     uint8_t* iv8 = reinterpret_cast<uint8_t*>(iv);
     const uint32_t npieces = halo / 4;
     for (uint32_t p0 = 0; p0 < npieces; p0 += 64) {
       const uint32_t pc = p0 + lane;
-      const uint32_t v = (p0 == 0 && (f.fast & 4u)) ? f.h : gather4(r, r.t0 + kTile + 4ull * pc);
+      const uint32_t v = (p0 == 0 && (f.fast & 4u)) ? f.h : gather4(r, r.t0 + TILE + 4ull * pc);
       uint32_t code8, inv4;
       ascii4(v, code8, inv4);
       // invalid bits of lane ^ 1 (quad permutation 1,0,3,2)
       const uint32_t other = (uint32_t)__builtin_amdgcn_mov_dpp((int)inv4, 0xB1, 0xF, 0xF, false);
       if (pc < npieces) {
-        // bases kTile+4pc .. +3: byte 3 - (pc & 3) of code word kTile/16 + pc/4
-        pk8[4 * (kTile / 16 + (pc >> 2)) + 3 - (pc & 3)] = (uint8_t)code8;
-        if (!(pc & 1u)) iv8[(kTile + 4 * pc) / 8] = (uint8_t)(inv4 | (other << 4));
+        // bases TILE+4pc .. +3: byte 3 - (pc & 3) of code word TILE/16 + pc/4
+        pk8[4 * (TILE / 16 + (pc >> 2)) + 3 - (pc & 3)] = (uint8_t)code8;
+        if (!(pc & 1u)) iv8[(TILE + 4 * pc) / 8] = (uint8_t)(inv4 | (other << 4));
       }
     }
   } else {
@@ -512,18 +530,18 @@ __device__ __forceinline__ void commit(const TextRef& r, uint32_t halo, const Pr
 // bits (+2), deep-walk results, deep-walk queue and the list of queue entries
 // that pass the second filter (16-bit entries).
 __host__ __device__ constexpr uint32_t round4(uint32_t x) { return (x + 3) & ~3u; }
-__host__ __device__ constexpr uint32_t pk_words(uint32_t halo) {
-  return round4((kTile + halo) / 16 + 2);
+__host__ __device__ constexpr uint32_t pk_words(uint32_t tile, uint32_t halo) {
+  return round4((tile + halo) / 16 + 2);
 }
-__host__ __device__ constexpr uint32_t iv_words(uint32_t halo) {
-  return round4((kTile + halo) / 32 + 2);
+__host__ __device__ constexpr uint32_t iv_words(uint32_t tile, uint32_t halo) {
+  return round4((tile + halo) / 32 + 2);
 }
 // LDS of one wave of the global-memory variant: results and queue.
 constexpr uint32_t kGlobalWaveWords = kQueue + kQueue / 2;
 // Trie-level descriptors copied into LDS after the image and the second filter.
 constexpr uint32_t kLvlWords = 4 * kImageLevels;
-__host__ __device__ constexpr uint32_t wave_words(uint32_t halo) {
-  return pk_words(halo) + iv_words(halo) + kQueue + kQueue / 2 + kQueue / 2;
+__host__ __device__ constexpr uint32_t wave_words(uint32_t tile, uint32_t halo) {
+  return pk_words(tile, halo) + iv_words(tile, halo) + kQueue + kQueue / 2 + kQueue / 2;
 }
 
 struct TileLoc {
@@ -553,9 +571,9 @@ __device__ __forceinline__ TileLoc locate(const ScanParams& p, uint64_t lt) {
   return L;
 }
 
-// Main scan.  Each wave takes whole 1024-position tiles (grid-stride).  A
-// lane owns 16 positions of a tile, four groups of four consecutive ones:
-// q = g*256 + 4*lane + r.  Positions whose walk goes on past the filter are
+// Main scan.  Each wave takes whole tiles of TILE positions (grid-stride).  A
+// lane owns 4*NG positions of a tile, NG = TILE/256 groups of four
+// consecutive ones: q = g*256 + 4*lane + r.  Positions whose walk goes on past the filter are
 // queued and walked by all lanes together; their results come back through
 // a result slot per queue entry.
 template <int BLOCK, bool GLOBAL, int DT, bool SINGLE>
@@ -566,6 +584,8 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   constexpr uint32_t D = GLOBAL ? 0u : (uint32_t)DT;   // filter depth (compile time)
+  constexpr uint32_t TILE = SINGLE ? kTileSingle : kTileBatch;
+  constexpr uint32_t NG = TILE / 256;                   // groups of 4 positions per lane
   const uint32_t img_words = GLOBAL ? 0u : p.image_words;
   uint32_t* bm = lds;                             // image: filter bitmap first
   const uint32_t* bmpre = lds + (GLOBAL ? 0u : (1u << (2 * D)) / 32);
@@ -581,9 +601,10 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
     res = reinterpret_cast<int32_t*>(lds + wave * kGlobalWaveWords);
     queue = reinterpret_cast<uint16_t*>(res + kQueue);
   } else {
-    pk = lds + img_words + (hashed ? p.hash_words : 0u) + kLvlWords + wave * wave_words(p.halo);
-    iv = pk + pk_words(p.halo);
-    res = reinterpret_cast<int32_t*>(iv + iv_words(p.halo));
+    pk = lds + img_words + (hashed ? p.hash_words : 0u) + kLvlWords +
+         wave * wave_words(TILE, p.halo);
+    iv = pk + pk_words(TILE, p.halo);
+    res = reinterpret_cast<int32_t*>(iv + iv_words(TILE, p.halo));
     queue = reinterpret_cast<uint16_t*>(res + kQueue);
     queue2 = queue + kQueue;
   }
@@ -618,13 +639,14 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
   TileLoc cur = locate<SINGLE>(p, lt);
   Prefetch pf{};
   if (!GLOBAL)
-    pf = fetch(TextRef{p.text + cur.seg.text_off, cur.seg.n, cur.ts * kTile, cur.seg.enc}, p.halo);
+    pf = fetch<TILE>(TextRef{p.text + cur.seg.text_off, cur.seg.n, cur.ts * TILE, cur.seg.enc},
+                     p.halo);
 
   for (;;) {
-    const uint64_t t0 = cur.ts * kTile;
+    const uint64_t t0 = cur.ts * TILE;
     const uint64_t n = cur.seg.n;
-    const uint32_t nt = (uint32_t)((n - t0) < kTile ? (n - t0) : kTile);  // positions in text
-    const bool full = nt == kTile;
+    const uint32_t nt = (uint32_t)((n - t0) < TILE ? (n - t0) : TILE);  // positions in text
+    const bool full = nt == TILE;
     const uint8_t* text = p.text + cur.seg.text_off;
     const uint32_t enc = cur.seg.enc;
     const uint64_t gtile = cur.gtile;
@@ -632,7 +654,7 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
     const bool maligned = mt && ((reinterpret_cast<uintptr_t>(mt) & 15) == 0);
 
     if (!GLOBAL) {
-      commit(TextRef{text, n, t0, enc}, p.halo, pf, pk, iv);
+      commit<TILE>(TextRef{text, n, t0, enc}, p.halo, pf, pk, iv);
       wave_sync();
     }
     // next tile: locate it and start loading its text now
@@ -642,14 +664,15 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
     if (more) {
       nxt = locate<SINGLE>(p, lt_next);
       if (!GLOBAL)
-        pf = fetch(TextRef{p.text + nxt.seg.text_off, nxt.seg.n, nxt.ts * kTile, nxt.seg.enc},
-                   p.halo);
+        pf = fetch<TILE>(TextRef{p.text + nxt.seg.text_off, nxt.seg.n, nxt.ts * TILE,
+                                 nxt.seg.enc},
+                         p.halo);
     }
 
-    // ---- classify the lane's 16 positions: bit 4g+r of want / slow
+    // ---- classify the lane's 4*NG positions: bit 4g+r of want / slow
     uint32_t want = 0, slow = 0;
     #pragma unroll
-    for (uint32_t g = 0; g < 4; ++g) {
+    for (uint32_t g = 0; g < NG; ++g) {
       const uint32_t q0 = g * 256 + 4 * lane;
       const uint32_t vmask =
           full ? 0xFu : (q0 >= nt ? 0u : (nt - q0 >= 4 ? 0xFu : (1u << (nt - q0)) - 1u));
@@ -691,9 +714,9 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
     uint32_t tile_hits = 0;
     uint32_t total;
     const uint32_t base = wave_excl_dpp(__builtin_popcount(want), &total);
-    const uint32_t passes = total <= kQueue ? 1u : 4u;
+    const uint32_t passes = total <= kQueue ? 1u : NG;
     for (uint32_t pass = 0; pass < passes; ++pass) {
-      const uint32_t sel = passes == 1 ? 0xFFFFu : (0xFu << (4 * pass));
+      const uint32_t sel = passes == 1 ? (0xFFFFFFFFu >> (32 - 4 * NG)) : (0xFu << (4 * pass));
       const uint32_t wsel = want & sel;
       uint32_t pbase = base, ptotal = total;
       if (passes != 1) pbase = wave_excl_dpp(__builtin_popcount(wsel), &ptotal);
@@ -751,7 +774,7 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
       wave_sync();
       // ---- the groups of this pass: pick up results, dense output, hits
       #pragma unroll 1
-      for (uint32_t g = 0; g < 4; ++g) {
+      for (uint32_t g = 0; g < NG; ++g) {
         if (!((sel >> (4 * g)) & 1u)) continue;
         const uint32_t q0 = g * 256 + 4 * lane;
         if (!any) {
@@ -898,6 +921,7 @@ struct ScatterParams {
   const Slot* slots;
   const unsigned long long* block_prefix;
   uint64_t tiles;
+  uint32_t tile;                  // start positions per tile
   void* hits;                     // pfac_hit* (single) or pfac_batch_hit* (batch)
   uint64_t hit_cap;
   uint32_t single;
@@ -995,9 +1019,9 @@ __global__ __launch_bounds__(1024) void pfac_scatter_kernel(ScatterParams p) {
       ts = t - p.tile_prefix[text];
       tab = p.tables[seg.table];
     }
-    const uint64_t t0 = ts * kTile;
+    const uint64_t t0 = ts * p.tile;
     const uint8_t* tx = p.text + seg.text_off;
-    for (uint32_t k = 0; k < kTile / 256; ++k) {   // 64 lanes x 4 positions per step
+    for (uint32_t k = 0; k < p.tile / 256; ++k) {   // 64 lanes x 4 positions per step
       const uint64_t pos0 = t0 + k * 256 + 4 * lane;
       int32_t v[4] = {0, 0, 0, 0};
       #pragma unroll
@@ -1188,8 +1212,11 @@ static uint32_t image_words(const HostTable& h, uint32_t D, bool lds_trie, uint3
   return h.image[D].upto[levels - 1];
 }
 
-static uint32_t scan_lds_bytes(uint32_t block, uint32_t img_words, uint32_t halo) {
-  return 4u * (img_words + kLvlWords + (block / 64) * wave_words(halo));
+// LDS of a scan launch.  The planner sizes for the larger (one-text) tile, so
+// a plan fits both kinds of launch.
+static uint32_t scan_lds_bytes(uint32_t block, uint32_t img_words, uint32_t halo,
+                               uint32_t tile = kTileSingle) {
+  return 4u * (img_words + kLvlWords + (block / 64) * wave_words(tile, halo));
 }
 
 using ScanFn = void (*)(ScanParams);
@@ -1370,7 +1397,7 @@ static int launch_scan(const ScanParams& sp, const pfac_plan& plan, int dev, hip
   const uint32_t lds =
       global ? 4u * (plan.block / 64) * kGlobalWaveWords
              : scan_lds_bytes(plan.block, sp.image_words + (sp.hash_on ? sp.hash_words : 0u),
-                              sp.halo);
+                              sp.halo, sp.single ? kTileSingle : kTileBatch);
   const uint64_t grid = grid_for(fn, plan, lds, dev, sp.local_tiles);
   hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(plan.block), lds, stream, sp);
   return hipGetLastError() == hipSuccess ? PFAC_OK : PFAC_E_HIP;
@@ -1569,7 +1596,7 @@ int pfac_match(const pfac_table* t, const void* d_text, uint64_t n, int enc, int
   int rc = resolve_plan(plan, t->host, dev, &pl);
   if (rc) return rc;
   unsigned long long* counters = reinterpret_cast<unsigned long long*>(d_counters);
-  const uint64_t tiles = (n + kTile - 1) / kTile;
+  const uint64_t tiles = (n + kTileSingle - 1) / kTileSingle;
   if (tiles == 0) {
     hipLaunchKernelGGL(pfac_zero_kernel, dim3(1), dim3(64), 0, stream, counters, 2u);
     return hipGetLastError() == hipSuccess ? PFAC_OK : PFAC_E_HIP;
@@ -1600,6 +1627,7 @@ int pfac_match(const pfac_table* t, const void* d_text, uint64_t n, int enc, int
   sc.hits = d_hits;
   sc.hit_cap = hit_cap;
   sc.single = 1;
+  sc.tile = kTileSingle;
   sc.seg0 = sp.seg0;
   sc.text = sp.text;
   sc.match = d_match;
@@ -1652,7 +1680,7 @@ static int layout_batch(const pfac_table* const* tables, uint32_t num_tables,
   if (num_texts) memcpy(L->segs.data(), descs, num_texts * sizeof(DevSeg));
   L->tile_prefix.assign(num_texts + 1, 0);
   for (uint32_t s = 0; s < num_texts; ++s)
-    L->tile_prefix[s + 1] = L->tile_prefix[s] + (descs[s].n + kTile - 1) / kTile;
+    L->tile_prefix[s + 1] = L->tile_prefix[s] + (descs[s].n + kTileBatch - 1) / kTileBatch;
   L->tiles = L->tile_prefix[num_texts];
   L->groups.assign(num_tables, {});
   for (uint32_t s = 0; s < num_texts; ++s)
@@ -1667,7 +1695,7 @@ static int layout_batch(const pfac_table* const* tables, uint32_t num_tables,
     std::vector<uint64_t>& lp = L->local_prefix[g];
     lp.assign(L->groups[g].size() + 1, 0);
     for (size_t i = 0; i < L->groups[g].size(); ++i)
-      lp[i + 1] = lp[i] + (descs[L->groups[g][i]].n + kTile - 1) / kTile;
+      lp[i + 1] = lp[i] + (descs[L->groups[g][i]].n + kTileBatch - 1) / kTileBatch;
     L->o_gs[g] = off; off = al256(off + L->groups[g].size() * 4);
     L->o_gp[g] = off; off = al256(off + lp.size() * 8);
   }
@@ -1728,6 +1756,7 @@ static int enqueue_batch(const BatchLayout& L, const Workspace* ws, const uint8_
   sc.hits = d_hits;
   sc.hit_cap = hit_cap;
   sc.single = 0;
+  sc.tile = kTileBatch;
   sc.nsegs = L.num_texts;
   sc.segs = reinterpret_cast<const DevSeg*>(db + L.o_segs);
   sc.tile_prefix = reinterpret_cast<const uint64_t*>(db + L.o_tp);
