@@ -122,6 +122,29 @@ int build_host_table(const char* const* patterns, const uint32_t* lengths, uint3
         if (out->next[i * 4 + a]) v |= (uint8_t)(1u << a);
       out->node[i] = v;
     }
+    // 4b. runs of single-child steps below every state (path compression)
+    out->chain.assign(2 * S, 0);
+    for (uint64_t i = 0; i < S; ++i) {
+      uint32_t len = 0, codes = 0;
+      uint64_t cur = i;
+      bool fin = false;
+      while (len < kChainMax) {
+        const uint8_t nb = out->node[cur];
+        const uint32_t kids_mask = nb & 0x0Fu;
+        if (__builtin_popcount(kids_mask) != 1) break;      // not a single child
+        const uint32_t a = (uint32_t)__builtin_ctz(kids_mask);
+        const uint32_t e = out->next[cur * 4 + a];
+        codes |= a << (30 - 2 * len);
+        ++len;
+        cur = e & kStateMask;
+        fin = (e & kFinalBit) != 0;
+        if (fin) break;                                      // a pattern ends here
+      }
+      if (len >= 2) {
+        out->chain[2 * i] = codes | len;
+        out->chain[2 * i + 1] = (uint32_t)cur | (fin ? kFinalBit : 0u);
+      }
+    }
     // 5. root jump tables of depth D: the result of the first D steps of the
     //    walk for every D-base window (first base most significant), filled by
     //    a depth-first pass over the trie; windows that leave the trie early

@@ -23,6 +23,9 @@ constexpr uint32_t kHashMinBits = 12;
 constexpr uint32_t kHashMaxBits = 17;
 constexpr uint32_t kHashMul = 0x9E3779B1u;
 
+// Longest run of single-child trie steps a walk takes at once.
+constexpr uint32_t kChainMax = 14;
+
 // Edge word of the next-state table: child state in bits 0..30 (0 = no edge,
 // the root is never a child), bit 31 set when the child is a final state.
 constexpr uint32_t kFinalBit = 0x80000000u;
@@ -57,6 +60,13 @@ struct HostTable {
   std::vector<OutEntry> jres[kMaxJump + 1];
   std::vector<uint32_t> bitmap[kMaxJump + 1];   // 4^D bits
   std::vector<uint8_t> node;              // [S]: bits 0..3 child exists (A,C,G,T), bit 4 final
+  // Path compression of the walk: chain[2s] = the bases of the run of
+  // single-child steps below s (first base in the top bits, up to kChainMax
+  // of them) with the run length in bits 0..3, chain[2s+1] = the state the run
+  // ends at, bit 31 set when it is final.  Every state strictly inside the
+  // run has exactly one child and is not final, so a walk either matches the
+  // whole run or ends inside it with nothing to report.  Length < 2: no run.
+  std::vector<uint32_t> chain;            // [2S]
   // LDS image per filter depth D: what the scan kernel copies into LDS.
   //   words [0, 4^D/32)           filter bitmap
   //   then 4^D/128 words          set bits before each 128-bit group (rank)
@@ -87,6 +97,7 @@ struct DevTable {
   const uint32_t* image[kMaxJump + 1];   // LDS image words (HostTable::Image)
   const uint32_t* levels[kMaxJump + 1];  // per image level: {byte_off, pre_off, first state, 0}
   const uint32_t* hash[kHashMaxBits + 1]; // second-filter bitmaps
+  const uint32_t* chain;                  // [2S] runs of single-child steps
   uint32_t num_states;
   uint32_t max_len;
 };

@@ -48,6 +48,7 @@ constexpr uint32_t kMaxHalo = 4096;    // longest halo staged in LDS (bases)
 constexpr uint32_t kRedTiles = 4096;   // tiles per reduce/scatter workgroup
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 
 struct DevSeg {
@@ -68,6 +69,7 @@ struct Slot {
 struct ScanParams {
   const uint32_t* next;
   const OutEntry* out;
+  const uint32_t* chain;          // runs of single-child steps (TILED)
   const uint32_t* jump;           // depth-D jump table (TILED)
   const OutEntry* jres;
   const uint32_t* image;          // LDS image of depth D (TILED): filter bitmap, its
@@ -129,6 +131,14 @@ __device__ __forceinline__ void ascii4(uint32_t x, uint32_t& code8, uint32_t& in
   inv4 = ((nz >> 7) * 0x01020408u) >> 24;
   const uint32_t t1 = shl_or<10>(cb, cb);   // as in ascii_chunk
   code8 = shl_or<20>(t1, t1) >> 24;
+}
+
+// The 32-bit LDS word at byte address a.  The kernels declare no static LDS,
+// so the dynamic area (the filter bitmap first) starts at LDS address 0 and a
+// bitmap word is read at its byte offset with no base added.
+typedef const uint32_t __attribute__((address_space(3))) lds_u32;
+__device__ __forceinline__ uint32_t lds_word(uint32_t a) {
+  return *reinterpret_cast<lds_u32*>(static_cast<uintptr_t>(a));
 }
 
 __device__ __forceinline__ void wave_sync() {
@@ -218,6 +228,48 @@ __device__ __forceinline__ void walk(uint32_t s, uint64_t q, const uint32_t* __r
   }
 }
 
+// The walk over LDS text with path compression: at a state with a run of
+// single-child steps (chain record, see the table layout) the next bases are
+// compared with the whole run at once -- all of them match and the walk jumps
+// to the end of the run, or the walk ends inside it, where no pattern ends.
+// The run record and the ordinary edge for the next base are loaded together,
+// so a step costs one round trip either way.
+__device__ __forceinline__ void walk_lds(uint32_t s, uint32_t q, const uint32_t* __restrict__ pk,
+                                         const uint32_t* __restrict__ iv,
+                                         const uint32_t* __restrict__ next,
+                                         const OutEntry* __restrict__ out,
+                                         const uint32_t* __restrict__ chain, int32_t& best,
+                                         unsigned long long& occ) {
+  for (;;) {
+    // validity bits and codes of the 16 bases from q (first base on top)
+    const uint32_t ivw = __builtin_amdgcn_alignbit(iv[(q >> 5) + 1], iv[q >> 5], q & 31u);
+    const uint32_t win =
+        (uint32_t)(((((uint64_t)pk[q >> 4] << 32) | pk[(q >> 4) + 1]) << (2 * (q & 15u))) >> 32);
+    const u32x2 ch = *reinterpret_cast<const u32x2*>(chain + 2ull * s);
+    const uint32_t e = next[(uint64_t)s * 4 + (win >> 30)];
+    const uint32_t len = ch.x & 15u;
+    if (len >= 2) {
+      if ((ivw & ((1u << len) - 1u)) | ((win ^ ch.x) & (0xFFFFFFFFu << (32 - 2 * len)))) break;
+      s = ch.y & kStateMask;
+      q += len;
+      if (ch.y & kFinalBit) {
+        const OutEntry o = out[s];
+        best = o.pid;
+        occ += o.mult;
+      }
+      continue;
+    }
+    if ((ivw & 1u) || e == 0) break;
+    s = e & kStateMask;
+    if (e & kFinalBit) {
+      const OutEntry o = out[s];
+      best = o.pid;
+      occ += o.mult;
+    }
+    ++q;
+  }
+}
+
 // Set bits among the first t (0..15) node bytes of a 16-node group (child
 // bits only, the low nibble of each byte).
 __device__ __forceinline__ uint32_t children_before(const u32x4& g, uint32_t t) {
@@ -253,6 +305,7 @@ __device__ __forceinline__ int32_t deep_walk(uint32_t e, uint32_t D, uint32_t ld
                                              const OutEntry* __restrict__ out,
                                              const uint32_t* __restrict__ jump,
                                              const OutEntry* __restrict__ jres,
+                                             const uint32_t* __restrict__ chain,
                                              unsigned long long& occ) {
   const uint32_t qt = e & 0x7FFFu;
   int32_t best = 0;
@@ -304,7 +357,7 @@ __device__ __forceinline__ int32_t deep_walk(uint32_t e, uint32_t D, uint32_t ld
       if (!s) return best;
     }
   }
-  walk<false>(s, q, pk, iv, next, out, nullptr, 0, 0, best, occ);
+  walk_lds(s, q, pk, iv, next, out, chain, best, occ);
   return best;
 }
 
@@ -684,15 +737,20 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
         // 16 bases from q0, first base in the top bits
         const uint32_t w = __builtin_amdgcn_perm(pk[wi], pk[wi + 1], bsel);
         const uint32_t inv = __builtin_amdgcn_alignbit(iv[ii + 1], iv[ii], sh4);
+        // window key x_r = bits [o_r, o_r+2D) of w, o_r = 32-2r-2D: its
+        // bitmap word is bits [o_r+5, o_r+2D) (read at byte offset 4x that)
+        // and its bit within the word bits [o_r, o_r+5) (a bit-field offset
+        // uses the low 5 bits of its operand).  All four reads are issued
+        // before the first is used.
+        uint32_t word[4];
         #pragma unroll
         for (uint32_t r = 0; r < 4; ++r) {
-          // window key x = bits [o, o+2D) of w: its bitmap word is bits
-          // [o+5, o+2D) and its bit within the word bits [o, o+5) (a bit-field
-          // offset uses the low 5 bits of its operand)
           const uint32_t o = 32 - 2 * r - 2 * D;
-          const uint32_t word = bm[__builtin_amdgcn_ubfe(w, o + 5, 2 * D - 5)];
-          m4 |= __builtin_amdgcn_ubfe(word, w >> o, 1u) << r;
+          word[r] = lds_word((w >> (o + 3)) & (((1u << (2 * D - 5)) - 1u) << 2));
         }
+        #pragma unroll
+        for (uint32_t r = 0; r < 4; ++r)
+          m4 |= __builtin_amdgcn_ubfe(word[r], w >> (32 - 2 * r - 2 * D), 1u) << r;
         if (inv & gmask) {
           // a window holds a non-base: such positions walk from the root
           #pragma unroll
@@ -763,7 +821,7 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
           walk<true>(0u, t0 + qt, nullptr, nullptr, p.next, p.out, text, n, enc, best, occ);
         } else {
           best = deep_walk(e, D, p.lds_trie, p.levels, lds, bmpre, lvl, pk, iv, p.next, p.out,
-                           p.jump, p.jres, occ);
+                           p.jump, p.jres, p.chain, occ);
         }
         res[i] = best;
         nz |= (uint32_t)best;
@@ -1424,6 +1482,7 @@ static int launch_tail(Workspace* ws, uint64_t tiles, unsigned long long* counte
 static void fill_table(ScanParams& sp, const pfac_table* t, const pfac_plan& pl) {
   sp.next = t->dev.next;
   sp.out = t->dev.out;
+  sp.chain = t->dev.chain;
   if (pl.variant == PFAC_VARIANT_TILED) {
     const HostTable& h = t->host;
     const uint32_t D = pl.depth;
@@ -1489,6 +1548,7 @@ int pfac_build_table(const char* const* patterns, const uint32_t* lengths, uint3
   uint64_t off = 0;
   const uint64_t o_next = off; off = align(off + h.next.size() * 4);
   const uint64_t o_out = off; off = align(off + h.out.size() * sizeof(OutEntry));
+  const uint64_t o_chain = off; off = align(off + h.chain.size() * 4);
   uint64_t o_jump[kMaxJump + 1] = {}, o_jres[kMaxJump + 1] = {}, o_im[kMaxJump + 1] = {};
   uint64_t o_lv[kMaxJump + 1] = {};
   std::vector<uint32_t> lvdesc[kMaxJump + 1];
@@ -1520,11 +1580,13 @@ int pfac_build_table(const char* const* patterns, const uint32_t* lengths, uint3
     return hipMemcpy(base + o, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
   };
   bool ok = put(o_next, h.next.data(), h.next.size() * 4) &&
-            put(o_out, h.out.data(), h.out.size() * sizeof(OutEntry));
+            put(o_out, h.out.data(), h.out.size() * sizeof(OutEntry)) &&
+            put(o_chain, h.chain.data(), h.chain.size() * 4);
   DevTable& v = t->dev;
   memset(&v, 0, sizeof(v));
   v.next = reinterpret_cast<const uint32_t*>(base + o_next);
   v.out = reinterpret_cast<const OutEntry*>(base + o_out);
+  v.chain = reinterpret_cast<const uint32_t*>(base + o_chain);
   v.num_states = (uint32_t)h.num_states;
   v.max_len = h.max_len;
   for (uint32_t D = kMinJump; D <= kMaxJump; ++D) {

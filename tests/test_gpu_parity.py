@@ -436,3 +436,33 @@ def test_prepared_batch_empty_and_rejections():
         pf.Batch([tab], [0], [5], table_index=[1], device=DEV)
     with pytest.raises(pf.PfacError):
         pf.Batch([tab], [0], [5], plan=dict(block=300), device=DEV)
+
+
+@pytest.mark.parametrize("plan", [None, dict(levels=pf.PFAC_LEVELS_NONE),
+                                  dict(block=256, depth=6, levels=2)])
+def test_long_single_child_runs(plan):
+    """Walks through long runs of single-child trie steps (the walk takes a
+    run at once): long patterns, prefixes of them ending inside runs,
+    occurrences with a substituted base or a non-base at every offset of a
+    run, and occurrences cut short by the end of the text."""
+    g = W.rng(90)
+    longs = W.random_patterns(60, 40, 64, g)
+    pats = list(longs)
+    for p in longs[:30]:
+        for k in sorted(set(int(x) for x in g.integers(8, len(p), size=3))):
+            pats.append(p[:k])                      # finals inside a run
+    parts = []
+    for i, p in enumerate(longs):
+        for off in range(0, len(p), 3):
+            q = bytearray(p)
+            if i % 3 == 0:
+                q[off] = ord("N")
+            elif i % 3 == 1:
+                q[off] = ord("ACGT"[("ACGT".index(chr(q[off])) + 1) % 4])
+            parts.append(bytes(q))
+            parts.append(bytes(W.uniform_ascii(int(g.integers(0, 20)), g)))
+        parts.append(p)                             # and one clean copy
+    text = np.frombuffer(b"".join(parts) + longs[0][:30], dtype=np.uint8).copy()
+    print("patterns", len(pats), "text", text.size, "plan", plan, flush=True)
+    res = _gpu(pats, text, plan=plan)
+    _check(res, pats, text)
