@@ -1312,10 +1312,11 @@ static ScanFn pick_scan(uint32_t block, bool global, uint32_t D, bool single) {
 }
 
 // Filter depth the library picks: deepen while at least 5 % of the windows
-// of the next level are trie prefixes, capped at 9 (32 KB of LDS).
+// of the next level are trie prefixes, up to 10 (a 128 KB bitmap, which only
+// fits beside the text of 512-thread or smaller workgroups).
 static uint32_t auto_depth(const HostTable& h) {
   uint32_t D = kMinJump;
-  for (uint32_t d = kMinJump; d <= 9; ++d) {
+  for (uint32_t d = kMinJump; d <= kMaxJump; ++d) {
     const uint64_t at_d = (d + 1 < h.depth_start.size())
                               ? h.depth_start[d + 1] - h.depth_start[d] : 0;
     D = d;
@@ -1372,6 +1373,27 @@ static int resolve_plan(const pfac_plan* in, const HostTable& h, int dev, pfac_p
     if (in && in->depth) return PFAC_E_ARG;
     p.variant = PFAC_VARIANT_GLOBAL;  // patterns too long to stage a halo in LDS
   }
+  // Library choice when every pattern is longer than the filter depth and
+  // the second filter is worth keeping: bitmap + second filter only (the few
+  // windows that pass both are walked from the global jump table) in
+  // 512-thread workgroups -- measured faster than keeping trie levels in LDS,
+  // whose walks the second filter has already cut down.  Otherwise
+  // 1024-thread workgroups and as many LDS trie levels as fit.
+  // The depth then stays at most 9 (a 32 KB bitmap next to the second
+  // filter).
+  const bool auto_b = p.block == 0;
+  const bool auto_d = p.depth == 0;
+  if (p.variant == PFAC_VARIANT_TILED && p.levels == 0 && p.hash_bits == 0) {
+    const uint32_t D = p.depth ? p.depth : std::min<uint32_t>(auto_depth(h), 9u);
+    if (h.hash_k > D && auto_hash_bits(h) != PFAC_HASH_NONE) {
+      p.levels = PFAC_LEVELS_NONE;
+      p.depth = D;
+      if (p.block == 0) p.block = 512;
+    }
+  }
+  // with the workgroup size left to the library, a depth whose image does
+  // not fit beside 1024 threads' text tries 512, then 256, before a
+  // shallower depth
   if (p.block == 0) p.block = 1024;
   if (p.block != 256 && p.block != 512 && p.block != 768 && p.block != 1024) return PFAC_E_ARG;
   if (p.variant == PFAC_VARIANT_GLOBAL) {
@@ -1382,12 +1404,11 @@ static int resolve_plan(const pfac_plan* in, const HostTable& h, int dev, pfac_p
     return PFAC_OK;
   }
   const uint32_t budget = (uint32_t)di.lds_per_block;
-  const bool auto_d = p.depth == 0;
   const bool auto_h = p.hash_bits == 0;
   if (!auto_h && p.hash_bits != PFAC_HASH_NONE &&
       (p.hash_bits < kHashMinBits || p.hash_bits > kHashMaxBits))
     return PFAC_E_ARG;
-  if (auto_d) p.depth = auto_depth(h);
+  if (p.depth == 0) p.depth = auto_depth(h);
   for (;;) {
     if (p.depth < kMinJump || p.depth > kMaxJump) return PFAC_E_ARG;
     const uint32_t D = p.depth;
@@ -1397,6 +1418,7 @@ static int resolve_plan(const pfac_plan* in, const HostTable& h, int dev, pfac_p
     uint32_t hb = PFAC_HASH_NONE;
     if (h.hash_k > D && p.hash_bits != PFAC_HASH_NONE)
       hb = auto_h ? auto_hash_bits(h) : p.hash_bits;
+    const uint32_t block0 = p.block;
     for (;;) {
       const uint32_t hw = hb == PFAC_HASH_NONE ? 0u : (1u << hb) / 32;
       const int rc = place_image(h, D, hw, halo, budget, &p);
@@ -1406,9 +1428,15 @@ static int resolve_plan(const pfac_plan* in, const HostTable& h, int dev, pfac_p
         return PFAC_OK;
       }
       if (rc != kNoFit) return rc;
+      if (auto_b && p.block > 256) {
+        p.block = p.block > 512 ? 512 : 256;
+        continue;
+      }
       if (hb == PFAC_HASH_NONE || !auto_h) break;
       hb = PFAC_HASH_NONE;
+      p.block = block0;
     }
+    p.block = block0;
     if (!auto_d || D == kMinJump) return PFAC_E_ARG;
     --p.depth;
   }
