@@ -172,6 +172,8 @@ def main():
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched workload")
     ap.add_argument("--no-served", action="store_true", help="skip the served workload")
+    ap.add_argument("--autotune", action="store_true",
+                    help="also time the autotuner's plan (reported beside the default plan)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -256,6 +258,25 @@ def main():
                          "(wall %.2f s, about %.0f core-seconds)"
                          % (sample >> 20, len(w.patterns), threads, reps, dt, dt * threads)}
 
+    tuned = None
+    if args.autotune:
+        # the autotuner's choice on a 32 Mbase sample, timed like the default
+        from paper_1811_10498_amd.autotune import Autotuner
+        tr = Autotuner(reps=3).tune(table, text, n=n, enc=w.enc)
+        s_ev = torch.cuda.Event(enable_timing=True)
+        e_ev = torch.cuda.Event(enable_timing=True)
+        rt = pf.match(table, text, n=n, enc=w.enc, plan=tr.plan, hit_cap=num_hits + 1024)
+        torch.cuda.synchronize()
+        assert rt.num_hits() == num_hits and rt.total() == total
+        s_ev.record()
+        for _ in range(K):
+            pf.match(table, text, n=n, enc=w.enc, plan=tr.plan, out=rt)
+        e_ev.record()
+        torch.cuda.synchronize()
+        tms = s_ev.elapsed_time(e_ev) / K
+        tuned = {"plan": tr.plan, "candidates_tried": len(tr.tried), "ms_per_step": round(tms, 4),
+                 "gbases_per_s": round(n / tms / 1e6, 2)}
+
     batched = None if args.no_batched else bench_batched(pf, torch)
     served = None if args.no_served else bench_served(pf, torch)
 
@@ -296,6 +317,7 @@ def main():
             "avg_launch_ms": round(avg_launch_s * 1e3, 4),
         },
         "cpu_baseline": cpu,
+        "autotuned": tuned,
         "batched": batched,
         "served": served,
         "hbm_fraction_of_peak": round(achieved / HBM_PEAK_GBS, 4),

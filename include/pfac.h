@@ -258,6 +258,21 @@ int pfac_build_host_image(const char* const* patterns, const uint32_t* lengths, 
 int pfac_build_host_hash(const char* const* patterns, const uint32_t* lengths, uint32_t num,
                          uint32_t bits, uint32_t* words, uint32_t* k, int64_t* bad_index);
 
+/*
+ * Host-only: the path-compression records the walk uses, for inspection and
+ * tests.  chain[2s] = the bases of the run of single-child steps below state
+ * s (base k of the run in bits 31-2k..30-2k, A=0 C=1 G=2 T=3) with the run
+ * length in bits 0..3, chain[2s+1] = the state the run ends at, bit 31 set
+ * when that state is final.  Every state strictly inside a run has exactly
+ * one child and is not final; runs are at most 14 bases; a length below 2
+ * means no run.  States are numbered as in pfac_build_host.  *num_states
+ * always receives the state count; chain (uint32[2*cap]) is written only
+ * when it is <= cap.
+ */
+int pfac_build_host_chain(const char* const* patterns, const uint32_t* lengths, uint32_t num,
+                          uint32_t* chain, uint64_t cap, uint64_t* num_states,
+                          int64_t* bad_index);
+
 /* Human-readable text of a status code (static storage). */
 const char* pfac_strerror(int status);
 

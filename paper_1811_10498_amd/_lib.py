@@ -19,6 +19,7 @@ EXPORTS = (
     "pfac_build_table", "pfac_table_info", "pfac_free_table", "pfac_match",
     "pfac_match_batch", "pfac_batch_create", "pfac_batch_launch", "pfac_batch_free",
     "pfac_default_plan", "pfac_build_host", "pfac_build_host_image", "pfac_build_host_hash",
+    "pfac_build_host_chain",
     "pfac_strerror",
     "pfac_version",
 )
@@ -100,6 +101,9 @@ def lib():
             L.pfac_build_host_hash.argtypes = [P, P, u32, u32, P, ctypes.POINTER(u32),
                                                ctypes.POINTER(i64)]
             L.pfac_build_host_hash.restype = ctypes.c_int
+            L.pfac_build_host_chain.argtypes = [P, P, u32, P, u64, ctypes.POINTER(u64),
+                                                ctypes.POINTER(i64)]
+            L.pfac_build_host_chain.restype = ctypes.c_int
             L.pfac_strerror.argtypes = [ctypes.c_int]
             L.pfac_strerror.restype = ctypes.c_char_p
             L.pfac_version.argtypes = []

@@ -326,3 +326,17 @@ extern "C" int pfac_build_host_hash(const char* const* patterns, const uint32_t*
   }
   return PFAC_OK;
 }
+
+extern "C" int pfac_build_host_chain(const char* const* patterns, const uint32_t* lengths,
+                                     uint32_t num, uint32_t* chain, uint64_t cap,
+                                     uint64_t* num_states, int64_t* bad_index) {
+  using namespace pfac;
+  if (!num_states) return PFAC_E_ARG;
+  HostTable h;
+  int rc = build_host_table(patterns, lengths, num, &h, bad_index);
+  if (rc != PFAC_OK) return rc;
+  *num_states = h.num_states;
+  if (chain && h.num_states <= cap)
+    memcpy(chain, h.chain.data(), h.chain.size() * sizeof(uint32_t));
+  return PFAC_OK;
+}

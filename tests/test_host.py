@@ -339,3 +339,98 @@ def test_second_filter_k_is_shortest_pattern_capped_at_16():
         assert lib.pfac_build_host_hash(arr, lens, len(pats), 12, None, ctypes.byref(k),
                                         ctypes.byref(bad)) == 0
         assert k.value == want
+
+
+def host_chain(patterns):
+    lib = _lib()
+    arr, lens, keep = _pattern_arrays(patterns)
+    S = ctypes.c_uint64(0)
+    bad = ctypes.c_int64(-1)
+    assert lib.pfac_build_host_chain(arr, lens, len(patterns), None, 0, ctypes.byref(S),
+                                     ctypes.byref(bad)) == 0
+    chain = np.zeros(2 * S.value, dtype=np.uint32)
+    assert lib.pfac_build_host_chain(arr, lens, len(patterns), chain.ctypes.data, S.value,
+                                     ctypes.byref(S), ctypes.byref(bad)) == 0
+    return chain.reshape(-1, 2)
+
+
+def walk_all_with_runs(t, chain, text):
+    """Walk every start position taking runs of single-child steps at once
+    (the kernel's deep walk), on the host tables."""
+    codes = [CODE.get(int(b), -1) for b in text]
+    n = len(codes)
+    out = np.zeros(n, dtype=np.int32)
+    total = 0
+    for i in range(n):
+        s, q, best = 0, i, 0
+        while True:
+            cx, cy = int(chain[s, 0]), int(chain[s, 1])
+            L = cx & 15
+            if L >= 2:
+                ok = q + L <= n and all(codes[q + k] == (cx >> (30 - 2 * k)) & 3
+                                        for k in range(L))
+                if not ok:
+                    break
+                s = cy & 0x7FFFFFFF
+                q += L
+                if cy >> 31:
+                    best = int(t["pid"][s])
+                    total += int(t["mult"][s])
+                continue
+            if q >= n or codes[q] < 0:
+                break
+            e = int(t["next"][s, codes[q]])
+            if e == 0:
+                break
+            s = e & 0x7FFFFFFF
+            if e >> 31:
+                best = int(t["pid"][s])
+                total += int(t["mult"][s])
+            q += 1
+        out[i] = best
+    return out, total
+
+
+def test_runs_of_single_child_steps_are_well_formed():
+    """Every run record: its bases follow single-child edges of the next
+    table, every state strictly inside is non-final with one child, it ends
+    where the record says, with the right final bit."""
+    g = W.rng(91)
+    pats = W.random_patterns(200, 10, 60, g) + [b"A" * 50, b"A" * 20, b"ACGT" * 10]
+    rc, _, t = host_table(pats)
+    chain = host_chain(pats)
+    nxt = t["next"]
+    runs = 0
+    for s in range(t["S"]):
+        cx, cy = int(chain[s, 0]), int(chain[s, 1])
+        L = cx & 15
+        if L < 2:
+            continue
+        runs += 1
+        assert L <= 14
+        cur = s
+        for k in range(L):
+            kids = [a for a in range(4) if nxt[cur, a]]
+            assert len(kids) == 1, (s, k)
+            a = (cx >> (30 - 2 * k)) & 3
+            assert kids == [a]
+            e = int(nxt[cur, a])
+            cur = e & 0x7FFFFFFF
+            fin = bool(e >> 31)
+            if k < L - 1:
+                assert not fin and bin(int(sum(1 for b in range(4) if nxt[cur, b]))).count("1")
+        assert cur == (cy & 0x7FFFFFFF) and fin == bool(cy >> 31)
+    assert runs > 100
+
+
+def test_walking_with_runs_reproduces_oracle():
+    g = W.rng(92)
+    text = W.uniform_ascii(4000, g)
+    pats = (W.cut_patterns(text, 60, 12, 60, g) + W.random_patterns(40, 5, 30, g)
+            + [bytes(text[100:160]), bytes(text[100:130]), bytes(text[100:116])])
+    text[700] = ord("N")
+    rc, _, t = host_table(pats)
+    chain = host_chain(pats)
+    m, total = walk_all_with_runs(t, chain, text)
+    m_ref, total_ref = oracle.scan(pats, text)
+    assert np.array_equal(m, m_ref) and total == total_ref
