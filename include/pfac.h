@@ -100,11 +100,20 @@ typedef struct {
                            some pattern has D bases or fewer) */
   uint32_t hash_bits;   /* second filter for the positions that pass the first one,
                            used when every pattern has more than D bases: their first
-                           K = min(shortest pattern, 16) bases hashed into an LDS
-                           bitmap of 2^hash_bits bits (12..17); only windows whose bit
-                           is set (or that hold a non-base) walk on.  0 = library
+                           K = min(shortest pattern, 16) bases hashed twice into an
+                           LDS bitmap of 2^hash_bits bits (12..17); only windows whose
+                           two bits are set (or that hold a non-base) walk on.  0 = library
                            choice, PFAC_HASH_NONE = no second filter */
+  uint32_t walks;       /* where the walks that pass both filters run, one-text calls:
+                           PFAC_WALKS_INLINE = inside the scan kernel, by the wave
+                           that found them; PFAC_WALKS_DEFERRED = the scan kernel
+                           hands each one (start position + its next 64 bases) to a
+                           separate walk kernel, so the streaming scan never waits on
+                           their table reads.  0 = library choice (deferred when the
+                           second filter is on).  Batched calls always walk inline. */
 } pfac_plan;
+
+enum { PFAC_WALKS_INLINE = 1, PFAC_WALKS_DEFERRED = 2 };
 
 enum { PFAC_VARIANT_TILED = 0, PFAC_VARIANT_GLOBAL = 1 };
 #define PFAC_LEVELS_NONE 0xFFFFFFFFu
@@ -250,9 +259,11 @@ int pfac_build_host_image(const char* const* patterns, const uint32_t* lengths, 
  * Host-only: the second-filter bitmap of 2^bits bits (bits = 12..17) the
  * scan kernel uses, for inspection and tests.  K = min(shortest pattern, 16);
  * the key of a K-base window is sum of base_k * 4^(15-k) for k < K (first
- * base most significant, left-aligned in 32 bits, lower bits 0); its bit is
- * h = (key * 0x9E3779B1 mod 2^32) >> (32 - bits), and bit h of word h/32 is
- * set for the first K bases of every pattern.  *k receives K; `words`
+ * base most significant, left-aligned in 32 bits, lower bits 0); its bits
+ * are h1 = (key * 0x9E3779B1 mod 2^32) >> (32 - bits) and
+ * h2 = (key * 0x85EBCA77 mod 2^32) >> (32 - bits), and both (bit h of word
+ * h/32) are set for the first K bases of every pattern; a window passes the
+ * filter when both of its bits are set.  *k receives K; `words`
  * (uint32[2^bits / 32], caller-owned) is written when non-NULL.
  */
 int pfac_build_host_hash(const char* const* patterns, const uint32_t* lengths, uint32_t num,

@@ -14,6 +14,8 @@ PFAC_VARIANT_TILED = 0
 PFAC_VARIANT_GLOBAL = 1
 PFAC_LEVELS_NONE = 0xFFFFFFFF
 PFAC_HASH_NONE = 0xFFFFFFFF
+PFAC_WALKS_INLINE = 1
+PFAC_WALKS_DEFERRED = 2
 
 EXPORTS = (
     "pfac_build_table", "pfac_table_info", "pfac_free_table", "pfac_match",
@@ -28,7 +30,8 @@ EXPORTS = (
 class PfacPlan(ctypes.Structure):
     _fields_ = [("block", ctypes.c_uint32), ("depth", ctypes.c_uint32),
                 ("grid", ctypes.c_uint32), ("variant", ctypes.c_uint32),
-                ("levels", ctypes.c_uint32), ("hash_bits", ctypes.c_uint32)]
+                ("levels", ctypes.c_uint32), ("hash_bits", ctypes.c_uint32),
+                ("walks", ctypes.c_uint32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}

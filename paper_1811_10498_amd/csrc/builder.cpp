@@ -224,9 +224,9 @@ int build_host_table(const char* const* patterns, const uint32_t* lengths, uint3
         im.levels = k + 1;
       }
     }
-    // 6. second filter: hash of the first K bases of every pattern, one
-    //    bitmap per size; a smaller one is the OR of adjacent bits of the
-    //    largest (the hash of `bits` bits is the top bits of the product)
+    // 6. second filter: two hashes of the first K bases of every pattern,
+    //    one bitmap per size; a smaller one is the OR of adjacent bits of the
+    //    largest (a hash of `bits` bits is the top bits of its product)
     out->hash_k = num ? std::min(minl, kHashK) : 0;
     if (out->hash_k) {
       std::vector<uint32_t>& big = out->hash[kHashMaxBits];
@@ -237,7 +237,9 @@ int build_host_table(const char* const* patterns, const uint32_t* lengths, uint3
         for (uint32_t k = 0; k < K; ++k)
           key |= (uint32_t)base_code((uint8_t)patterns[i][k]) << (30 - 2 * k);
         const uint32_t h = (key * kHashMul) >> (32 - kHashMaxBits);
+        const uint32_t h2 = (key * kHashMul2) >> (32 - kHashMaxBits);
         big[h >> 5] |= 1u << (h & 31);
+        big[h2 >> 5] |= 1u << (h2 & 31);
       }
       for (uint32_t b = kHashMinBits; b < kHashMaxBits; ++b) {
         std::vector<uint32_t>& v = out->hash[b];

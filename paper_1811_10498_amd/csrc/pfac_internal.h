@@ -17,11 +17,14 @@ constexpr uint32_t kImageMaxBytes = 160 * 1024;
 
 // Second filter: the first K = min(shortest pattern, kHashK) bases of a
 // window, left-aligned in 32 bits (first base most significant), hashed
-// multiplicatively to `bits` bits (kHashMinBits..kHashMaxBits).
+// multiplicatively to `bits` bits (kHashMinBits..kHashMaxBits) with two
+// multipliers; a window passes when both of its bits are set (a Bloom filter
+// with two hash functions).
 constexpr uint32_t kHashK = 16;
 constexpr uint32_t kHashMinBits = 12;
 constexpr uint32_t kHashMaxBits = 17;
 constexpr uint32_t kHashMul = 0x9E3779B1u;
+constexpr uint32_t kHashMul2 = 0x85EBCA77u;
 
 // Longest run of single-child trie steps a walk takes at once.
 constexpr uint32_t kChainMax = 14;

@@ -65,6 +65,18 @@ struct Slot {
   int32_t pid;
 };
 
+// A walk handed from the scan kernel to the walk kernel: its start position
+// and a copy of the next kWindow bases (2-bit codes, 16 per word, first base
+// in the top bits of codes[0]; invalid bits, base k in bit k of inv).
+constexpr uint32_t kWindow = 64;
+struct WalkEntry {
+  uint32_t pos;
+  uint32_t slow;       // 1: a non-base within the first D bases (walk from the root)
+  uint32_t codes[4];
+  uint32_t inv[2];
+};
+static_assert(sizeof(WalkEntry) == 32, "walk entry layout");
+
 // Parameters of the scan kernel (one table per launch).
 struct ScanParams {
   const uint32_t* next;
@@ -101,6 +113,12 @@ struct ScanParams {
   uint32_t* tile_hits;            // [tiles]
   unsigned long long* tile_occ;   // [tiles]
   Slot* slots;                    // [tiles * kSlot] or nullptr
+  // deferred walks (one-text launches): every wave owns wq_cap entries of wq
+  // (wave w from w*wq_cap) and writes how many it used to wq_count[w]
+  uint32_t defer;
+  uint32_t wq_cap;
+  WalkEntry* wq;
+  uint32_t* wq_count;
 };
 
 // ---------------------------------------------------------------- device helpers
@@ -363,7 +381,7 @@ __device__ __forceinline__ int32_t deep_walk(uint32_t e, uint32_t D, uint32_t ld
 
 // Second filter for one queued entry (see deep_walk for the entry format):
 // true when the walk must go on -- the window holds a non-base within its
-// first K bases, or the hash of its first K bases has its bit set.  A window
+// first K bases, or both hashes of its first K bases have their bits set.  A window
 // whose first K bases are no pattern's first K bases can only fail the test
 // (every pattern has at least K bases), so a cleared bit proves the walk
 // reports nothing.
@@ -378,7 +396,8 @@ __device__ __forceinline__ bool hash_pass(uint32_t e, const uint32_t* __restrict
   const uint32_t key =
       (uint32_t)(((((uint64_t)pk[wi] << 32) | pk[wi + 1]) << (2 * (qt & 15u))) >> 32) & kmask;
   const uint32_t h = (key * kHashMul) >> shift;
-  return (hl[h >> 5] >> (h & 31u)) & 1u;
+  const uint32_t h2 = (key * kHashMul2) >> shift;
+  return (hl[h >> 5] >> (h & 31u)) & (hl[h2 >> 5] >> (h2 & 31u)) & 1u;
 }
 
 // Text of one wave tile: bases [t0, t0+span) of one text, span = TILE + halo.
@@ -687,8 +706,14 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
   const uint32_t bsel = ((7u - k8) << 24) | ((6u - k8) << 16) | ((5u - k8) << 8) | (4u - k8);
   const uint32_t sh4 = 4u * (lane & 7u);          // its bit in the invalid-bit word
   const uint64_t nwaves = (uint64_t)gridDim.x * (BLOCK / 64);
-  uint64_t lt = (uint64_t)blockIdx.x * (BLOCK / 64) + wave;
-  if (lt >= p.local_tiles) return;
+  const uint32_t gwave = blockIdx.x * (BLOCK / 64) + wave;
+  uint64_t lt = gwave;
+  uint32_t wq_n = 0;                                // deferred walks of this wave
+  WalkEntry* wq = (SINGLE && p.defer) ? p.wq + (uint64_t)gwave * p.wq_cap : nullptr;
+  if (lt >= p.local_tiles) {
+    if (SINGLE && p.defer && lane == 0) p.wq_count[gwave] = 0;
+    return;
+  }
   TileLoc cur = locate<SINGLE>(p, lt);
   Prefetch pf{};
   if (!GLOBAL)
@@ -809,10 +834,39 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
         }
         wave_sync();
       }
+      // ---- one-text launches may hand the walks to the walk kernel: each
+      //      lane copies an entry into the wave's own part of the buffer;
+      //      the entries that do not fit there are walked here
+      uint32_t ndef = 0;
+      if (SINGLE && !GLOBAL && p.defer && nwalk > 0) {
+        const uint32_t wbase = wq_n;
+        ndef = min(nwalk, p.wq_cap - wq_n);
+        wq_n += ndef;
+        #pragma unroll 1
+        for (uint32_t j = lane; j < ndef; j += 64) {
+          const uint32_t i = hashed ? (uint32_t)queue2[j] : j;
+          const uint32_t e = queue[i];
+          const uint32_t qt = e & 0x7FFFu;
+          const uint32_t wi = qt >> 4, sh = 2 * (qt & 15u);
+          const uint32_t ii = qt >> 5, s5 = qt & 31u;
+          u32x4 c;
+          c.x = (uint32_t)(((((uint64_t)pk[wi] << 32) | pk[wi + 1]) << sh) >> 32);
+          c.y = (uint32_t)(((((uint64_t)pk[wi + 1] << 32) | pk[wi + 2]) << sh) >> 32);
+          c.z = (uint32_t)(((((uint64_t)pk[wi + 2] << 32) | pk[wi + 3]) << sh) >> 32);
+          c.w = (uint32_t)(((((uint64_t)pk[wi + 3] << 32) | pk[wi + 4]) << sh) >> 32);
+          const uint32_t inv0 = __builtin_amdgcn_alignbit(iv[ii + 1], iv[ii], s5);
+          const uint32_t inv1 = __builtin_amdgcn_alignbit(iv[ii + 2], iv[ii + 1], s5);
+          // entry = {pos, slow, codes[0..1]}, {codes[2..3], inv[0..1]}
+          u32x4* dst = reinterpret_cast<u32x4*>(wq + wbase + j);
+          dst[0] = u32x4{(uint32_t)(t0 + qt), (e >> 15) & 1u, c.x, c.y};
+          dst[1] = u32x4{c.z, c.w, inv0, inv1};
+          res[i] = 0;       // the walk kernel writes its result
+        }
+      }
       // ---- walk them with all lanes
       uint32_t nz = 0;
       #pragma unroll 1
-      for (uint32_t j = lane; j < nwalk; j += 64) {
+      for (uint32_t j = ndef + lane; j < nwalk; j += 64) {
         const uint32_t i = hashed ? (uint32_t)queue2[j] : j;
         const uint32_t e = queue[i];
         const uint32_t qt = e & 0x7FFFu;                 // index within the tile
@@ -896,6 +950,104 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
     lt = lt_next;
     cur = nxt;
   }
+  if (SINGLE && p.defer && lane == 0) p.wq_count[gwave] = wq_n;
+}
+
+// Parameters of the walk kernel (deferred walks of a one-text launch).
+struct WalkParams {
+  const WalkEntry* wq;
+  const uint32_t* wq_count;       // per scan wave
+  uint32_t nwaves;
+  uint32_t wq_cap;                // entries per scan wave
+  uint32_t D;
+  uint32_t tile;
+  uint32_t enc;
+  const uint32_t* next;
+  const OutEntry* out;
+  const uint32_t* chain;
+  const uint32_t* jump;
+  const OutEntry* jres;
+  const uint8_t* text;
+  uint64_t n;
+  int32_t* match;
+  uint32_t* tile_hits;
+  unsigned long long* tile_occ;
+  Slot* slots;
+};
+
+// The deferred walks, one per lane: the depth-D jump entry of the window,
+// then the walk with path compression over the copied 64 bases, continued on
+// the text in global memory past them.  A pattern found is written to the
+// dense output and appended to its tile's hit slots (the scatter kernel
+// orders each tile's slots by position).
+__global__ __launch_bounds__(256) void pfac_walk_kernel(WalkParams p) {
+  for (uint32_t r = blockIdx.x; r < p.nwaves; r += gridDim.x)
+  for (uint32_t k = threadIdx.x; k < min(p.wq_count[r], p.wq_cap); k += 256) {
+    const WalkEntry* we = p.wq + (uint64_t)r * p.wq_cap + k;
+    const u32x4 a = reinterpret_cast<const u32x4*>(we)[0];
+    const u32x4 b = reinterpret_cast<const u32x4*>(we)[1];
+    const uint32_t pos = a.x;
+    const uint32_t c0 = a.z, c1 = a.w, c2 = b.x, c3 = b.y;
+    const uint64_t ivall = ((uint64_t)b.w << 32) | b.z;
+    int32_t best = 0;
+    unsigned long long occ = 0;
+    uint32_t s = 0, q = 0;
+    bool live = true;
+    if (!a.y) {
+      const uint32_t x = c0 >> (32 - 2 * p.D);
+      const uint32_t jj = p.jump[x];
+      if (jj & kFinalBit) {
+        const OutEntry o = p.jres[x];
+        best = o.pid;
+        occ += o.mult;
+      }
+      s = jj & kStateMask;
+      q = p.D;
+      live = s != 0;
+    }
+    while (live) {
+      if (q + 16 > kWindow) {
+        // past the copied bases: go on reading the text itself
+        walk<true>(s, (uint64_t)pos + q, nullptr, nullptr, p.next, p.out, p.text, p.n, p.enc,
+                   best, occ);
+        break;
+      }
+      const uint32_t wk = q >> 4, sh = 2 * (q & 15u);
+      const uint32_t hi = wk == 0 ? c0 : wk == 1 ? c1 : wk == 2 ? c2 : c3;
+      const uint32_t lo = wk == 0 ? c1 : wk == 1 ? c2 : wk == 2 ? c3 : 0u;
+      const uint32_t win = (uint32_t)(((((uint64_t)hi << 32) | lo) << sh) >> 32);
+      const uint32_t ivw = (uint32_t)(ivall >> q);
+      const u32x2 ch = *reinterpret_cast<const u32x2*>(p.chain + 2ull * s);
+      const uint32_t e = p.next[(uint64_t)s * 4 + (win >> 30)];
+      const uint32_t len = ch.x & 15u;
+      if (len >= 2) {
+        if ((ivw & ((1u << len) - 1u)) | ((win ^ ch.x) & (0xFFFFFFFFu << (32 - 2 * len)))) break;
+        s = ch.y & kStateMask;
+        q += len;
+        if (ch.y & kFinalBit) {
+          const OutEntry o = p.out[s];
+          best = o.pid;
+          occ += o.mult;
+        }
+        continue;
+      }
+      if ((ivw & 1u) || e == 0) break;
+      s = e & kStateMask;
+      if (e & kFinalBit) {
+        const OutEntry o = p.out[s];
+        best = o.pid;
+        occ += o.mult;
+      }
+      ++q;
+    }
+    const uint64_t gt = pos / p.tile;
+    if (best) {
+      if (p.match) p.match[pos] = best;
+      const uint32_t slot = atomicAdd(&p.tile_hits[gt], 1u);
+      if (p.slots && slot < kSlot) p.slots[gt * kSlot + slot] = Slot{pos, best};
+    }
+    if (occ) atomicAdd(&p.tile_occ[gt], occ);
+  }
 }
 
 // Per block of kRedTiles tiles: sums of hits and occurrences.  The last
@@ -976,7 +1128,7 @@ __global__ __launch_bounds__(1024) void pfac_reduce_kernel(
 // Parameters of the scatter kernel.
 struct ScatterParams {
   const uint32_t* tile_hits;
-  const Slot* slots;
+  Slot* slots;
   const unsigned long long* block_prefix;
   uint64_t tiles;
   uint32_t tile;                  // start positions per tile
@@ -1050,8 +1202,20 @@ __global__ __launch_bounds__(1024) void pfac_scatter_kernel(ScatterParams p) {
     if (h[k] && off < p.hit_cap) {
       if (h[k] <= kSlot) {
         const uint32_t text = p.single ? 0u : text_of_tile(p, t);
+        // order the slots by position (hits found by the walk kernel were
+        // appended after the scan kernel's, in no particular order)
+        Slot* sl = p.slots + t * kSlot;
+        for (uint32_t j = 1; j < h[k]; ++j) {
+          const Slot key = sl[j];
+          uint32_t m = j;
+          while (m > 0 && sl[m - 1].pos > key.pos) {
+            sl[m] = sl[m - 1];
+            --m;
+          }
+          sl[m] = key;
+        }
         for (uint32_t j = 0; j < h[k]; ++j) {
-          const Slot s = p.slots[t * kSlot + j];
+          const Slot s = sl[j];
           put_hit(p, off + j, text, s.pos, s.pid);
         }
       } else {
@@ -1177,6 +1341,10 @@ struct Workspace {
   uint8_t* stage = nullptr;        // pinned host copy of `batch` being uploaded
   hipEvent_t staged = nullptr;     // recorded after the upload that read `stage`
   bool staged_pending = false;
+  WalkEntry* walk = nullptr;       // deferred walks of one-text calls
+  uint64_t walk_cap = 0;           // entries
+  uint32_t* walk_count = nullptr;  // per scan wave
+  uint64_t walk_waves = 0;
 };
 
 static std::map<std::pair<int, void*>, Workspace*> g_ws;
@@ -1245,6 +1413,29 @@ static int ensure_batch(Workspace* ws, uint64_t bytes, hipStream_t stream) {
   }
   ws->stage = static_cast<uint8_t*>(st);
   ws->batch_cap = cap;
+  return PFAC_OK;
+}
+
+// Room for `cap` deferred walks and `waves` per-wave counts (grown, never
+// shrunk).
+static int ensure_walk(Workspace* ws, uint64_t cap, uint64_t waves, hipStream_t stream) {
+  if (cap <= ws->walk_cap && waves <= ws->walk_waves && ws->walk) return PFAC_OK;
+  if (ws->walk) {
+    if (hipStreamSynchronize(stream) != hipSuccess) return PFAC_E_HIP;
+    (void)hipFree(ws->walk);
+    ws->walk = nullptr;
+    ws->walk_count = nullptr;
+    ws->walk_cap = ws->walk_waves = 0;
+  }
+  cap = std::max(cap, ws->walk_cap);
+  waves = std::max(waves, ws->walk_waves);
+  const uint64_t o_count = (cap * sizeof(WalkEntry) + 255) / 256 * 256;
+  void* m = nullptr;
+  if (hipMalloc(&m, o_count + waves * 4) != hipSuccess) return PFAC_E_NOMEM;
+  ws->walk = static_cast<WalkEntry*>(m);
+  ws->walk_count = reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(m) + o_count);
+  ws->walk_cap = cap;
+  ws->walk_waves = waves;
   return PFAC_OK;
 }
 
@@ -1326,11 +1517,12 @@ static uint32_t auto_depth(const HostTable& h) {
 }
 
 // Second-filter size the library picks: the smallest bitmap with at most
-// one bit in 16 set by the patterns, else the largest one while at most 40 %
-// of it is set (beyond that it passes too much to pay for its lookups).
+// one bit in 16 set by the patterns (two per pattern), else the largest one
+// while the patterns number at most 40 % of its bits (beyond that it passes
+// too much to pay for its lookups).
 static uint32_t auto_hash_bits(const HostTable& h) {
   for (uint32_t b = kHashMinBits; b <= kHashMaxBits; ++b)
-    if ((uint64_t)h.num_patterns * 16 <= (1ull << b)) return b;
+    if ((uint64_t)h.num_patterns * 32 <= (1ull << b)) return b;
   if ((double)h.num_patterns <= 0.4 * (double)(1u << kHashMaxBits)) return kHashMaxBits;
   return PFAC_HASH_NONE;
 }
@@ -1366,7 +1558,7 @@ static int place_image(const HostTable& h, uint32_t D, uint32_t hw, uint32_t hal
 static int resolve_plan(const pfac_plan* in, const HostTable& h, int dev, pfac_plan* out) {
   const DeviceInfo di = device_info(dev);
   if (!di.ok) return PFAC_E_NODEV;
-  pfac_plan p = in ? *in : pfac_plan{0, 0, 0, 0, 0, 0};
+  pfac_plan p = in ? *in : pfac_plan{0, 0, 0, 0, 0, 0, 0};
   if (p.variant != PFAC_VARIANT_TILED && p.variant != PFAC_VARIANT_GLOBAL) return PFAC_E_ARG;
   const uint32_t halo = halo_for(h.max_len);
   if (p.variant == PFAC_VARIANT_TILED && halo > kMaxHalo) {
@@ -1396,10 +1588,13 @@ static int resolve_plan(const pfac_plan* in, const HostTable& h, int dev, pfac_p
   // shallower depth
   if (p.block == 0) p.block = 1024;
   if (p.block != 256 && p.block != 512 && p.block != 768 && p.block != 1024) return PFAC_E_ARG;
+  if (p.walks != 0 && p.walks != PFAC_WALKS_INLINE && p.walks != PFAC_WALKS_DEFERRED)
+    return PFAC_E_ARG;
   if (p.variant == PFAC_VARIANT_GLOBAL) {
     p.depth = 0;
     p.levels = PFAC_LEVELS_NONE;
     p.hash_bits = PFAC_HASH_NONE;
+    p.walks = PFAC_WALKS_INLINE;
     *out = p;
     return PFAC_OK;
   }
@@ -1424,6 +1619,10 @@ static int resolve_plan(const pfac_plan* in, const HostTable& h, int dev, pfac_p
       const int rc = place_image(h, D, hw, halo, budget, &p);
       if (rc == PFAC_OK) {
         p.hash_bits = hb;
+        // walks that survive the second filter are few: hand them to the walk
+        // kernel so the streaming scan never waits on their table reads
+        if (p.walks == 0)
+          p.walks = hb != PFAC_HASH_NONE ? PFAC_WALKS_DEFERRED : PFAC_WALKS_INLINE;
         *out = p;
         return PFAC_OK;
       }
@@ -1475,16 +1674,26 @@ static uint64_t grid_for(ScanFn fn, const pfac_plan& plan, uint32_t lds, int dev
   return g ? g : 1;
 }
 
+// Kernel, dynamic LDS and grid of a scan launch.
+static int scan_shape(const ScanParams& sp, const pfac_plan& plan, int dev, ScanFn* fn,
+                      uint32_t* lds, uint64_t* grid) {
+  const bool global = plan.variant == PFAC_VARIANT_GLOBAL;
+  *fn = pick_scan(plan.block, global, sp.D, sp.single != 0);
+  if (!*fn) return PFAC_E_ARG;
+  *lds = global ? 4u * (plan.block / 64) * kGlobalWaveWords
+                : scan_lds_bytes(plan.block, sp.image_words + (sp.hash_on ? sp.hash_words : 0u),
+                                 sp.halo, sp.single ? kTileSingle : kTileBatch);
+  *grid = grid_for(*fn, plan, *lds, dev, sp.local_tiles);
+  return PFAC_OK;
+}
+
 static int launch_scan(const ScanParams& sp, const pfac_plan& plan, int dev, hipStream_t stream) {
   if (sp.local_tiles == 0) return PFAC_OK;
-  const bool global = plan.variant == PFAC_VARIANT_GLOBAL;
-  ScanFn fn = pick_scan(plan.block, global, sp.D, sp.single != 0);
-  if (!fn) return PFAC_E_ARG;
-  const uint32_t lds =
-      global ? 4u * (plan.block / 64) * kGlobalWaveWords
-             : scan_lds_bytes(plan.block, sp.image_words + (sp.hash_on ? sp.hash_words : 0u),
-                              sp.halo, sp.single ? kTileSingle : kTileBatch);
-  const uint64_t grid = grid_for(fn, plan, lds, dev, sp.local_tiles);
+  ScanFn fn;
+  uint32_t lds;
+  uint64_t grid;
+  const int rc = scan_shape(sp, plan, dev, &fn, &lds, &grid);
+  if (rc) return rc;
   hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(plan.block), lds, stream, sp);
   return hipGetLastError() == hipSuccess ? PFAC_OK : PFAC_E_HIP;
 }
@@ -1710,8 +1919,54 @@ int pfac_match(const pfac_table* t, const void* d_text, uint64_t n, int enc, int
   sp.tile_hits = ws->tile_hits;
   sp.tile_occ = ws->tile_occ;
   sp.slots = d_hits ? ws->slots : nullptr;
+  const bool defer = pl.variant == PFAC_VARIANT_TILED && pl.walks == PFAC_WALKS_DEFERRED;
+  uint32_t nwaves = 0;
+  if (defer) {
+    // every scan wave gets room for 16 walks per tile it will scan
+    ScanFn fn;
+    uint32_t lds;
+    uint64_t grid;
+    rc = scan_shape(sp, pl, dev, &fn, &lds, &grid);
+    if (rc) return rc;
+    nwaves = (uint32_t)(grid * (pl.block / 64));
+    const uint64_t per = std::max<uint64_t>(16 * ((tiles + nwaves - 1) / nwaves), 64);
+    {
+      std::lock_guard<std::mutex> lk(g_mu);
+      rc = ensure_walk(ws, per * nwaves, nwaves, stream);
+    }
+    if (rc) return rc;
+    sp.defer = 1;
+    sp.wq = ws->walk;
+    sp.wq_count = ws->walk_count;
+    sp.wq_cap = (uint32_t)per;
+  }
   rc = launch_scan(sp, pl, dev, stream);
   if (rc) return rc;
+  if (defer) {
+    WalkParams wp;
+    memset(&wp, 0, sizeof(wp));
+    wp.wq = ws->walk;
+    wp.wq_count = ws->walk_count;
+    wp.nwaves = nwaves;
+    wp.wq_cap = sp.wq_cap;
+    wp.D = pl.depth;
+    wp.tile = kTileSingle;
+    wp.enc = (uint32_t)enc;
+    wp.next = t->dev.next;
+    wp.out = t->dev.out;
+    wp.chain = t->dev.chain;
+    wp.jump = t->dev.jump[pl.depth];
+    wp.jres = t->dev.jres[pl.depth];
+    wp.text = sp.text;
+    wp.n = n;
+    wp.match = d_match;
+    wp.tile_hits = ws->tile_hits;
+    wp.tile_occ = ws->tile_occ;
+    wp.slots = d_hits ? ws->slots : nullptr;
+    const uint32_t grid = (uint32_t)std::max(1, 8 * device_info(dev).cus);
+    hipLaunchKernelGGL(pfac_walk_kernel, dim3(grid), dim3(256), 0, stream, wp);
+    if (hipGetLastError() != hipSuccess) return PFAC_E_HIP;
+  }
   ScatterParams sc;
   memset(&sc, 0, sizeof(sc));
   sc.hits = d_hits;
@@ -1873,6 +2128,7 @@ static void free_workspace(Workspace* ws) {
   if (ws->batch) (void)hipFree(ws->batch);
   if (ws->stage) (void)hipHostFree(ws->stage);
   if (ws->staged) (void)hipEventDestroy(ws->staged);
+  if (ws->walk) (void)hipFree(ws->walk);
   *ws = Workspace();
 }
 

@@ -466,3 +466,59 @@ def test_long_single_child_runs(plan):
     print("patterns", len(pats), "text", text.size, "plan", plan, flush=True)
     res = _gpu(pats, text, plan=plan)
     _check(res, pats, text)
+
+
+WALK_PLANS = [
+    dict(walks=pf.PFAC_WALKS_INLINE),
+    dict(walks=pf.PFAC_WALKS_DEFERRED),
+    dict(walks=pf.PFAC_WALKS_DEFERRED, hash_bits=pf.PFAC_HASH_NONE),   # many, overflows
+    dict(walks=pf.PFAC_WALKS_DEFERRED, block=1024, depth=8, hash_bits=12),
+]
+
+
+@pytest.mark.parametrize("plan", range(len(WALK_PLANS)))
+def test_deferred_walks_match_inline(plan):
+    """Walks handed to the walk kernel (start + 64 copied bases, continued on
+    the text past them) give the oracle's results: patterns up to 120 bases,
+    occurrences near tile and text ends, non-bases inside copied windows, and
+    a plan whose walks overflow the hand-off buffer (the rest walk inline)."""
+    w = W.plain_workload(1, n=2_500_001, num_patterns=2500)
+    g = W.rng(93)
+    longs = W.cut_patterns(w.text, 40, 65, 120, g)
+    pats = w.patterns + longs
+    text = w.text.copy()
+    m0, _ = oracle.scan(pats, text, threads=8)
+    occ = np.nonzero(m0)[0]
+    for q in g.choice(occ, size=min(30, occ.size), replace=False):
+        off = int(g.integers(16, 70))
+        if q + off < text.size:
+            text[q + off] = ord("N")
+    for t0 in (2048 * 7, 2048 * 300):        # plant long patterns across tile edges
+        p = longs[t0 % len(longs)]
+        text[t0 - 30:t0 - 30 + len(p)] = np.frombuffer(p, dtype=np.uint8)
+    p = longs[0]
+    text[-40:] = np.frombuffer(p[:40], dtype=np.uint8)       # cut short by the end
+    print("plan", WALK_PLANS[plan], flush=True)
+    res = _gpu(pats, text, plan=WALK_PLANS[plan])
+    _check(res, pats, text)
+
+
+def test_deferred_walks_with_optional_outputs():
+    w = W.plain_workload(1, n=1_000_003, num_patterns=1500)
+    tab = pf.Table(w.patterns)
+    dt = torch.from_numpy(w.text).to(DEV)
+    m_ref, total_ref = oracle.scan(w.patterns, w.text, threads=8)
+    pos, ids = oracle.hits_of(m_ref)
+    plan = dict(walks=pf.PFAC_WALKS_DEFERRED)
+    r1 = pf.match(tab, dt, plan=plan, dense=False, hit_cap=w.n)
+    r2 = pf.match(tab, dt, plan=plan, hits=False)
+    r3 = pf.match(tab, dt, plan=plan, dense=False, hits=False)
+    torch.cuda.synchronize()
+    h = r1.hit_list()
+    assert np.array_equal(h[:, 0], pos) and np.array_equal(h[:, 1], ids)
+    assert np.array_equal(r2.match.cpu().numpy(), m_ref)
+    assert r1.total() == r2.total() == r3.total() == total_ref
+    assert r3.num_hits() == pos.size
+    assert tab.default_plan(w.n)["walks"] == pf.PFAC_WALKS_DEFERRED
+    with pytest.raises(pf.PfacError):
+        pf.match(tab, dt, plan=dict(walks=3))

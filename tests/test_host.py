@@ -289,8 +289,9 @@ def test_lds_image_navigation_matches_next_table(D, npat, lmin, lmax):
 @pytest.mark.parametrize("bits", [12, 14, 17])
 def test_second_filter_bitmap_holds_every_pattern_prefix(bits):
     """The hash bitmap (its definition is part of the public header) has the
-    bit of the first K bases of every pattern; smaller bitmaps are the OR-fold
-    of the largest; random windows pass at about the fraction of set bits."""
+    two bits of the first K bases of every pattern; smaller bitmaps are the
+    OR-fold of the largest; random windows pass at about the square of the
+    fraction of set bits."""
     import ctypes
     from paper_1811_10498_amd import _lib as L
     lib = L.lib()
@@ -307,24 +308,27 @@ def test_second_filter_bitmap_holds_every_pattern_prefix(bits):
         return words, k.value
     words, K = get(bits)
     assert K == 16
-    def h(key, b):
-        return ((key * 0x9E3779B1) & 0xFFFFFFFF) >> (32 - b)
+    def h(key, b, mul=0x9E3779B1):
+        return ((key * mul) & 0xFFFFFFFF) >> (32 - b)
     code = {ord("A"): 0, ord("C"): 1, ord("G"): 2, ord("T"): 3}
     for p in pats:
         key = 0
         for i in range(K):
             key |= code[p[i]] << (30 - 2 * i)
-        x = h(key, bits)
-        assert (words[x >> 5] >> (x & 31)) & 1
+        for mul in (0x9E3779B1, 0x85EBCA77):
+            x = h(key, bits, mul)
+            assert (words[x >> 5] >> (x & 31)) & 1
     big, _ = get(17)
     bigbits = np.unpackbits(big.view(np.uint8), bitorder="little").astype(bool)
     folded = bigbits.reshape(1 << bits, 1 << (17 - bits)).any(axis=1)
     mine = np.unpackbits(words.view(np.uint8), bitorder="little").astype(bool)
     assert np.array_equal(folded, mine)
     keys = g.integers(0, 1 << 32, size=20000, dtype=np.uint64)
-    xs = ((keys * np.uint64(0x9E3779B1)) & np.uint64(0xFFFFFFFF)) >> np.uint64(32 - bits)
-    rate = mine[xs.astype(np.int64)].mean()
-    assert abs(rate - mine.mean()) < 0.03
+    def hv(mul):
+        x = ((keys * np.uint64(mul)) & np.uint64(0xFFFFFFFF)) >> np.uint64(32 - bits)
+        return mine[x.astype(np.int64)]
+    rate = (hv(0x9E3779B1) & hv(0x85EBCA77)).mean()      # both bits: about f^2
+    assert abs(rate - mine.mean() ** 2) < 0.03
 
 
 def test_second_filter_k_is_shortest_pattern_capped_at_16():
