@@ -981,9 +981,12 @@ struct WalkParams {
 // dense output and appended to its tile's hit slots (the scatter kernel
 // orders each tile's slots by position).
 __global__ __launch_bounds__(256) void pfac_walk_kernel(WalkParams p) {
-  for (uint32_t r = blockIdx.x; r < p.nwaves; r += gridDim.x)
-  for (uint32_t k = threadIdx.x; k < min(p.wq_count[r], p.wq_cap); k += 256) {
-    const WalkEntry* we = p.wq + (uint64_t)r * p.wq_cap + k;
+  // one thread per entry slot of every scan wave; slots past a wave's count
+  // are empty
+  const uint64_t slot = (uint64_t)blockIdx.x * 256 + threadIdx.x;
+  const uint32_t r = (uint32_t)(slot / p.wq_cap), k = (uint32_t)(slot % p.wq_cap);
+  if (r < p.nwaves && k < p.wq_count[r]) {
+    const WalkEntry* we = p.wq + slot;
     const u32x4 a = reinterpret_cast<const u32x4*>(we)[0];
     const u32x4 b = reinterpret_cast<const u32x4*>(we)[1];
     const uint32_t pos = a.x;
@@ -1006,7 +1009,7 @@ __global__ __launch_bounds__(256) void pfac_walk_kernel(WalkParams p) {
       live = s != 0;
     }
     while (live) {
-      if (q + 16 > kWindow) {
+      if (q >= kWindow) {
         // past the copied bases: go on reading the text itself
         walk<true>(s, (uint64_t)pos + q, nullptr, nullptr, p.next, p.out, p.text, p.n, p.enc,
                    best, occ);
@@ -1021,6 +1024,12 @@ __global__ __launch_bounds__(256) void pfac_walk_kernel(WalkParams p) {
       const uint32_t e = p.next[(uint64_t)s * 4 + (win >> 30)];
       const uint32_t len = ch.x & 15u;
       if (len >= 2) {
+        if (q + len > kWindow) {
+          // the run reaches past the copied bases
+          walk<true>(s, (uint64_t)pos + q, nullptr, nullptr, p.next, p.out, p.text, p.n, p.enc,
+                     best, occ);
+          break;
+        }
         if ((ivw & ((1u << len) - 1u)) | ((win ^ ch.x) & (0xFFFFFFFFu << (32 - 2 * len)))) break;
         s = ch.y & kStateMask;
         q += len;
@@ -1963,8 +1972,9 @@ int pfac_match(const pfac_table* t, const void* d_text, uint64_t n, int enc, int
     wp.tile_hits = ws->tile_hits;
     wp.tile_occ = ws->tile_occ;
     wp.slots = d_hits ? ws->slots : nullptr;
-    const uint32_t grid = (uint32_t)std::max(1, 8 * device_info(dev).cus);
-    hipLaunchKernelGGL(pfac_walk_kernel, dim3(grid), dim3(256), 0, stream, wp);
+    const uint64_t slots = (uint64_t)nwaves * wp.wq_cap;
+    hipLaunchKernelGGL(pfac_walk_kernel, dim3((uint32_t)((slots + 255) / 256)), dim3(256), 0,
+                       stream, wp);
     if (hipGetLastError() != hipSuccess) return PFAC_E_HIP;
   }
   ScatterParams sc;
