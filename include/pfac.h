@@ -101,7 +101,7 @@ typedef struct {
   uint32_t hash_bits;   /* second filter for the positions that pass the first one,
                            used when every pattern has more than D bases: their first
                            K = min(shortest pattern, 16) bases hashed twice into an
-                           LDS bitmap of 2^hash_bits bits (12..17); only windows whose
+                           LDS bitmap of 2^hash_bits bits (12..18); only windows whose
                            two bits are set (or that hold a non-base) walk on.  0 = library
                            choice, PFAC_HASH_NONE = no second filter */
   uint32_t walks;       /* where the walks that pass both filters run, one-text calls:
@@ -256,7 +256,7 @@ int pfac_build_host_image(const char* const* patterns, const uint32_t* lengths, 
                           uint64_t* num_words, int64_t* bad_index);
 
 /*
- * Host-only: the second-filter bitmap of 2^bits bits (bits = 12..17) the
+ * Host-only: the second-filter bitmap of 2^bits bits (bits = 12..18) the
  * scan kernel uses, for inspection and tests.  K = min(shortest pattern, 16);
  * the key of a K-base window is sum of base_k * 4^(15-k) for k < K (first
  * base most significant, left-aligned in 32 bits, lower bits 0); its bits

@@ -22,7 +22,7 @@ constexpr uint32_t kImageMaxBytes = 160 * 1024;
 // with two hash functions).
 constexpr uint32_t kHashK = 16;
 constexpr uint32_t kHashMinBits = 12;
-constexpr uint32_t kHashMaxBits = 17;
+constexpr uint32_t kHashMaxBits = 18;
 constexpr uint32_t kHashMul = 0x9E3779B1u;
 constexpr uint32_t kHashMul2 = 0x85EBCA77u;
 

@@ -1586,10 +1586,13 @@ static int resolve_plan(const pfac_plan* in, const HostTable& h, int dev, pfac_p
   const bool auto_d = p.depth == 0;
   if (p.variant == PFAC_VARIANT_TILED && p.levels == 0 && p.hash_bits == 0) {
     const uint32_t D = p.depth ? p.depth : std::min<uint32_t>(auto_depth(h), 9u);
-    if (h.hash_k > D && auto_hash_bits(h) != PFAC_HASH_NONE) {
+    const uint32_t hb = auto_hash_bits(h);
+    if (h.hash_k > D && hb != PFAC_HASH_NONE) {
       p.levels = PFAC_LEVELS_NONE;
       p.depth = D;
-      if (p.block == 0) p.block = 512;
+      // two 512-thread groups share a CU while bitmap and filter take at most
+      // 48 KB; a larger filter goes with one 1024-thread group
+      if (p.block == 0) p.block = hb <= 17 ? 512 : 1024;
     }
   }
   // with the workgroup size left to the library, a depth whose image does
@@ -1931,14 +1934,16 @@ int pfac_match(const pfac_table* t, const void* d_text, uint64_t n, int enc, int
   const bool defer = pl.variant == PFAC_VARIANT_TILED && pl.walks == PFAC_WALKS_DEFERRED;
   uint32_t nwaves = 0;
   if (defer) {
-    // every scan wave gets room for 16 walks per tile it will scan
+    // every scan wave gets room for 4 walks per tile it will scan (about
+    // four times what the second filter lets through on random-like text;
+    // walks beyond it run inline); the walk kernel has a thread per slot
     ScanFn fn;
     uint32_t lds;
     uint64_t grid;
     rc = scan_shape(sp, pl, dev, &fn, &lds, &grid);
     if (rc) return rc;
     nwaves = (uint32_t)(grid * (pl.block / 64));
-    const uint64_t per = std::max<uint64_t>(16 * ((tiles + nwaves - 1) / nwaves), 64);
+    const uint64_t per = std::max<uint64_t>(4 * ((tiles + nwaves - 1) / nwaves), 64);
     {
       std::lock_guard<std::mutex> lk(g_mu);
       rc = ensure_walk(ws, per * nwaves, nwaves, stream);

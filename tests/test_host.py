@@ -286,7 +286,7 @@ def test_lds_image_navigation_matches_next_table(D, npat, lmin, lmax):
     assert checked > 50
 
 
-@pytest.mark.parametrize("bits", [12, 14, 17])
+@pytest.mark.parametrize("bits", [12, 14, 18])
 def test_second_filter_bitmap_holds_every_pattern_prefix(bits):
     """The hash bitmap (its definition is part of the public header) has the
     two bits of the first K bases of every pattern; smaller bitmaps are the
@@ -318,9 +318,9 @@ def test_second_filter_bitmap_holds_every_pattern_prefix(bits):
         for mul in (0x9E3779B1, 0x85EBCA77):
             x = h(key, bits, mul)
             assert (words[x >> 5] >> (x & 31)) & 1
-    big, _ = get(17)
+    big, _ = get(18)
     bigbits = np.unpackbits(big.view(np.uint8), bitorder="little").astype(bool)
-    folded = bigbits.reshape(1 << bits, 1 << (17 - bits)).any(axis=1)
+    folded = bigbits.reshape(1 << bits, 1 << (18 - bits)).any(axis=1)
     mine = np.unpackbits(words.view(np.uint8), bitorder="little").astype(bool)
     assert np.array_equal(folded, mine)
     keys = g.integers(0, 1 << 32, size=20000, dtype=np.uint64)
