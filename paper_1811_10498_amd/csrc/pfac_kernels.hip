@@ -114,11 +114,10 @@ struct ScanParams {
   unsigned long long* tile_occ;   // [tiles]
   Slot* slots;                    // [tiles * kSlot] or nullptr
   // deferred walks (one-text launches): every wave owns wq_cap entries of wq
-  // (wave w from w*wq_cap) and writes how many it used to wq_count[w]
+  // (wave w from w*wq_cap) and walks them after its last tile
   uint32_t defer;
   uint32_t wq_cap;
   WalkEntry* wq;
-  uint32_t* wq_count;
 };
 
 // ---------------------------------------------------------------- device helpers
@@ -612,6 +611,8 @@ __host__ __device__ constexpr uint32_t iv_words(uint32_t tile, uint32_t halo) {
 constexpr uint32_t kGlobalWaveWords = kQueue + kQueue / 2;
 // Trie-level descriptors copied into LDS after the image and the second filter.
 constexpr uint32_t kLvlWords = 4 * kImageLevels;
+// After the waves' areas: the workgroup's tile counter (padded to 16 bytes).
+constexpr uint32_t kCtlWords = 4;
 __host__ __device__ constexpr uint32_t wave_words(uint32_t tile, uint32_t halo) {
   return pk_words(tile, halo) + iv_words(tile, halo) + kQueue + kQueue / 2 + kQueue / 2;
 }
@@ -643,6 +644,120 @@ __device__ __forceinline__ TileLoc locate(const ScanParams& p, uint64_t lt) {
   return L;
 }
 
+// Per-tile counts of a scan.  Atomic stores: deferred walks of the same
+// launch add to them with atomics.
+__device__ __forceinline__ void put_counts(const ScanParams& p, uint64_t tile, uint32_t hits,
+                                           unsigned long long occ) {
+  __hip_atomic_store(&p.tile_hits[tile], hits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(&p.tile_occ[tile], occ, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One deferred walk (one-text launches): the depth-D jump entry of the
+// window, then the walk with path compression over the 64 bases copied with
+// the entry, continued on the text in global memory past them.  A pattern
+// found is written to the dense output and appended to its tile's hit slots
+// (the finish kernel orders each tile's slots by position).
+template <uint32_t D>
+__device__ __forceinline__ void deferred_walk(const ScanParams& p, const WalkEntry& we) {
+  const u32x4 a = reinterpret_cast<const u32x4*>(&we)[0];
+  const u32x4 b = reinterpret_cast<const u32x4*>(&we)[1];
+  const uint32_t pos = a.x;
+  const uint32_t c0 = a.z, c1 = a.w, c2 = b.x, c3 = b.y;
+  const uint64_t ivall = ((uint64_t)b.w << 32) | b.z;
+  const uint64_t n = p.seg0.n;
+  const uint32_t enc = p.seg0.enc;
+  int32_t best = 0;
+  unsigned long long occ = 0;
+  uint32_t s = 0, q = 0;
+  bool live = true;
+  if (!a.y) {
+    const uint32_t x = c0 >> (32 - 2 * D);
+    const uint32_t jj = p.jump[x];
+    if (jj & kFinalBit) {
+      const OutEntry o = p.jres[x];
+      best = o.pid;
+      occ += o.mult;
+    }
+    s = jj & kStateMask;
+    q = D;
+    live = s != 0;
+  }
+  while (live) {
+    if (q >= kWindow) {
+      // past the copied bases: go on reading the text itself
+      walk<true>(s, (uint64_t)pos + q, nullptr, nullptr, p.next, p.out, p.text, n, enc, best,
+                 occ);
+      break;
+    }
+    const uint32_t wk = q >> 4, sh = 2 * (q & 15u);
+    const uint32_t hi = wk == 0 ? c0 : wk == 1 ? c1 : wk == 2 ? c2 : c3;
+    const uint32_t lo = wk == 0 ? c1 : wk == 1 ? c2 : wk == 2 ? c3 : 0u;
+    const uint32_t win = (uint32_t)(((((uint64_t)hi << 32) | lo) << sh) >> 32);
+    const uint32_t ivw = (uint32_t)(ivall >> q);
+    const u32x2 ch = *reinterpret_cast<const u32x2*>(p.chain + 2ull * s);
+    const uint32_t e = p.next[(uint64_t)s * 4 + (win >> 30)];
+    const uint32_t len = ch.x & 15u;
+    if (len >= 2) {
+      if (q + len > kWindow) {
+        // the run reaches past the copied bases
+        walk<true>(s, (uint64_t)pos + q, nullptr, nullptr, p.next, p.out, p.text, n, enc, best,
+                   occ);
+        break;
+      }
+      if ((ivw & ((1u << len) - 1u)) | ((win ^ ch.x) & (0xFFFFFFFFu << (32 - 2 * len)))) break;
+      s = ch.y & kStateMask;
+      q += len;
+      if (ch.y & kFinalBit) {
+        const OutEntry o = p.out[s];
+        best = o.pid;
+        occ += o.mult;
+      }
+      continue;
+    }
+    if ((ivw & 1u) || e == 0) break;
+    s = e & kStateMask;
+    if (e & kFinalBit) {
+      const OutEntry o = p.out[s];
+      best = o.pid;
+      occ += o.mult;
+    }
+    ++q;
+  }
+  const uint64_t gt = pos / kTileSingle;
+  if (best) {
+    if (p.match) p.match[pos] = best;
+    const uint32_t slot = atomicAdd(&p.tile_hits[gt], 1u);
+    if (p.slots && slot < kSlot) p.slots[gt * kSlot + slot] = Slot{pos, best};
+  }
+  if (occ) atomicAdd(&p.tile_occ[gt], occ);
+}
+
+// Zero dense output of a whole tile of nt positions (mt 16-byte aligned or
+// not), the lane's NG groups of four.
+template <uint32_t NG>
+__device__ __forceinline__ void zero_tile(int32_t* mt, uint32_t nt, bool aligned) {
+  const uint32_t lane = threadIdx.x & 63;
+  const i32x4 z = {0, 0, 0, 0};
+  if (aligned && nt == NG * 256) {
+    #pragma unroll
+    for (uint32_t g = 0; g < NG; ++g)
+      __builtin_nontemporal_store(z, reinterpret_cast<i32x4*>(mt + g * 256) + lane);
+    return;
+  }
+  #pragma unroll 1
+  for (uint32_t g = 0; g < NG; ++g) {
+    const uint32_t q0 = g * 256 + 4 * lane;
+    if (aligned && q0 + 4 <= nt) {
+      __builtin_nontemporal_store(z, reinterpret_cast<i32x4*>(mt + q0));
+    } else {
+      if (q0 < nt) mt[q0] = 0;
+      if (q0 + 1 < nt) mt[q0 + 1] = 0;
+      if (q0 + 2 < nt) mt[q0 + 2] = 0;
+      if (q0 + 3 < nt) mt[q0 + 3] = 0;
+    }
+  }
+}
+
 // Main scan.  Each wave takes whole tiles of TILE positions (grid-stride).  A
 // lane owns 4*NG positions of a tile, NG = TILE/256 groups of four
 // consecutive ones: q = g*256 + 4*lane + r.  Positions whose walk goes on past the filter are
@@ -669,10 +784,17 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
   int32_t* res;
   uint16_t* queue;
   uint16_t* queue2 = nullptr;
+  // tiles are handed out to the workgroup's waves one at a time from a
+  // counter in LDS: waves that the CU issues more often take more tiles, and
+  // all end within about one tile of each other
+  uint32_t* ctl;
   if (GLOBAL) {
     res = reinterpret_cast<int32_t*>(lds + wave * kGlobalWaveWords);
     queue = reinterpret_cast<uint16_t*>(res + kQueue);
+    ctl = lds + (BLOCK / 64) * kGlobalWaveWords;
   } else {
+    ctl = lds + img_words + (hashed ? p.hash_words : 0u) + kLvlWords +
+          (BLOCK / 64) * wave_words(TILE, p.halo);
     pk = lds + img_words + (hashed ? p.hash_words : 0u) + kLvlWords +
          wave * wave_words(TILE, p.halo);
     iv = pk + pk_words(TILE, p.halo);
@@ -693,8 +815,9 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
     if (p.lds_trie && threadIdx.x < kLvlWords / 4)
       reinterpret_cast<u32x4*>(bm + img_words + (hashed ? p.hash_words : 0u))[threadIdx.x] =
           p.lvl[threadIdx.x];
-    __syncthreads();
   }
+  if (threadIdx.x == 0) ctl[0] = BLOCK / 64;   // wave w starts with local tile w
+  __syncthreads();
   const u32x4* lvl = reinterpret_cast<const u32x4*>(lds + img_words +
                                                     (hashed ? p.hash_words : 0u));
 
@@ -710,12 +833,20 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
   uint64_t lt = gwave;
   uint32_t wq_n = 0;                                // deferred walks of this wave
   WalkEntry* wq = (SINGLE && p.defer) ? p.wq + (uint64_t)gwave * p.wq_cap : nullptr;
-  if (lt >= p.local_tiles) {
-    if (SINGLE && p.defer && lane == 0) p.wq_count[gwave] = 0;
-    return;
-  }
+  if (lt >= p.local_tiles) return;
   TileLoc cur = locate<SINGLE>(p, lt);
   Prefetch pf{};
+  // the all-zero dense output and the counters of the previous tile, written
+  // after the next tile's text is in LDS: the wait for that text (the
+  // vector-memory counter also counts stores, completing in issue order) then
+  // does not wait for stores issued just before it
+  int32_t* zmt = nullptr;
+  uint32_t znt = 0;
+  bool zal = false;
+  bool cpend = false;
+  uint64_t ctile = 0;
+  uint32_t chits = 0;
+  unsigned long long cocc = 0;
   if (!GLOBAL)
     pf = fetch<TILE>(TextRef{p.text + cur.seg.text_off, cur.seg.n, cur.ts * TILE, cur.seg.enc},
                      p.halo);
@@ -735,8 +866,12 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
       commit<TILE>(TextRef{text, n, t0, enc}, p.halo, pf, pk, iv);
       wave_sync();
     }
-    // next tile: locate it and start loading its text now
-    const uint64_t lt_next = lt + nwaves;
+    // next tile: take it, locate it and start loading its text now.  Local
+    // tile i of workgroup b is b*W + i%W + (i/W)*nwaves (W waves per
+    // workgroup), increasing in i: the first one past the end ends the wave
+    const uint32_t li = __builtin_amdgcn_readfirstlane(lane == 0 ? atomicAdd(ctl, 1u) : 0u);
+    const uint64_t lt_next = (uint64_t)blockIdx.x * (BLOCK / 64) + li % (BLOCK / 64) +
+                             (uint64_t)(li / (BLOCK / 64)) * nwaves;
     const bool more = lt_next < p.local_tiles;
     TileLoc nxt = cur;
     if (more) {
@@ -745,6 +880,14 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
         pf = fetch<TILE>(TextRef{p.text + nxt.seg.text_off, nxt.seg.n, nxt.ts * TILE,
                                  nxt.seg.enc},
                          p.halo);
+    }
+    if (zmt) {
+      zero_tile<NG>(zmt, znt, zal);
+      zmt = nullptr;
+    }
+    if (cpend) {
+      if (lane == 0) put_counts(p, ctile, chits, cocc);
+      cpend = false;
     }
 
     // ---- classify the lane's 4*NG positions: bit 4g+r of want / slow
@@ -890,6 +1033,13 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
         if (!((sel >> (4 * g)) & 1u)) continue;
         const uint32_t q0 = g * 256 + 4 * lane;
         if (!any) {
+          if (mt && passes == 1) {
+            // the whole tile is zero: written with the next tile
+            zmt = mt;
+            znt = nt;
+            zal = maligned;
+            break;
+          }
           if (mt) {
             const i32x4 z = {0, 0, 0, 0};
             if (maligned && q0 + 4 <= nt) {
@@ -941,209 +1091,44 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
       }
       wave_sync();
     }
-    const unsigned long long tocc = __ballot(occ != 0) ? wave_sum(occ) : 0ull;
-    if (lane == 0) {
-      p.tile_hits[gtile] = tile_hits;
-      p.tile_occ[gtile] = tocc;
-    }
+    cocc = __ballot(occ != 0) ? wave_sum(occ) : 0ull;
+    chits = tile_hits;
+    ctile = gtile;
+    cpend = true;
     if (!more) break;
     lt = lt_next;
     cur = nxt;
   }
-  if (SINGLE && p.defer && lane == 0) p.wq_count[gwave] = wq_n;
-}
-
-// Parameters of the walk kernel (deferred walks of a one-text launch).
-struct WalkParams {
-  const WalkEntry* wq;
-  const uint32_t* wq_count;       // per scan wave
-  uint32_t nwaves;
-  uint32_t wq_cap;                // entries per scan wave
-  uint32_t D;
-  uint32_t tile;
-  uint32_t enc;
-  const uint32_t* next;
-  const OutEntry* out;
-  const uint32_t* chain;
-  const uint32_t* jump;
-  const OutEntry* jres;
-  const uint8_t* text;
-  uint64_t n;
-  int32_t* match;
-  uint32_t* tile_hits;
-  unsigned long long* tile_occ;
-  Slot* slots;
-};
-
-// The deferred walks, one per lane: the depth-D jump entry of the window,
-// then the walk with path compression over the copied 64 bases, continued on
-// the text in global memory past them.  A pattern found is written to the
-// dense output and appended to its tile's hit slots (the scatter kernel
-// orders each tile's slots by position).
-__global__ __launch_bounds__(256) void pfac_walk_kernel(WalkParams p) {
-  // one thread per entry slot of every scan wave; slots past a wave's count
-  // are empty
-  const uint64_t slot = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-  const uint32_t r = (uint32_t)(slot / p.wq_cap), k = (uint32_t)(slot % p.wq_cap);
-  if (r < p.nwaves && k < p.wq_count[r]) {
-    const WalkEntry* we = p.wq + slot;
-    const u32x4 a = reinterpret_cast<const u32x4*>(we)[0];
-    const u32x4 b = reinterpret_cast<const u32x4*>(we)[1];
-    const uint32_t pos = a.x;
-    const uint32_t c0 = a.z, c1 = a.w, c2 = b.x, c3 = b.y;
-    const uint64_t ivall = ((uint64_t)b.w << 32) | b.z;
-    int32_t best = 0;
-    unsigned long long occ = 0;
-    uint32_t s = 0, q = 0;
-    bool live = true;
-    if (!a.y) {
-      const uint32_t x = c0 >> (32 - 2 * p.D);
-      const uint32_t jj = p.jump[x];
-      if (jj & kFinalBit) {
-        const OutEntry o = p.jres[x];
-        best = o.pid;
-        occ += o.mult;
-      }
-      s = jj & kStateMask;
-      q = p.D;
-      live = s != 0;
+  if (zmt) zero_tile<NG>(zmt, znt, zal);
+  if (lane == 0) put_counts(p, ctile, chits, cocc);
+  if constexpr (SINGLE && !GLOBAL) {
+    if (p.defer && wq_n) {
+      // the deferred walks of this wave's tiles, one per lane: their results
+      // go over the zeros and counts stored above, so those stores complete
+      // first
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      #pragma unroll 1
+      for (uint32_t j = lane; j < wq_n; j += 64) deferred_walk<D>(p, wq[j]);
     }
-    while (live) {
-      if (q >= kWindow) {
-        // past the copied bases: go on reading the text itself
-        walk<true>(s, (uint64_t)pos + q, nullptr, nullptr, p.next, p.out, p.text, p.n, p.enc,
-                   best, occ);
-        break;
-      }
-      const uint32_t wk = q >> 4, sh = 2 * (q & 15u);
-      const uint32_t hi = wk == 0 ? c0 : wk == 1 ? c1 : wk == 2 ? c2 : c3;
-      const uint32_t lo = wk == 0 ? c1 : wk == 1 ? c2 : wk == 2 ? c3 : 0u;
-      const uint32_t win = (uint32_t)(((((uint64_t)hi << 32) | lo) << sh) >> 32);
-      const uint32_t ivw = (uint32_t)(ivall >> q);
-      const u32x2 ch = *reinterpret_cast<const u32x2*>(p.chain + 2ull * s);
-      const uint32_t e = p.next[(uint64_t)s * 4 + (win >> 30)];
-      const uint32_t len = ch.x & 15u;
-      if (len >= 2) {
-        if (q + len > kWindow) {
-          // the run reaches past the copied bases
-          walk<true>(s, (uint64_t)pos + q, nullptr, nullptr, p.next, p.out, p.text, p.n, p.enc,
-                     best, occ);
-          break;
-        }
-        if ((ivw & ((1u << len) - 1u)) | ((win ^ ch.x) & (0xFFFFFFFFu << (32 - 2 * len)))) break;
-        s = ch.y & kStateMask;
-        q += len;
-        if (ch.y & kFinalBit) {
-          const OutEntry o = p.out[s];
-          best = o.pid;
-          occ += o.mult;
-        }
-        continue;
-      }
-      if ((ivw & 1u) || e == 0) break;
-      s = e & kStateMask;
-      if (e & kFinalBit) {
-        const OutEntry o = p.out[s];
-        best = o.pid;
-        occ += o.mult;
-      }
-      ++q;
-    }
-    const uint64_t gt = pos / p.tile;
-    if (best) {
-      if (p.match) p.match[pos] = best;
-      const uint32_t slot = atomicAdd(&p.tile_hits[gt], 1u);
-      if (p.slots && slot < kSlot) p.slots[gt * kSlot + slot] = Slot{pos, best};
-    }
-    if (occ) atomicAdd(&p.tile_occ[gt], occ);
   }
 }
 
-// Per block of kRedTiles tiles: sums of hits and occurrences.  The last
-// block to finish (atomic ticket, reset by that block for the next launch)
-// turns the block sums into block prefixes and writes the totals.
-__global__ __launch_bounds__(1024) void pfac_reduce_kernel(
-    const uint32_t* tile_hits, const unsigned long long* tile_occ, uint64_t tiles,
-    unsigned long long* block_hits, unsigned long long* block_occ,
-    unsigned long long* block_prefix, uint32_t* done, unsigned long long* counters) {
-  __shared__ unsigned long long red_h[16], red_o[16];
-  __shared__ unsigned long long wsum[16];
-  __shared__ unsigned long long carry_h, carry_o;
-  __shared__ bool last;
-  const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const uint64_t base = (uint64_t)blockIdx.x * kRedTiles;
-  unsigned long long h = 0, o = 0;
-  for (uint32_t i = threadIdx.x; i < kRedTiles; i += 1024) {
-    const uint64_t t = base + i;
-    if (t < tiles) {
-      h += tile_hits[t];
-      o += tile_occ[t];
-    }
-  }
-  h = wave_sum(h);
-  o = wave_sum(o);
-  if (lane == 0) { red_h[w] = h; red_o[w] = o; }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned long long sh = 0, so = 0;
-    for (int i = 0; i < 16; ++i) { sh += red_h[i]; so += red_o[i]; }
-    __hip_atomic_store(&block_hits[blockIdx.x], sh, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&block_occ[blockIdx.x], so, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
-    const uint32_t prev = atomicAdd(done, 1u);
-    last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  // the last block: exclusive scan of the block sums
-  if (threadIdx.x == 0) { carry_h = 0; carry_o = 0; }
-  __syncthreads();
-  for (uint32_t b0 = 0; b0 < gridDim.x; b0 += 1024) {
-    const uint32_t b = b0 + threadIdx.x;
-    unsigned long long vh = 0, vo = 0;
-    if (b < gridDim.x) {
-      vh = __hip_atomic_load(&block_hits[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      vo = __hip_atomic_load(&block_occ[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    unsigned long long inc = vh;
-    for (int off = 1; off < 64; off <<= 1) {
-      const unsigned long long y = __shfl_up(inc, off, 64);
-      if ((int)lane >= off) inc += y;
-    }
-    const unsigned long long so = wave_sum(vo);
-    if (lane == 63) wsum[w] = inc;
-    if (lane == 0) red_o[w] = so;
-    __syncthreads();
-    unsigned long long before = carry_h;
-    for (uint32_t k = 0; k < w; ++k) before += wsum[k];
-    if (b < gridDim.x) block_prefix[b] = before + inc - vh;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      unsigned long long th = 0, to = 0;
-      for (int k = 0; k < 16; ++k) { th += wsum[k]; to += red_o[k]; }
-      carry_h += th;
-      carry_o += to;
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    counters[0] = carry_h;
-    counters[1] = carry_o;
-    *done = 0;
-  }
-}
-
-// Parameters of the scatter kernel.
-struct ScatterParams {
+// Parameters of the finish kernel.
+struct FinishParams {
   const uint32_t* tile_hits;
+  const unsigned long long* tile_occ;
   Slot* slots;
-  const unsigned long long* block_prefix;
   uint64_t tiles;
   uint32_t tile;                  // start positions per tile
-  void* hits;                     // pfac_hit* (single) or pfac_batch_hit* (batch)
+  void* hits;                     // pfac_hit* (single) or pfac_batch_hit* (batch); null: none
   uint64_t hit_cap;
   uint32_t single;
+  // per workgroup: look-back word and occurrence sum; two counters (work
+  // ticket, finished look-backs), zero between launches
+  unsigned long long* status;
+  unsigned long long* block_occ;
+  uint32_t* sync;
+  unsigned long long* counters;   // [0] hits, [1] occurrences
   // tile -> text (batch), and what an overflowing tile needs to redo its hits
   uint32_t nsegs;
   const DevSeg* segs;
@@ -1155,7 +1140,7 @@ struct ScatterParams {
   DevTable tab0;
 };
 
-__device__ __forceinline__ void put_hit(const ScatterParams& p, uint64_t o, uint32_t text,
+__device__ __forceinline__ void put_hit(const FinishParams& p, uint64_t o, uint32_t text,
                                         uint32_t pos, int32_t pid) {
   if (o >= p.hit_cap) return;
   if (p.single) {
@@ -1165,7 +1150,7 @@ __device__ __forceinline__ void put_hit(const ScatterParams& p, uint64_t o, uint
   }
 }
 
-__device__ __forceinline__ uint32_t text_of_tile(const ScatterParams& p, uint64_t t) {
+__device__ __forceinline__ uint32_t text_of_tile(const FinishParams& p, uint64_t t) {
   uint32_t lo = 0, hi = p.nsegs;   // tile_prefix[lo] <= t < tile_prefix[hi]
   while (hi - lo > 1) {
     const uint32_t mid = (lo + hi) >> 1;
@@ -1174,105 +1159,224 @@ __device__ __forceinline__ uint32_t text_of_tile(const ScatterParams& p, uint64_
   return lo;
 }
 
-// Places every tile's hits at its position-ordered offset.  Tiles with more
-// hits than their slot holds take them from the dense output when it was
-// written, otherwise walk their positions again from the root.
-__global__ __launch_bounds__(1024) void pfac_scatter_kernel(ScatterParams p) {
+// Look-back word of a workgroup: bits 62..63 what it holds (0 nothing yet,
+// 1 the workgroup's own hit count, 2 the count of it and every workgroup
+// before it), bits 0..61 the count.
+constexpr unsigned long long kLbAgg = 1ull << 62;
+constexpr unsigned long long kLbIncl = 2ull << 62;
+constexpr unsigned long long kLbMask = (1ull << 62) - 1;
+constexpr uint32_t kLbSpinLimit = 1u << 22;
+
+// Hit list and totals after the scan, one launch.  Workgroups take tickets in
+// the order they start and handle kRedTiles tiles in ticket order: the hit
+// and occurrence sums of their tiles, then the hits before them by looking
+// back over the words of the workgroups with earlier tickets (one lane per
+// workgroup, 64 at a time; a workgroup with a ticket has started, so every
+// wait ends), then every tile's hits at their position-ordered offsets.  The
+// last workgroup to finish its look-back writes the totals and clears the
+// words and counters for the next launch.  Tiles with more hits than their
+// slots hold take them from the dense output when it was written, otherwise
+// walk their positions again from the root.
+__global__ __launch_bounds__(1024) void pfac_finish_kernel(FinishParams p) {
   __shared__ uint32_t wsum[16];
+  __shared__ unsigned long long wocc[16];
   __shared__ uint32_t ovf_tile[kRedTiles];
   __shared__ unsigned long long ovf_off[kRedTiles];
-  __shared__ uint32_t novf;
+  __shared__ uint32_t novf, s_vb, s_last;
+  __shared__ unsigned long long s_excl;
   const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const uint64_t base = (uint64_t)blockIdx.x * kRedTiles;
-  if (threadIdx.x == 0) novf = 0;
-  // 4 consecutive tiles per thread
+  if (threadIdx.x == 0) {
+    novf = 0;
+    s_vb = __hip_atomic_fetch_add(&p.sync[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  // workgroups almost always start in index order: load the tiles of this
+  // index while the ticket is taken, again if the ticket differs
   uint32_t h[4];
-  uint32_t sum = 0;
-  #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const uint64_t t = base + 4 * threadIdx.x + k;
-    h[k] = (t < p.tiles) ? p.tile_hits[t] : 0u;
-    sum += h[k];
+  unsigned long long oc;
+  auto load = [&](uint64_t tt) {
+    oc = 0;
+    if (tt + 4 <= p.tiles) {
+      const u32x4 hv = *reinterpret_cast<const u32x4*>(p.tile_hits + tt);
+      h[0] = hv.x; h[1] = hv.y; h[2] = hv.z; h[3] = hv.w;
+      oc = p.tile_occ[tt] + p.tile_occ[tt + 1] + p.tile_occ[tt + 2] + p.tile_occ[tt + 3];
+    } else {
+      #pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        h[k] = tt + k < p.tiles ? p.tile_hits[tt + k] : 0u;
+        oc += tt + k < p.tiles ? p.tile_occ[tt + k] : 0ull;
+      }
+    }
+  };
+  load((uint64_t)blockIdx.x * kRedTiles + 4 * threadIdx.x);
+  __syncthreads();
+  const uint32_t vb = s_vb;
+  const uint64_t base = (uint64_t)vb * kRedTiles;
+  const uint64_t tt = base + 4 * threadIdx.x;   // 4 consecutive tiles per thread
+  if (vb != blockIdx.x) load(tt);
+  // order each tile's slots by position (hits found by deferred walks were
+  // appended after the scan's, in no particular order); this needs no offset
+  if (p.hits && p.hit_cap) {
+    #pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (h[k] < 2 || h[k] > kSlot) continue;
+      Slot* sl = p.slots + (tt + k) * kSlot;
+      for (uint32_t i = 1; i < h[k]; ++i) {
+        const Slot key = sl[i];
+        uint32_t m = i;
+        while (m > 0 && sl[m - 1].pos > key.pos) {
+          sl[m] = sl[m - 1];
+          --m;
+        }
+        sl[m] = key;
+      }
+    }
   }
-  uint32_t inc = sum;
-  #pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint32_t y = __shfl_up(inc, off, 64);
-    if ((int)lane >= off) inc += y;
-  }
+  const uint32_t sum = h[0] + h[1] + h[2] + h[3];
+  const uint32_t inc = wave_incl_dpp(sum);
+  oc = wave_sum(oc);
   if (lane == 63) wsum[w] = inc;
+  if (lane == 0) wocc[w] = oc;
   __syncthreads();
-  uint64_t off = p.block_prefix[blockIdx.x];
-  for (uint32_t k = 0; k < w; ++k) off += wsum[k];
-  off += inc - sum;
-  #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const uint64_t t = base + 4 * threadIdx.x + k;
-    if (h[k] && off < p.hit_cap) {
-      if (h[k] <= kSlot) {
-        const uint32_t text = p.single ? 0u : text_of_tile(p, t);
-        // order the slots by position (hits found by the walk kernel were
-        // appended after the scan kernel's, in no particular order)
-        Slot* sl = p.slots + t * kSlot;
-        for (uint32_t j = 1; j < h[k]; ++j) {
-          const Slot key = sl[j];
-          uint32_t m = j;
-          while (m > 0 && sl[m - 1].pos > key.pos) {
-            sl[m] = sl[m - 1];
-            --m;
-          }
-          sl[m] = key;
-        }
-        for (uint32_t j = 0; j < h[k]; ++j) {
-          const Slot s = sl[j];
-          put_hit(p, off + j, text, s.pos, s.pid);
-        }
-      } else {
-        const uint32_t i = atomicAdd(&novf, 1u);
-        ovf_tile[i] = 4 * threadIdx.x + k;
-        ovf_off[i] = off;
-      }
+  if (w == 0) {
+    unsigned long long agg = lane < 16 ? wsum[lane] : 0u;
+    unsigned long long occ = lane < 16 ? wocc[lane] : 0ull;
+    agg = wave_sum(agg);
+    occ = wave_sum(occ);
+    // a look-back word carries its own data: relaxed atomics suffice
+    if (lane == 0) {
+      __hip_atomic_store(&p.block_occ[vb], occ, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&p.status[vb], (vb == 0 ? kLbIncl : kLbAgg) | agg, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
     }
-    off += h[k];
+    // look back: lane l reads the word of workgroup j - l
+    unsigned long long excl = 0;
+    int64_t j = (int64_t)vb - 1;
+    uint32_t spins = 0;
+    while (j >= 0) {
+      const int64_t jj = j - (int64_t)lane;
+      const unsigned long long v =
+          jj >= 0 ? __hip_atomic_load(&p.status[jj], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                  : kLbIncl;
+      const uint64_t stop = __ballot((v & ~kLbMask) == kLbIncl);
+      const uint32_t first = stop ? (uint32_t)__builtin_ctzll(stop) : 64u;
+      const uint64_t upto = first >= 63 ? ~0ull : ((2ull << first) - 1ull);
+      if (__ballot((v & ~kLbMask) == 0) & upto) {
+        if (++spins >= kLbSpinLimit) {
+          // never expected (every awaited workgroup is running): give up
+          // rather than hang; this workgroup writes no hits and the hit
+          // total reads as all ones
+          excl = ~0ull;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+        continue;
+      }
+      excl += wave_sum(lane <= first ? (v & kLbMask) : 0ull);
+      if (first < 64) break;
+      j -= 64;
+    }
+    if (lane == 0) {
+      if (vb != 0)
+        __hip_atomic_store(&p.status[vb], kLbIncl | ((excl + agg) & kLbMask), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      s_excl = excl;
+      // release: this workgroup's words before the count of finished
+      // look-backs; acquire: the last one then sees every workgroup's words
+      const uint32_t prev = __hip_atomic_fetch_add(&p.sync[1], 1u, __ATOMIC_ACQ_REL,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+      s_last = prev == gridDim.x - 1;
+    }
   }
   __syncthreads();
-  // tiles whose hits did not fit their slot: one wave each
-  for (uint32_t i = w; i < novf; i += 16) {
-    const uint64_t t = base + ovf_tile[i];
-    uint64_t o = ovf_off[i];
-    uint32_t text = 0;
-    DevSeg seg = p.seg0;
-    uint64_t ts = t;
-    DevTable tab = p.tab0;
-    if (!p.single) {
-      text = text_of_tile(p, t);
-      seg = p.segs[text];
-      ts = t - p.tile_prefix[text];
-      tab = p.tables[seg.table];
-    }
-    const uint64_t t0 = ts * p.tile;
-    const uint8_t* tx = p.text + seg.text_off;
-    for (uint32_t k = 0; k < p.tile / 256; ++k) {   // 64 lanes x 4 positions per step
-      const uint64_t pos0 = t0 + k * 256 + 4 * lane;
-      int32_t v[4] = {0, 0, 0, 0};
-      #pragma unroll
-      for (uint32_t r = 0; r < 4; ++r) {
-        if (pos0 + r >= seg.n) continue;
-        if (p.match) {
-          v[r] = p.match[seg.match_off + pos0 + r];
+  if (p.hits && p.hit_cap && s_excl != ~0ull) {
+    uint64_t off = s_excl;
+    for (uint32_t k = 0; k < w; ++k) off += wsum[k];
+    off += inc - sum;
+    #pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint64_t t = tt + k;
+      if (h[k] && off < p.hit_cap) {
+        if (h[k] <= kSlot) {
+          const uint32_t text = p.single ? 0u : text_of_tile(p, t);
+          const Slot* sl = p.slots + t * kSlot;
+          for (uint32_t i = 0; i < h[k]; ++i) {
+            const Slot s = sl[i];
+            put_hit(p, off + i, text, s.pos, s.pid);
+          }
         } else {
-          unsigned long long unused = 0;
-          walk<true>(0u, pos0 + r, nullptr, nullptr, tab.next, tab.out, tx, seg.n, seg.enc,
-                     v[r], unused);
+          const uint32_t i = atomicAdd(&novf, 1u);
+          ovf_tile[i] = 4 * threadIdx.x + k;
+          ovf_off[i] = off;
         }
       }
-      const uint32_t c = (v[0] != 0) + (v[1] != 0) + (v[2] != 0) + (v[3] != 0);
-      uint32_t tot;
-      uint64_t oo = o + wave_excl(c, &tot);
-      #pragma unroll
-      for (uint32_t r = 0; r < 4; ++r)
-        if (v[r]) put_hit(p, oo++, text, (uint32_t)(pos0 + r), v[r]);
-      o += tot;
+      off += h[k];
+    }
+    __syncthreads();
+    // tiles whose hits did not fit their slots: one wave each
+    for (uint32_t i = w; i < novf; i += 16) {
+      const uint64_t t = base + ovf_tile[i];
+      uint64_t o = ovf_off[i];
+      uint32_t text = 0;
+      DevSeg seg = p.seg0;
+      uint64_t ts = t;
+      DevTable tab = p.tab0;
+      if (!p.single) {
+        text = text_of_tile(p, t);
+        seg = p.segs[text];
+        ts = t - p.tile_prefix[text];
+        tab = p.tables[seg.table];
+      }
+      const uint64_t t0 = ts * p.tile;
+      const uint8_t* tx = p.text + seg.text_off;
+      for (uint32_t k = 0; k < p.tile / 256; ++k) {   // 64 lanes x 4 positions per step
+        const uint64_t pos0 = t0 + k * 256 + 4 * lane;
+        int32_t v[4] = {0, 0, 0, 0};
+        #pragma unroll
+        for (uint32_t r = 0; r < 4; ++r) {
+          if (pos0 + r >= seg.n) continue;
+          if (p.match) {
+            v[r] = p.match[seg.match_off + pos0 + r];
+          } else {
+            unsigned long long unused = 0;
+            walk<true>(0u, pos0 + r, nullptr, nullptr, tab.next, tab.out, tx, seg.n, seg.enc,
+                       v[r], unused);
+          }
+        }
+        const uint32_t c = (v[0] != 0) + (v[1] != 0) + (v[2] != 0) + (v[3] != 0);
+        uint32_t tot;
+        uint64_t oo = o + wave_excl(c, &tot);
+        #pragma unroll
+        for (uint32_t r = 0; r < 4; ++r)
+          if (v[r]) put_hit(p, oo++, text, (uint32_t)(pos0 + r), v[r]);
+        o += tot;
+      }
+    }
+  }
+  if (s_last) {
+    // every workgroup has published its counts and finished its look-back:
+    // totals, then clear the words and counters for the next launch
+    __shared__ unsigned long long tot_occ[16];
+    const uint32_t nb = gridDim.x;
+    unsigned long long o = 0;
+    for (uint32_t b = threadIdx.x; b < nb; b += 1024)
+      o += __hip_atomic_load(&p.block_occ[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    o = wave_sum(o);
+    if (lane == 0) tot_occ[w] = o;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long to = 0;
+      for (int k = 0; k < 16; ++k) to += tot_occ[k];
+      const unsigned long long last =
+          __hip_atomic_load(&p.status[nb - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      p.counters[0] = (s_excl == ~0ull) ? ~0ull : (last & kLbMask);
+      p.counters[1] = to;
+    }
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < nb; b += 1024)
+      __hip_atomic_store(&p.status[b], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) {
+      __hip_atomic_store(&p.sync[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&p.sync[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
 }
@@ -1341,10 +1445,9 @@ struct Workspace {
   uint32_t* tile_hits = nullptr;
   unsigned long long* tile_occ = nullptr;
   Slot* slots = nullptr;
-  unsigned long long* block_hits = nullptr;
+  unsigned long long* status = nullptr;     // finish kernel: look-back word per workgroup
   unsigned long long* block_occ = nullptr;
-  unsigned long long* block_prefix = nullptr;
-  uint32_t* done = nullptr;
+  uint32_t* sync = nullptr;                 // finish kernel: ticket, finished look-backs
   void* batch = nullptr;           // descriptors, prefixes, group lists, table views
   uint64_t batch_cap = 0;
   uint8_t* stage = nullptr;        // pinned host copy of `batch` being uploaded
@@ -1352,8 +1455,6 @@ struct Workspace {
   bool staged_pending = false;
   WalkEntry* walk = nullptr;       // deferred walks of one-text calls
   uint64_t walk_cap = 0;           // entries
-  uint32_t* walk_count = nullptr;  // per scan wave
-  uint64_t walk_waves = 0;
 };
 
 static std::map<std::pair<int, void*>, Workspace*> g_ws;
@@ -1366,11 +1467,10 @@ static int ensure_tiles(Workspace* ws, uint64_t tiles, hipStream_t stream) {
   const uint64_t o_hits = 0;
   const uint64_t o_occ = al(o_hits + cap * 4);
   const uint64_t o_slots = al(o_occ + cap * 8);
-  const uint64_t o_bh = al(o_slots + cap * kSlot * sizeof(Slot));
-  const uint64_t o_bo = al(o_bh + blocks * 8);
-  const uint64_t o_bp = al(o_bo + blocks * 8);
-  const uint64_t o_done = al(o_bp + blocks * 8);
-  const uint64_t total = al(o_done + 256);
+  const uint64_t o_st = al(o_slots + cap * kSlot * sizeof(Slot));
+  const uint64_t o_bo = al(o_st + blocks * 8);
+  const uint64_t o_sync = al(o_bo + blocks * 8);
+  const uint64_t total = al(o_sync + 256);
   if (ws->mem) {
     if (hipStreamSynchronize(stream) != hipSuccess) return PFAC_E_HIP;
     (void)hipFree(ws->mem);
@@ -1380,15 +1480,15 @@ static int ensure_tiles(Workspace* ws, uint64_t tiles, hipStream_t stream) {
   void* m = nullptr;
   if (hipMalloc(&m, total) != hipSuccess) return PFAC_E_NOMEM;
   ws->mem = static_cast<uint8_t*>(m);
-  if (hipMemset(ws->mem + o_done, 0, 256) != hipSuccess) return PFAC_E_HIP;
+  // look-back words and counters start at zero; the finish kernel leaves them so
+  if (hipMemset(ws->mem + o_st, 0, total - o_st) != hipSuccess) return PFAC_E_HIP;
   ws->cap_tiles = cap;
   ws->tile_hits = reinterpret_cast<uint32_t*>(ws->mem + o_hits);
   ws->tile_occ = reinterpret_cast<unsigned long long*>(ws->mem + o_occ);
   ws->slots = reinterpret_cast<Slot*>(ws->mem + o_slots);
-  ws->block_hits = reinterpret_cast<unsigned long long*>(ws->mem + o_bh);
+  ws->status = reinterpret_cast<unsigned long long*>(ws->mem + o_st);
   ws->block_occ = reinterpret_cast<unsigned long long*>(ws->mem + o_bo);
-  ws->block_prefix = reinterpret_cast<unsigned long long*>(ws->mem + o_bp);
-  ws->done = reinterpret_cast<uint32_t*>(ws->mem + o_done);
+  ws->sync = reinterpret_cast<uint32_t*>(ws->mem + o_sync);
   return PFAC_OK;
 }
 
@@ -1425,26 +1525,19 @@ static int ensure_batch(Workspace* ws, uint64_t bytes, hipStream_t stream) {
   return PFAC_OK;
 }
 
-// Room for `cap` deferred walks and `waves` per-wave counts (grown, never
-// shrunk).
-static int ensure_walk(Workspace* ws, uint64_t cap, uint64_t waves, hipStream_t stream) {
-  if (cap <= ws->walk_cap && waves <= ws->walk_waves && ws->walk) return PFAC_OK;
+// Room for `cap` deferred walks (grown, never shrunk).
+static int ensure_walk(Workspace* ws, uint64_t cap, hipStream_t stream) {
+  if (cap <= ws->walk_cap && ws->walk) return PFAC_OK;
   if (ws->walk) {
     if (hipStreamSynchronize(stream) != hipSuccess) return PFAC_E_HIP;
     (void)hipFree(ws->walk);
     ws->walk = nullptr;
-    ws->walk_count = nullptr;
-    ws->walk_cap = ws->walk_waves = 0;
+    ws->walk_cap = 0;
   }
-  cap = std::max(cap, ws->walk_cap);
-  waves = std::max(waves, ws->walk_waves);
-  const uint64_t o_count = (cap * sizeof(WalkEntry) + 255) / 256 * 256;
   void* m = nullptr;
-  if (hipMalloc(&m, o_count + waves * 4) != hipSuccess) return PFAC_E_NOMEM;
+  if (hipMalloc(&m, cap * sizeof(WalkEntry)) != hipSuccess) return PFAC_E_NOMEM;
   ws->walk = static_cast<WalkEntry*>(m);
-  ws->walk_count = reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(m) + o_count);
   ws->walk_cap = cap;
-  ws->walk_waves = waves;
   return PFAC_OK;
 }
 
@@ -1474,7 +1567,7 @@ static uint32_t image_words(const HostTable& h, uint32_t D, bool lds_trie, uint3
 // a plan fits both kinds of launch.
 static uint32_t scan_lds_bytes(uint32_t block, uint32_t img_words, uint32_t halo,
                                uint32_t tile = kTileSingle) {
-  return 4u * (img_words + kLvlWords + (block / 64) * wave_words(tile, halo));
+  return 4u * (img_words + kLvlWords + (block / 64) * wave_words(tile, halo) + kCtlWords);
 }
 
 using ScanFn = void (*)(ScanParams);
@@ -1692,7 +1785,7 @@ static int scan_shape(const ScanParams& sp, const pfac_plan& plan, int dev, Scan
   const bool global = plan.variant == PFAC_VARIANT_GLOBAL;
   *fn = pick_scan(plan.block, global, sp.D, sp.single != 0);
   if (!*fn) return PFAC_E_ARG;
-  *lds = global ? 4u * (plan.block / 64) * kGlobalWaveWords
+  *lds = global ? 4u * ((plan.block / 64) * kGlobalWaveWords + kCtlWords)
                 : scan_lds_bytes(plan.block, sp.image_words + (sp.hash_on ? sp.hash_words : 0u),
                                  sp.halo, sp.single ? kTileSingle : kTileBatch);
   *grid = grid_for(*fn, plan, *lds, dev, sp.local_tiles);
@@ -1711,21 +1804,22 @@ static int launch_scan(const ScanParams& sp, const pfac_plan& plan, int dev, hip
 }
 
 static int launch_tail(Workspace* ws, uint64_t tiles, unsigned long long* counters,
-                       ScatterParams* sc, bool want_hits, hipStream_t stream) {
+                       FinishParams* sc, bool want_hits, hipStream_t stream) {
   const uint32_t blocks = (uint32_t)((tiles + kRedTiles - 1) / kRedTiles);
-  hipLaunchKernelGGL(pfac_reduce_kernel, dim3(blocks), dim3(1024), 0, stream, ws->tile_hits,
-                     ws->tile_occ, tiles, ws->block_hits, ws->block_occ, ws->block_prefix,
-                     ws->done, counters);
-  if (hipGetLastError() != hipSuccess) return PFAC_E_HIP;
-  if (want_hits) {
-    sc->tile_hits = ws->tile_hits;
-    sc->slots = ws->slots;
-    sc->block_prefix = ws->block_prefix;
-    sc->tiles = tiles;
-    hipLaunchKernelGGL(pfac_scatter_kernel, dim3(blocks), dim3(1024), 0, stream, *sc);
-    if (hipGetLastError() != hipSuccess) return PFAC_E_HIP;
+  sc->tile_hits = ws->tile_hits;
+  sc->tile_occ = ws->tile_occ;
+  sc->slots = ws->slots;
+  sc->tiles = tiles;
+  sc->status = ws->status;
+  sc->block_occ = ws->block_occ;
+  sc->sync = ws->sync;
+  sc->counters = counters;
+  if (!want_hits) {
+    sc->hits = nullptr;
+    sc->hit_cap = 0;
   }
-  return PFAC_OK;
+  hipLaunchKernelGGL(pfac_finish_kernel, dim3(blocks), dim3(1024), 0, stream, *sc);
+  return hipGetLastError() == hipSuccess ? PFAC_OK : PFAC_E_HIP;
 }
 
 static void fill_table(ScanParams& sp, const pfac_table* t, const pfac_plan& pl) {
@@ -1932,57 +2026,29 @@ int pfac_match(const pfac_table* t, const void* d_text, uint64_t n, int enc, int
   sp.tile_occ = ws->tile_occ;
   sp.slots = d_hits ? ws->slots : nullptr;
   const bool defer = pl.variant == PFAC_VARIANT_TILED && pl.walks == PFAC_WALKS_DEFERRED;
-  uint32_t nwaves = 0;
   if (defer) {
     // every scan wave gets room for 4 walks per tile it will scan (about
     // four times what the second filter lets through on random-like text;
-    // walks beyond it run inline); the walk kernel has a thread per slot
+    // walks beyond it run at once) and walks them after its last tile
     ScanFn fn;
     uint32_t lds;
     uint64_t grid;
     rc = scan_shape(sp, pl, dev, &fn, &lds, &grid);
     if (rc) return rc;
-    nwaves = (uint32_t)(grid * (pl.block / 64));
+    const uint64_t nwaves = grid * (pl.block / 64);
     const uint64_t per = std::max<uint64_t>(4 * ((tiles + nwaves - 1) / nwaves), 64);
     {
       std::lock_guard<std::mutex> lk(g_mu);
-      rc = ensure_walk(ws, per * nwaves, nwaves, stream);
+      rc = ensure_walk(ws, per * nwaves, stream);
     }
     if (rc) return rc;
     sp.defer = 1;
     sp.wq = ws->walk;
-    sp.wq_count = ws->walk_count;
     sp.wq_cap = (uint32_t)per;
   }
   rc = launch_scan(sp, pl, dev, stream);
   if (rc) return rc;
-  if (defer) {
-    WalkParams wp;
-    memset(&wp, 0, sizeof(wp));
-    wp.wq = ws->walk;
-    wp.wq_count = ws->walk_count;
-    wp.nwaves = nwaves;
-    wp.wq_cap = sp.wq_cap;
-    wp.D = pl.depth;
-    wp.tile = kTileSingle;
-    wp.enc = (uint32_t)enc;
-    wp.next = t->dev.next;
-    wp.out = t->dev.out;
-    wp.chain = t->dev.chain;
-    wp.jump = t->dev.jump[pl.depth];
-    wp.jres = t->dev.jres[pl.depth];
-    wp.text = sp.text;
-    wp.n = n;
-    wp.match = d_match;
-    wp.tile_hits = ws->tile_hits;
-    wp.tile_occ = ws->tile_occ;
-    wp.slots = d_hits ? ws->slots : nullptr;
-    const uint64_t slots = (uint64_t)nwaves * wp.wq_cap;
-    hipLaunchKernelGGL(pfac_walk_kernel, dim3((uint32_t)((slots + 255) / 256)), dim3(256), 0,
-                       stream, wp);
-    if (hipGetLastError() != hipSuccess) return PFAC_E_HIP;
-  }
-  ScatterParams sc;
+  FinishParams sc;
   memset(&sc, 0, sizeof(sc));
   sc.hits = d_hits;
   sc.hit_cap = hit_cap;
@@ -2111,7 +2177,7 @@ static int enqueue_batch(const BatchLayout& L, const Workspace* ws, const uint8_
     const int rc = launch_scan(sp, L.plans[g], dev, stream);
     if (rc) return rc;
   }
-  ScatterParams sc;
+  FinishParams sc;
   memset(&sc, 0, sizeof(sc));
   sc.hits = d_hits;
   sc.hit_cap = hit_cap;
