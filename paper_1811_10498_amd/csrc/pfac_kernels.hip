@@ -1214,11 +1214,15 @@ __global__ __launch_bounds__(1024) void pfac_finish_kernel(FinishParams p) {
   const uint64_t tt = base + 4 * threadIdx.x;   // 4 consecutive tiles per thread
   if (vb != blockIdx.x) load(tt);
   // order each tile's slots by position (hits found by deferred walks were
-  // appended after the scan's, in no particular order); this needs no offset
-  if (p.hits && p.hit_cap) {
+  // appended after the scan's, in no particular order); needs no offset, so
+  // waves 1.. do it while wave 0 looks back, and wave 0 after that (the
+  // first slot of each tile is then read ahead of the offsets)
+  Slot first[4];
+  auto sort_slots = [&]() {
+    if (!p.hits || !p.hit_cap) return;
     #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      if (h[k] < 2 || h[k] > kSlot) continue;
+      if (h[k] == 0 || h[k] > kSlot) continue;
       Slot* sl = p.slots + (tt + k) * kSlot;
       for (uint32_t i = 1; i < h[k]; ++i) {
         const Slot key = sl[i];
@@ -1229,8 +1233,9 @@ __global__ __launch_bounds__(1024) void pfac_finish_kernel(FinishParams p) {
         }
         sl[m] = key;
       }
+      first[k] = sl[0];
     }
-  }
+  };
   const uint32_t sum = h[0] + h[1] + h[2] + h[3];
   const uint32_t inc = wave_incl_dpp(sum);
   oc = wave_sum(oc);
@@ -1287,6 +1292,7 @@ __global__ __launch_bounds__(1024) void pfac_finish_kernel(FinishParams p) {
       s_last = prev == gridDim.x - 1;
     }
   }
+  sort_slots();
   __syncthreads();
   if (p.hits && p.hit_cap && s_excl != ~0ull) {
     uint64_t off = s_excl;
@@ -1299,7 +1305,8 @@ __global__ __launch_bounds__(1024) void pfac_finish_kernel(FinishParams p) {
         if (h[k] <= kSlot) {
           const uint32_t text = p.single ? 0u : text_of_tile(p, t);
           const Slot* sl = p.slots + t * kSlot;
-          for (uint32_t i = 0; i < h[k]; ++i) {
+          put_hit(p, off, text, first[k].pos, first[k].pid);
+          for (uint32_t i = 1; i < h[k]; ++i) {
             const Slot s = sl[i];
             put_hit(p, off + i, text, s.pos, s.pid);
           }
