@@ -118,6 +118,7 @@ struct ScanParams {
   uint32_t defer;
   uint32_t wq_cap;
   WalkEntry* wq;
+  uint64_t wq_waves;              // waves wq has room for
 };
 
 // ---------------------------------------------------------------- device helpers
@@ -763,7 +764,7 @@ __device__ __forceinline__ void zero_tile(int32_t* mt, uint32_t nt, bool aligned
 // consecutive ones: q = g*256 + 4*lane + r.  Positions whose walk goes on past the filter are
 // queued and walked by all lanes together; their results come back through
 // a result slot per queue entry.
-template <int BLOCK, bool GLOBAL, int DT, bool SINGLE>
+template <int BLOCK, bool GLOBAL, int DT, bool SINGLE, bool DEFER>
 __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
   extern __shared__ uint32_t lds[];
   // the wave index is uniform across the wave: keep it (and every tile
@@ -832,7 +833,7 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
   const uint32_t gwave = blockIdx.x * (BLOCK / 64) + wave;
   uint64_t lt = gwave;
   uint32_t wq_n = 0;                                // deferred walks of this wave
-  WalkEntry* wq = (SINGLE && p.defer) ? p.wq + (uint64_t)gwave * p.wq_cap : nullptr;
+  WalkEntry* wq = DEFER ? p.wq + (uint64_t)gwave * p.wq_cap : nullptr;
   if (lt >= p.local_tiles) return;
   TileLoc cur = locate<SINGLE>(p, lt);
   Prefetch pf{};
@@ -881,7 +882,7 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
                                  nxt.seg.enc},
                          p.halo);
     }
-    if (zmt) {
+    if (DEFER && zmt) {
       zero_tile<NG>(zmt, znt, zal);
       zmt = nullptr;
     }
@@ -981,7 +982,7 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
       //      lane copies an entry into the wave's own part of the buffer;
       //      the entries that do not fit there are walked here
       uint32_t ndef = 0;
-      if (SINGLE && !GLOBAL && p.defer && nwalk > 0) {
+      if (DEFER && nwalk > 0) {
         const uint32_t wbase = wq_n;
         ndef = min(nwalk, p.wq_cap - wq_n);
         wq_n += ndef;
@@ -1033,7 +1034,7 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
         if (!((sel >> (4 * g)) & 1u)) continue;
         const uint32_t q0 = g * 256 + 4 * lane;
         if (!any) {
-          if (mt && passes == 1) {
+          if (DEFER && mt && passes == 1) {
             // the whole tile is zero: written with the next tile
             zmt = mt;
             znt = nt;
@@ -1099,10 +1100,10 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
     lt = lt_next;
     cur = nxt;
   }
-  if (zmt) zero_tile<NG>(zmt, znt, zal);
+  if (DEFER && zmt) zero_tile<NG>(zmt, znt, zal);
   if (lane == 0) put_counts(p, ctile, chits, cocc);
-  if constexpr (SINGLE && !GLOBAL) {
-    if (p.defer && wq_n) {
+  if constexpr (DEFER) {
+    if (wq_n) {
       // the deferred walks of this wave's tiles, one per lane: their results
       // go over the zeros and counts stored above, so those stores complete
       // first
@@ -1579,34 +1580,38 @@ static uint32_t scan_lds_bytes(uint32_t block, uint32_t img_words, uint32_t halo
 
 using ScanFn = void (*)(ScanParams);
 
-template <int BLOCK, bool SINGLE>
+template <int BLOCK, bool SINGLE, bool DEFER>
 static ScanFn pick_depth(uint32_t D) {
   switch (D) {
-    case 6: return pfac_scan_kernel<BLOCK, false, 6, SINGLE>;
-    case 7: return pfac_scan_kernel<BLOCK, false, 7, SINGLE>;
-    case 8: return pfac_scan_kernel<BLOCK, false, 8, SINGLE>;
-    case 9: return pfac_scan_kernel<BLOCK, false, 9, SINGLE>;
-    case 10: return pfac_scan_kernel<BLOCK, false, 10, SINGLE>;
+    case 6: return pfac_scan_kernel<BLOCK, false, 6, SINGLE, DEFER>;
+    case 7: return pfac_scan_kernel<BLOCK, false, 7, SINGLE, DEFER>;
+    case 8: return pfac_scan_kernel<BLOCK, false, 8, SINGLE, DEFER>;
+    case 9: return pfac_scan_kernel<BLOCK, false, 9, SINGLE, DEFER>;
+    case 10: return pfac_scan_kernel<BLOCK, false, 10, SINGLE, DEFER>;
     default: return nullptr;
   }
 }
 
-// One instantiation per (workgroup size, filter depth, one text or a batch):
-// the depth fixes every window shift at compile time, and a one-text launch
-// carries none of the batch bookkeeping.
+// One instantiation per (workgroup size, filter depth, one text or a batch,
+// walks at once or deferred): the depth fixes every window shift at compile
+// time, a one-text launch carries none of the batch bookkeeping, and only
+// launches with deferred walks (few survivors per tile) carry their hand-off
+// and the deferred zero stores.
 template <int BLOCK>
-static ScanFn pick_block(bool global, uint32_t D, bool single) {
+static ScanFn pick_block(bool global, uint32_t D, bool single, bool defer) {
   if (global)
-    return single ? pfac_scan_kernel<BLOCK, true, 0, true> : pfac_scan_kernel<BLOCK, true, 0, false>;
-  return single ? pick_depth<BLOCK, true>(D) : pick_depth<BLOCK, false>(D);
+    return single ? pfac_scan_kernel<BLOCK, true, 0, true, false>
+                  : pfac_scan_kernel<BLOCK, true, 0, false, false>;
+  if (!single) return pick_depth<BLOCK, false, false>(D);
+  return defer ? pick_depth<BLOCK, true, true>(D) : pick_depth<BLOCK, true, false>(D);
 }
 
-static ScanFn pick_scan(uint32_t block, bool global, uint32_t D, bool single) {
+static ScanFn pick_scan(uint32_t block, bool global, uint32_t D, bool single, bool defer) {
   switch (block) {
-    case 256: return pick_block<256>(global, D, single);
-    case 512: return pick_block<512>(global, D, single);
-    case 768: return pick_block<768>(global, D, single);
-    case 1024: return pick_block<1024>(global, D, single);
+    case 256: return pick_block<256>(global, D, single, defer);
+    case 512: return pick_block<512>(global, D, single, defer);
+    case 768: return pick_block<768>(global, D, single, defer);
+    case 1024: return pick_block<1024>(global, D, single, defer);
     default: return nullptr;
   }
 }
@@ -1790,7 +1795,7 @@ static uint64_t grid_for(ScanFn fn, const pfac_plan& plan, uint32_t lds, int dev
 static int scan_shape(const ScanParams& sp, const pfac_plan& plan, int dev, ScanFn* fn,
                       uint32_t* lds, uint64_t* grid) {
   const bool global = plan.variant == PFAC_VARIANT_GLOBAL;
-  *fn = pick_scan(plan.block, global, sp.D, sp.single != 0);
+  *fn = pick_scan(plan.block, global, sp.D, sp.single != 0, sp.defer != 0);
   if (!*fn) return PFAC_E_ARG;
   *lds = global ? 4u * ((plan.block / 64) * kGlobalWaveWords + kCtlWords)
                 : scan_lds_bytes(plan.block, sp.image_words + (sp.hash_on ? sp.hash_words : 0u),
@@ -1806,6 +1811,7 @@ static int launch_scan(const ScanParams& sp, const pfac_plan& plan, int dev, hip
   uint64_t grid;
   const int rc = scan_shape(sp, plan, dev, &fn, &lds, &grid);
   if (rc) return rc;
+  if (sp.defer && grid * (plan.block / 64) > sp.wq_waves) return PFAC_E_ARG;
   hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(plan.block), lds, stream, sp);
   return hipGetLastError() == hipSuccess ? PFAC_OK : PFAC_E_HIP;
 }
@@ -2037,6 +2043,8 @@ int pfac_match(const pfac_table* t, const void* d_text, uint64_t n, int enc, int
     // every scan wave gets room for 4 walks per tile it will scan (about
     // four times what the second filter lets through on random-like text;
     // walks beyond it run at once) and walks them after its last tile
+    // (the kernel, hence its grid, depends on `defer`: set it first)
+    sp.defer = 1;
     ScanFn fn;
     uint32_t lds;
     uint64_t grid;
@@ -2049,9 +2057,9 @@ int pfac_match(const pfac_table* t, const void* d_text, uint64_t n, int enc, int
       rc = ensure_walk(ws, per * nwaves, stream);
     }
     if (rc) return rc;
-    sp.defer = 1;
     sp.wq = ws->walk;
     sp.wq_cap = (uint32_t)per;
+    sp.wq_waves = nwaves;
   }
   rc = launch_scan(sp, pl, dev, stream);
   if (rc) return rc;
