@@ -87,7 +87,7 @@ typedef struct {
                            D-base window in an LDS bitmap of 4^D bits; only windows
                            whose walk continues past depth D (or passes a final state
                            within D bases) go on to the global-memory trie */
-  uint32_t grid;        /* persistent workgroups (0 = fill the device) */
+  uint32_t grid;        /* persistent workgroups (0 = fill the device; at most 2048) */
   uint32_t variant;     /* PFAC_VARIANT_TILED (LDS text tile + filter bitmap) or
                            PFAC_VARIANT_GLOBAL (every walk from the root, text and
                            table read straight from global memory) */
@@ -105,12 +105,13 @@ typedef struct {
                            two bits are set (or that hold a non-base) walk on.  0 = library
                            choice, PFAC_HASH_NONE = no second filter */
   uint32_t walks;       /* where the walks that pass both filters run, one-text calls:
-                           PFAC_WALKS_INLINE = inside the scan kernel, by the wave
-                           that found them; PFAC_WALKS_DEFERRED = the scan kernel
-                           hands each one (start position + its next 64 bases) to a
-                           separate walk kernel, so the streaming scan never waits on
-                           their table reads.  0 = library choice (deferred when the
-                           second filter is on).  Batched calls always walk inline. */
+                           PFAC_WALKS_INLINE = by the wave that found them, with the
+                           tile; PFAC_WALKS_DEFERRED = the wave keeps each one (start
+                           position + its next 64 bases, room for 4 per tile; more
+                           walk inline) and walks them all after its last tile, so
+                           the streaming scan does not wait on their table reads.
+                           0 = library choice (deferred when the second filter is
+                           on).  Batched calls always walk inline. */
 } pfac_plan;
 
 enum { PFAC_WALKS_INLINE = 1, PFAC_WALKS_DEFERRED = 2 };

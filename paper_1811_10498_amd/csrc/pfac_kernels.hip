@@ -12,17 +12,20 @@
 //     D-base window at the position.  A bitmap of 4^D bits in LDS says which
 //     windows lead anywhere (continue past depth D, or pass a final state);
 //     every other position reports nothing after one LDS lookup.
+//   * Second filter: survivors whose first K bases have a cleared bit in a
+//     two-hash LDS bitmap of the patterns' first K bases stop there too.
 //   * Deep walks: the surviving positions of a wave are compacted into an
-//     LDS queue and walked by all 64 lanes together: one global read of the
-//     depth-D jump table, then the breadth-first numbered next-state table
-//     (L2 / Infinity Cache resident), one base per step.
+//     LDS queue and walked by all 64 lanes together (or, when they are rare,
+//     after the wave's last tile): one global read of the depth-D jump
+//     table, then the breadth-first numbered next-state table (L2 /
+//     Infinity Cache resident), runs of single-child states in one step.
 //   * Text: each wave stages its tile (2048 positions, 1024 in a batch) plus a halo of
 //     max_len-1 bases with 16-byte loads, as 2-bit codes plus an "invalid"
 //     bit per base (bytes other than A,C,G,T, and everything past the end).
-//   * Outputs: the dense int32 array leaves through LDS with 16-byte
-//     non-temporal stores; hits are counted per tile and parked in a
-//     fixed-size slot per tile; a reduce kernel and a scatter kernel then
-//     place them in position order.  No workgroup ever waits for another.
+//   * Outputs: the dense int32 array leaves with 16-byte non-temporal
+//     stores; hits are counted per tile and parked in a fixed-size slot per
+//     tile; one finish kernel (decoupled look-back over its workgroups)
+//     places them in position order.  No scan workgroup waits for another.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
@@ -65,7 +68,7 @@ struct Slot {
   int32_t pid;
 };
 
-// A walk handed from the scan kernel to the walk kernel: its start position
+// A walk deferred to the end of the wave that found it: its start position
 // and a copy of the next kWindow bases (2-bit codes, 16 per word, first base
 // in the top bits of codes[0]; invalid bits, base k in bit k of inv).
 constexpr uint32_t kWindow = 64;
@@ -978,9 +981,9 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
         }
         wave_sync();
       }
-      // ---- one-text launches may hand the walks to the walk kernel: each
-      //      lane copies an entry into the wave's own part of the buffer;
-      //      the entries that do not fit there are walked here
+      // ---- launches with deferred walks keep them for the end of the
+      //      wave: each lane copies an entry into the wave's own part of the
+      //      buffer; the entries that do not fit there are walked here
       uint32_t ndef = 0;
       if (DEFER && nwalk > 0) {
         const uint32_t wbase = wq_n;
@@ -1004,7 +1007,7 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
           u32x4* dst = reinterpret_cast<u32x4*>(wq + wbase + j);
           dst[0] = u32x4{(uint32_t)(t0 + qt), (e >> 15) & 1u, c.x, c.y};
           dst[1] = u32x4{c.z, c.w, inv0, inv1};
-          res[i] = 0;       // the walk kernel writes its result
+          res[i] = 0;       // the deferred walk writes its result
         }
       }
       // ---- walk them with all lanes

@@ -478,7 +478,7 @@ WALK_PLANS = [
 
 @pytest.mark.parametrize("plan", range(len(WALK_PLANS)))
 def test_deferred_walks_match_inline(plan):
-    """Walks handed to the walk kernel (start + 64 copied bases, continued on
+    """Walks deferred to the end of the wave (start + 64 copied bases, continued on
     the text past them) give the oracle's results: patterns up to 120 bases,
     occurrences near tile and text ends, non-bases inside copied windows, and
     a plan whose walks overflow the hand-off buffer (the rest walk inline)."""
