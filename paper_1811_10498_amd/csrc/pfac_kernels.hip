@@ -162,6 +162,16 @@ __device__ __forceinline__ uint32_t lds_word(uint32_t a) {
   return *reinterpret_cast<lds_u32*>(static_cast<uintptr_t>(a));
 }
 
+// The lane index as a value the compiler must take anew where it is asked
+// for: conditions on it inside the tile loop are then recomputed (one
+// compare) instead of hoisted out as 64-bit masks that do not fit in the
+// scalar registers and go to spill slots.
+__device__ __forceinline__ uint32_t fresh_lane() {
+  uint32_t l = threadIdx.x & 63;
+  asm volatile("" : "+v"(l));
+  return l;
+}
+
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -427,7 +437,7 @@ struct Prefetch {
 
 template <uint32_t TILE>
 __device__ __forceinline__ Prefetch fetch(const TextRef& r, uint32_t halo) {
-  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t lane = fresh_lane();
   const uintptr_t addr = reinterpret_cast<uintptr_t>(r.t);
   Prefetch f;
   f.fast = 0;
@@ -561,7 +571,7 @@ __device__ __forceinline__ void commit_2bit_chunk(const TextRef& r, uint32_t c, 
 template <uint32_t TILE>
 __device__ __forceinline__ void commit(const TextRef& r, uint32_t halo, const Prefetch& f,
                                        uint32_t* pk, uint32_t* iv) {
-  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t lane = fresh_lane();
   const uint32_t span = TILE + halo;
   if (r.enc == PFAC_TEXT_ASCII) {
     uint32_t packed, inv;
@@ -621,8 +631,10 @@ __host__ __device__ constexpr uint32_t wave_words(uint32_t tile, uint32_t halo) 
   return pk_words(tile, halo) + iv_words(tile, halo) + kQueue + kQueue / 2 + kQueue / 2;
 }
 
+// A tile's text and place.  One-text launches read their one segment (text
+// and output at offset 0) from the parameters instead, and ts = gtile there.
 struct TileLoc {
-  DevSeg seg;
+  DevSeg seg;       // batch only
   uint64_t ts;      // tile index within its text
   uint64_t gtile;   // tile index in the call
 };
@@ -631,7 +643,6 @@ template <bool SINGLE>
 __device__ __forceinline__ TileLoc locate(const ScanParams& p, uint64_t lt) {
   TileLoc L;
   if (SINGLE) {
-    L.seg = p.seg0;
     L.ts = lt;
     L.gtile = lt;
   } else {
@@ -851,19 +862,27 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
   uint64_t ctile = 0;
   uint32_t chits = 0;
   unsigned long long cocc = 0;
+  // the segment of a tile: one-text launches have text and output at offset 0
+  auto seg_n = [&](const TileLoc& L) -> uint64_t { return SINGLE ? p.seg0.n : L.seg.n; };
+  auto seg_enc = [&](const TileLoc& L) -> uint32_t { return SINGLE ? p.seg0.enc : L.seg.enc; };
+  auto seg_text = [&](const TileLoc& L) -> const uint8_t* {
+    return SINGLE ? p.text : p.text + L.seg.text_off;
+  };
+  auto seg_match = [&](const TileLoc& L) -> int32_t* {
+    return SINGLE ? p.match : p.match + L.seg.match_off;
+  };
   if (!GLOBAL)
-    pf = fetch<TILE>(TextRef{p.text + cur.seg.text_off, cur.seg.n, cur.ts * TILE, cur.seg.enc},
-                     p.halo);
+    pf = fetch<TILE>(TextRef{seg_text(cur), seg_n(cur), cur.ts * TILE, seg_enc(cur)}, p.halo);
 
   for (;;) {
     const uint64_t t0 = cur.ts * TILE;
-    const uint64_t n = cur.seg.n;
+    const uint64_t n = seg_n(cur);
     const uint32_t nt = (uint32_t)((n - t0) < TILE ? (n - t0) : TILE);  // positions in text
     const bool full = nt == TILE;
-    const uint8_t* text = p.text + cur.seg.text_off;
-    const uint32_t enc = cur.seg.enc;
+    const uint8_t* text = seg_text(cur);
+    const uint32_t enc = seg_enc(cur);
     const uint64_t gtile = cur.gtile;
-    int32_t* mt = p.match ? p.match + cur.seg.match_off + t0 : nullptr;
+    int32_t* mt = p.match ? seg_match(cur) + t0 : nullptr;
     const bool maligned = mt && ((reinterpret_cast<uintptr_t>(mt) & 15) == 0);
 
     if (!GLOBAL) {
@@ -881,8 +900,7 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
     if (more) {
       nxt = locate<SINGLE>(p, lt_next);
       if (!GLOBAL)
-        pf = fetch<TILE>(TextRef{p.text + nxt.seg.text_off, nxt.seg.n, nxt.ts * TILE,
-                                 nxt.seg.enc},
+        pf = fetch<TILE>(TextRef{seg_text(nxt), seg_n(nxt), nxt.ts * TILE, seg_enc(nxt)},
                          p.halo);
     }
     if (DEFER && zmt) {
