@@ -157,6 +157,93 @@ def bench_served(pf, torch, num_requests=600, load=0.7, plain_requests=60):
     }
 
 
+# ---------------------------------------------------------------- paper ladder
+# The paper times its kernel on five pattern sets (1000..5000 patterns of
+# about 100 bases) against five read files (0.75 M..3.75 M reads), adding one
+# memory placement at a time: global memory only, then the text in shared
+# memory, then the table through the texture cache, each with the table as
+# two arrays or one merged array (Sec. VI, Tables II and III; Sec. VII).
+# --paper-ladder runs that structure with paper-shaped synthetic inputs over
+# the placements this library has (merged table throughout; no texture path
+# on this GPU), every plan checked bit for bit against the first:
+#   global      every position walks from the root, text and table in global
+#               memory (the paper's one-thread-per-character kernel);
+#   lds-d6      text tile and a depth-6 window bitmap in LDS, deep walks in
+#               the global table;
+#   lds-d9      the same with a depth-9 bitmap;
+#   lds-levels  depth-8 bitmap and the trie levels below it in LDS, the rest
+#               in the global table (the hot-prefix-in-LDS split);
+#   default     the library's plan (bitmap, hashed second filter, deferred
+#               walks for these long patterns).
+
+def ladder_plans(pf):
+    return (
+        ("global", dict(variant=pf.PFAC_VARIANT_GLOBAL)),
+        ("lds-d6", dict(depth=6, levels=pf.PFAC_LEVELS_NONE, hash_bits=pf.PFAC_HASH_NONE,
+                        walks=pf.PFAC_WALKS_INLINE)),
+        ("lds-d9", dict(depth=9, levels=pf.PFAC_LEVELS_NONE, hash_bits=pf.PFAC_HASH_NONE,
+                        walks=pf.PFAC_WALKS_INLINE)),
+        ("lds-levels", dict(depth=8, levels=0, hash_bits=pf.PFAC_HASH_NONE,
+                            walks=pf.PFAC_WALKS_INLINE)),
+        ("default", None),
+    )
+
+
+def run_ladder(pf, torch, pattern_sets=(1, 2, 3, 4, 5), data_sets=(1, 5), reps=10, num_reads=None,
+               seed=5):
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    rows = []
+    for d in data_sets:
+        for k in pattern_sets:
+            w = W.reads_workload(k, d, seed=seed, num_reads=num_reads)
+            tab = pf.Table(w.patterns)
+            text = torch.from_numpy(w.text).to(dev)
+            ref = None
+            for name, plan in ladder_plans(pf):
+                res = pf.match(tab, text, plan=plan, hit_cap=w.n // 8 + 1024)
+                torch.cuda.synchronize()
+                if ref is None:
+                    ref = (res.match.clone(), res.num_hits(), res.total())
+                else:
+                    same = (torch.equal(res.match, ref[0]) and res.num_hits() == ref[1]
+                            and res.total() == ref[2])
+                    if not same:
+                        raise RuntimeError("plan %s differs from plan %s on %s"
+                                           % (name, ladder_plans(pf)[0][0], w.name))
+                for _ in range(2):
+                    pf.match(tab, text, plan=plan, out=res)
+                s = torch.cuda.Event(enable_timing=True)
+                e = torch.cuda.Event(enable_timing=True)
+                s.record()
+                for _ in range(reps):
+                    pf.match(tab, text, plan=plan, out=res)
+                e.record()
+                torch.cuda.synchronize()
+                ms = s.elapsed_time(e) / reps
+                resolved = tab.default_plan(w.n, "ascii") if plan is None else plan
+                row = dict(pattern_set=k, data_set=d, patterns=len(w.patterns),
+                           reads=w.num_reads, bytes=w.n, plan=name, resolved=resolved,
+                           ms=round(ms, 4), gbases_per_s=round(w.n / ms / 1e6, 1),
+                           hits=ref[1], total=ref[2])
+                rows.append(row)
+                print(json.dumps(row), flush=True)
+            del text, tab
+    return rows
+
+
+def ladder_table(rows):
+    names = ["global", "lds-d6", "lds-d9", "lds-levels", "default"]
+    keys = sorted({(r["data_set"], r["pattern_set"]) for r in rows})
+    out = ["| data set | pattern set | " + " | ".join(names) + " |",
+           "|---|---|" + "---|" * len(names)]
+    for d, k in keys:
+        ms = {r["plan"]: r["ms"] for r in rows if r["data_set"] == d and r["pattern_set"] == k}
+        out.append("| %d | %d | " % (d, k) + " | ".join("%.3f" % ms[n] for n in names) + " |")
+    return "\n".join(out)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -172,6 +259,11 @@ def main():
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched workload")
     ap.add_argument("--no-served", action="store_true", help="skip the served workload")
+    ap.add_argument("--paper-ladder", action="store_true",
+                    help="instead: the paper's placement ladder on paper-shaped pattern and "
+                         "read sets (prints one JSON line per case and a table)")
+    ap.add_argument("--ladder-pattern-sets", default="1,2,3,4,5")
+    ap.add_argument("--ladder-data-sets", default="1,5")
     ap.add_argument("--autotune", action="store_true",
                     help="also time the autotuner's plan (reported beside the default plan)")
     args = ap.parse_args()
@@ -187,6 +279,16 @@ def main():
     import torch
 
     import paper_1811_10498_amd as pf
+
+    if args.paper_ladder:
+        t0 = time.time()
+        rows = run_ladder(pf, torch,
+                          tuple(int(x) for x in args.ladder_pattern_sets.split(",")),
+                          tuple(int(x) for x in args.ladder_data_sets.split(",")))
+        print("milliseconds per call (reads file resident in HBM, dense output + hit list):")
+        print(ladder_table(rows))
+        print("total %.1f s" % (time.time() - t0))
+        return
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)

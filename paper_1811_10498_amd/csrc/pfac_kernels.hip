@@ -1651,13 +1651,12 @@ static uint32_t auto_depth(const HostTable& h) {
   return D;
 }
 
-// Second-filter size the library picks: the smallest bitmap with at most
-// one bit in 16 set by the patterns (two per pattern), else the largest one
+// Second-filter size the library picks: the largest bitmap (fewest windows
+// let through; its LDS fits beside a depth-9 bitmap and 1024 threads' text)
 // while the patterns number at most 40 % of its bits (beyond that it passes
-// too much to pay for its lookups).
+// too much to pay for its lookups).  Smaller bitmaps were measured no faster
+// on 1,000 to 10,000 patterns.
 static uint32_t auto_hash_bits(const HostTable& h) {
-  for (uint32_t b = kHashMinBits; b <= kHashMaxBits; ++b)
-    if ((uint64_t)h.num_patterns * 32 <= (1ull << b)) return b;
   if ((double)h.num_patterns <= 0.4 * (double)(1u << kHashMaxBits)) return kHashMaxBits;
   return PFAC_HASH_NONE;
 }
@@ -1702,23 +1701,21 @@ static int resolve_plan(const pfac_plan* in, const HostTable& h, int dev, pfac_p
   }
   // Library choice when every pattern is longer than the filter depth and
   // the second filter is worth keeping: bitmap + second filter only (the few
-  // windows that pass both are walked from the global jump table) in
-  // 512-thread workgroups -- measured faster than keeping trie levels in LDS,
-  // whose walks the second filter has already cut down.  Otherwise
-  // 1024-thread workgroups and as many LDS trie levels as fit.
-  // The depth then stays at most 9 (a 32 KB bitmap next to the second
-  // filter).
+  // windows that pass both are walked from the global jump table), depth 9
+  // when the patterns' first K bases go past it (a 32 KB bitmap next to the
+  // filter), in 1024-thread workgroups -- measured faster than keeping trie
+  // levels in LDS, whose walks the second filter has already cut down, and
+  // than shallower bitmaps or 512-thread workgroups.  Otherwise 1024-thread
+  // workgroups and as many LDS trie levels as fit.
   const bool auto_b = p.block == 0;
   const bool auto_d = p.depth == 0;
   if (p.variant == PFAC_VARIANT_TILED && p.levels == 0 && p.hash_bits == 0) {
-    const uint32_t D = p.depth ? p.depth : std::min<uint32_t>(auto_depth(h), 9u);
+    uint32_t D = p.depth ? p.depth : std::min<uint32_t>(auto_depth(h), 9u);
+    if (!p.depth && h.hash_k > 9) D = 9;
     const uint32_t hb = auto_hash_bits(h);
     if (h.hash_k > D && hb != PFAC_HASH_NONE) {
       p.levels = PFAC_LEVELS_NONE;
       p.depth = D;
-      // two 512-thread groups share a CU while bitmap and filter take at most
-      // 48 KB; a larger filter goes with one 1024-thread group
-      if (p.block == 0) p.block = hb <= 17 ? 512 : 1024;
     }
   }
   // with the workgroup size left to the library, a depth whose image does

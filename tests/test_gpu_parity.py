@@ -522,3 +522,26 @@ def test_deferred_walks_with_optional_outputs():
     assert tab.default_plan(w.n)["walks"] == pf.PFAC_WALKS_DEFERRED
     with pytest.raises(pf.PfacError):
         pf.match(tab, dt, plan=dict(walks=3))
+
+
+READS_PLANS = [
+    dict(variant=pf.PFAC_VARIANT_GLOBAL),
+    dict(depth=6, levels=pf.PFAC_LEVELS_NONE, hash_bits=pf.PFAC_HASH_NONE,
+         walks=pf.PFAC_WALKS_INLINE),
+    dict(depth=9, levels=pf.PFAC_LEVELS_NONE, hash_bits=pf.PFAC_HASH_NONE,
+         walks=pf.PFAC_WALKS_INLINE),
+    dict(depth=8, levels=0, hash_bits=pf.PFAC_HASH_NONE, walks=pf.PFAC_WALKS_INLINE),
+    None,
+]
+
+
+@pytest.mark.parametrize("plan", range(len(READS_PLANS)))
+def test_paper_shaped_reads_every_ladder_plan(plan):
+    """The plans of the benchmark's placement ladder on a paper-shaped reads
+    file (newline-separated ~100-base reads, 100-base patterns): the oracle's
+    results, walks stopping at every newline."""
+    w = W.reads_workload(2, 1, num_reads=40_000)
+    print("reads: n=%d reads=%d patterns=%d plan=%s" % (w.n, w.num_reads, len(w.patterns),
+                                                         READS_PLANS[plan]), flush=True)
+    res = _gpu(w.patterns, w.text, plan=READS_PLANS[plan])
+    _check(res, w.patterns, w.text)

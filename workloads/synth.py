@@ -23,7 +23,7 @@ __all__ = [
     "codes_to_ascii", "ascii_to_codes", "pack2bit", "unpack2bit_ascii", "random_packed",
     "cut_patterns", "random_patterns", "PlainWorkload", "plain_workload", "BatchWorkload",
     "batch_workload", "served_tries", "ServedRequest", "served_requests", "CONFIG_NAMES",
-    "lognormal_lengths",
+    "lognormal_lengths", "ReadsWorkload", "reads_workload",
 ]
 
 ACGT = np.frombuffer(b"ACGT", dtype=np.uint8)
@@ -378,3 +378,51 @@ def served_requests(count: int, rate_bases_per_s: float, seed: int = 4, num_trie
         out.append(ServedRequest(r, k, int(g.integers(0, num_tries)),
                                  np.full(cnt, L, dtype=np.int64), int(g.integers(0, 2**62)), t))
     return out
+
+
+@dataclass
+class ReadsWorkload:
+    """A pattern set and a reads file in the shape of the paper's experiments
+    (Tables II and III): ``num_patterns`` patterns of 100 bases, and
+    ``num_reads`` reads of 95..105 bases, one per line (each read followed by
+    a newline byte, which no walk crosses)."""
+    name: str
+    text: np.ndarray              # ASCII uint8, reads joined by b"\n"
+    patterns: list
+    num_reads: int
+    recipe: str
+
+    @property
+    def n(self) -> int:
+        return int(self.text.size)
+
+
+def reads_workload(pattern_set: int, data_set: int, seed: int = 5,
+                   num_reads: int | None = None) -> ReadsWorkload:
+    """Paper-shaped stand-in: pattern set k has 1000*k patterns of 100 bases
+    (the 101.1 KB per 1000 lines of Table II); data set k has 750,000*k reads
+    of U[95,105] uniform-random bases, newline-terminated (about 101 bytes a
+    line, as in Table III).  Half of the patterns are cut from reads of at
+    least 100 bases (so they occur), the other half are uniform random."""
+    if not (1 <= pattern_set <= 5 and 1 <= data_set <= 5):
+        raise ValueError("pattern and data sets are numbered 1..5")
+    g = rng(seed * 100 + pattern_set * 10 + data_set)
+    R = 750_000 * data_set if num_reads is None else int(num_reads)
+    lens = g.integers(95, 106, size=R)
+    ends = np.cumsum(lens + 1)
+    total = int(ends[-1]) if R else 0
+    text = uniform_ascii(total, g)
+    text[ends - 1] = ord("\n")
+    starts = ends - 1 - lens
+    P = 1000 * pattern_set
+    long_reads = np.nonzero(lens >= 100)[0]
+    planted = P // 2
+    pats = []
+    for r in g.choice(long_reads, size=planted, replace=True):
+        off = int(starts[r]) + int(g.integers(0, int(lens[r]) - 100 + 1))
+        pats.append(text[off:off + 100].tobytes())
+    pats += random_patterns(P - planted, 100, 100, g)
+    return ReadsWorkload("paper_p%d_d%d" % (pattern_set, data_set), text, pats, R,
+                         "%d reads of U[95,105] uniform ACGT bases, newline-terminated; "
+                         "%d patterns of 100 bases, half cut from reads, half random; "
+                         "PCG64 seed %d" % (R, P, seed * 100 + pattern_set * 10 + data_set))
