@@ -173,8 +173,13 @@ def bench_served(pf, torch, num_requests=600, load=0.7, plain_requests=60):
 #   lds-d9      the same with a depth-9 bitmap;
 #   lds-levels  depth-8 bitmap and the trie levels below it in LDS, the rest
 #               in the global table (the hot-prefix-in-LDS split);
-#   default     the library's plan (bitmap, hashed second filter, deferred
-#               walks for these long patterns).
+#   d9-hash     depth-9 bitmap and the 2^18-bit hashed second filter, walks
+#               at once;
+#   default     the library's plan (the same filters, walks deferred to the
+#               end of each wave).
+
+LADDER_NAMES = ("global", "lds-d6", "lds-d9", "lds-levels", "d9-hash", "default")
+
 
 def ladder_plans(pf):
     return (
@@ -185,6 +190,8 @@ def ladder_plans(pf):
                         walks=pf.PFAC_WALKS_INLINE)),
         ("lds-levels", dict(depth=8, levels=0, hash_bits=pf.PFAC_HASH_NONE,
                             walks=pf.PFAC_WALKS_INLINE)),
+        ("d9-hash", dict(depth=9, levels=pf.PFAC_LEVELS_NONE, hash_bits=18,
+                         walks=pf.PFAC_WALKS_INLINE)),
         ("default", None),
     )
 
@@ -234,7 +241,7 @@ def run_ladder(pf, torch, pattern_sets=(1, 2, 3, 4, 5), data_sets=(1, 5), reps=1
 
 
 def ladder_table(rows):
-    names = ["global", "lds-d6", "lds-d9", "lds-levels", "default"]
+    names = LADDER_NAMES
     keys = sorted({(r["data_set"], r["pattern_set"]) for r in rows})
     out = ["| data set | pattern set | " + " | ".join(names) + " |",
            "|---|---|" + "---|" * len(names)]

@@ -91,6 +91,7 @@ struct ScanParams {
                                   // rank words, node bytes of the levels below
   uint32_t image_words;           // image words copied into LDS
   uint32_t levels;                // trie levels held in LDS (D .. D+levels-1)
+  uint32_t longer;                // 1: every pattern is longer than D bases
   uint32_t lds_trie;              // 1: no pattern is D bases or shorter, so a set
                                   // filter bit is a depth-D node found by rank
   const u32x4* lvl;                  // per LDS level: image word offset of its node
@@ -942,11 +943,18 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
         for (uint32_t r = 0; r < 4; ++r)
           m4 |= __builtin_amdgcn_ubfe(word[r], w >> (32 - 2 * r - 2 * D), 1u) << r;
         if (inv & gmask) {
-          // a window holds a non-base: such positions walk from the root
+          // a window holds a non-base (or runs past the text): such
+          // positions walk from the root -- or, when every pattern is longer
+          // than D, report nothing (no pattern fits before the non-base)
           #pragma unroll
           for (uint32_t r = 0; r < 4; ++r)
             if ((inv >> r) & dmask) s4 |= 1u << r;
-          m4 |= s4;
+          if (p.longer) {
+            m4 &= ~s4;
+            s4 = 0;
+          } else {
+            m4 |= s4;
+          }
         }
         m4 &= vmask;
         s4 &= vmask;
@@ -1864,6 +1872,7 @@ static void fill_table(ScanParams& sp, const pfac_table* t, const pfac_plan& pl)
     sp.jump = t->dev.jump[D];
     sp.jres = t->dev.jres[D];
     sp.image = t->dev.image[D];
+    sp.longer = h.min_len > D ? 1u : 0u;
     sp.lds_trie = (h.min_len > D && pl.levels != PFAC_LEVELS_NONE) ? 1u : 0u;
     sp.levels = sp.lds_trie ? pl.levels : 0u;
     sp.image_words = image_words(h, D, sp.lds_trie, sp.levels);

@@ -531,6 +531,7 @@ READS_PLANS = [
     dict(depth=9, levels=pf.PFAC_LEVELS_NONE, hash_bits=pf.PFAC_HASH_NONE,
          walks=pf.PFAC_WALKS_INLINE),
     dict(depth=8, levels=0, hash_bits=pf.PFAC_HASH_NONE, walks=pf.PFAC_WALKS_INLINE),
+    dict(depth=9, levels=pf.PFAC_LEVELS_NONE, hash_bits=18, walks=pf.PFAC_WALKS_INLINE),
     None,
 ]
 
