@@ -111,7 +111,8 @@ typedef struct {
                            walk inline) and walks them all after its last tile, so
                            the streaming scan does not wait on their table reads.
                            0 = library choice (deferred when the second filter is
-                           on).  Batched calls always walk inline. */
+                           on and no pattern is longer than 64 bases).  Batched
+                           calls always walk inline. */
 } pfac_plan;
 
 enum { PFAC_WALKS_INLINE = 1, PFAC_WALKS_DEFERRED = 2 };

@@ -394,10 +394,10 @@ __device__ __forceinline__ int32_t deep_walk(uint32_t e, uint32_t D, uint32_t ld
 }
 
 // Second filter for one queued entry (see deep_walk for the entry format):
-// true when the walk must go on -- the window holds a non-base within its
-// first K bases, or both hashes of its first K bases have their bits set.  A window
-// whose first K bases are no pattern's first K bases can only fail the test
-// (every pattern has at least K bases), so a cleared bit proves the walk
+// true when the walk must go on -- both hashes of its first K bases have
+// their bits set (or it is an entry that walks from the root).  Every pattern
+// has at least K bases, so a window with a non-base among its first K bases,
+// or whose first K bases are no pattern's first K bases (a cleared bit),
 // reports nothing.
 __device__ __forceinline__ bool hash_pass(uint32_t e, const uint32_t* __restrict__ pk,
                                           const uint32_t* __restrict__ iv,
@@ -405,7 +405,9 @@ __device__ __forceinline__ bool hash_pass(uint32_t e, const uint32_t* __restrict
                                           uint32_t imask, uint32_t shift) {
   if (e & 0x8000u) return true;
   const uint32_t qt = e & 0x7FFFu;
-  if (__builtin_amdgcn_alignbit(iv[(qt >> 5) + 1], iv[qt >> 5], qt & 31u) & imask) return true;
+  // a non-base among the first K bases: every pattern has at least K bases,
+  // so none starts here
+  if (__builtin_amdgcn_alignbit(iv[(qt >> 5) + 1], iv[qt >> 5], qt & 31u) & imask) return false;
   const uint32_t wi = qt >> 4;
   const uint32_t key =
       (uint32_t)(((((uint64_t)pk[wi] << 32) | pk[wi + 1]) << (2 * (qt & 15u))) >> 32) & kmask;
@@ -1762,10 +1764,13 @@ static int resolve_plan(const pfac_plan* in, const HostTable& h, int dev, pfac_p
       const int rc = place_image(h, D, hw, halo, budget, &p);
       if (rc == PFAC_OK) {
         p.hash_bits = hb;
-        // walks that survive the second filter are few: hand them to the walk
-        // kernel so the streaming scan never waits on their table reads
+        // walks that survive the second filter are few: keep them for the end
+        // of the wave so the streaming scan never waits on their table reads
+        // -- when the 64 bases copied with each cover every pattern (past
+        // them a deferred walk reads the text one base at a time)
         if (p.walks == 0)
-          p.walks = hb != PFAC_HASH_NONE ? PFAC_WALKS_DEFERRED : PFAC_WALKS_INLINE;
+          p.walks = (hb != PFAC_HASH_NONE && h.max_len <= kWindow) ? PFAC_WALKS_DEFERRED
+                                                                    : PFAC_WALKS_INLINE;
         *out = p;
         return PFAC_OK;
       }

@@ -546,3 +546,14 @@ def test_paper_shaped_reads_every_ladder_plan(plan):
                                                          READS_PLANS[plan]), flush=True)
     res = _gpu(w.patterns, w.text, plan=READS_PLANS[plan])
     _check(res, w.patterns, w.text)
+
+
+def test_default_plan_defers_walks_only_within_the_copied_window():
+    """Deferred walks carry 64 bases: the library defers them only when no
+    pattern is longer (100-base patterns walk at once)."""
+    g = W.rng(71)
+    short = pf.Table(W.random_patterns(2000, 16, 64, g))
+    long_ = pf.Table(W.random_patterns(2000, 100, 100, g))
+    assert short.default_plan(1 << 24)["walks"] == pf.PFAC_WALKS_DEFERRED
+    p = long_.default_plan(1 << 24)
+    assert p["walks"] == pf.PFAC_WALKS_INLINE and p["hash_bits"] == 18 and p["depth"] == 9
