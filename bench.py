@@ -366,6 +366,20 @@ def main():
                          "Aho-Corasick scan split over %d threads, %d passes "
                          "(wall %.2f s, about %.0f core-seconds)"
                          % (sample >> 20, len(w.patterns), threads, reps, dt, dt * threads)}
+        # the same oracle on one thread, a smaller sample for about half the time
+        sample1 = min(n, 8 << 20)
+        text1 = w.ascii(0, sample1)
+        reps1 = 0
+        t1 = time.perf_counter()
+        while True:
+            oracle.scan(w.patterns, text1, threads=1)
+            reps1 += 1
+            dt1 = time.perf_counter() - t1
+            if dt1 >= args.cpu_seconds / 2 or reps1 >= 1000:
+                break
+        cpu["one_thread_value"] = round(sample1 * reps1 / dt1 / 1e9, 4)
+        cpu["one_thread_sample"] = ("first %d Mbase, %d passes on one thread (wall %.2f s)"
+                                    % (sample1 >> 20, reps1, dt1))
 
     tuned = None
     if args.autotune:
