@@ -557,3 +557,32 @@ def test_default_plan_defers_walks_only_within_the_copied_window():
     assert short.default_plan(1 << 24)["walks"] == pf.PFAC_WALKS_DEFERRED
     p = long_.default_plan(1 << 24)
     assert p["walks"] == pf.PFAC_WALKS_INLINE and p["hash_bits"] == 18 and p["depth"] == 9
+
+
+def test_two_streams_keep_their_own_scratch():
+    """Calls on two streams at once (each stream has its own library scratch:
+    tile counts, hit slots, look-back words, deferred walks) give each text
+    its own results."""
+    w = W.plain_workload(1, n=3_000_001, num_patterns=2000)
+    tab = pf.Table(w.patterns)
+    a = torch.from_numpy(w.text).to(DEV)
+    b = torch.flip(a, [0]).contiguous()
+    ra0 = pf.match(tab, a, hit_cap=w.n)
+    rb0 = pf.match(tab, b, hit_cap=w.n)
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    outs = []
+    for _ in range(4):
+        with torch.cuda.stream(s1):
+            ra = pf.match(tab, a, hit_cap=w.n)
+        with torch.cuda.stream(s2):
+            rb = pf.match(tab, b, hit_cap=w.n)
+        outs.append((ra, rb))
+    torch.cuda.synchronize()
+    for ra, rb in outs:
+        for r, r0 in ((ra, ra0), (rb, rb0)):
+            assert torch.equal(r.match, r0.match)
+            assert r.total() == r0.total() and r.num_hits() == r0.num_hits()
+            assert np.array_equal(r.hit_list(), r0.hit_list())
+    m_ref, total_ref = oracle.scan(w.patterns, w.text, threads=8)
+    assert np.array_equal(ra0.match.cpu().numpy(), m_ref) and ra0.total() == total_ref
