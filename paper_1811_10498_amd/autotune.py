@@ -1,8 +1,8 @@
 """Launch-plan autotuner.
 
 A plan (threads per workgroup, filter depth D, trie levels kept in LDS, size
-of the second filter) never
-changes results, only speed.  The tuner times every candidate plan the
+of the second filter, walks at once or deferred) never changes results, only
+speed.  The tuner times every candidate plan the
 library accepts on a sample of the caller's own text and keeps the fastest,
 cached per (table, encoding, size class).  Timing uses HIP events on the
 current stream.
@@ -23,15 +23,23 @@ BLOCKS = (256, 512, 768, 1024)
 DEPTHS = (7, 8, 9, 10)
 LEVELS = (0, L.PFAC_LEVELS_NONE)
 HASHES = (0, L.PFAC_HASH_NONE)
+# library choice (deferred behind the second filter when patterns fit the
+# copied window) or at once: which is faster depends on how many windows the
+# text lets through, which only the text shows
+WALKS = (0, L.PFAC_WALKS_INLINE)
 
 
-def candidate_plans(blocks=BLOCKS, depths=DEPTHS, levels=LEVELS, hashes=HASHES) -> List[dict]:
+def candidate_plans(blocks=BLOCKS, depths=DEPTHS, levels=LEVELS, hashes=HASHES,
+                    walks=WALKS) -> List[dict]:
     out = []
     for b in blocks:
         for d in depths:
             for lv in levels:
                 for hb in hashes:
-                    out.append(dict(block=b, depth=d, levels=lv, hash_bits=hb))
+                    for wk in walks:
+                        if hb == L.PFAC_HASH_NONE and wk != 0:
+                            continue            # without the filter walks are at once
+                        out.append(dict(block=b, depth=d, levels=lv, hash_bits=hb, walks=wk))
     return out
 
 
@@ -52,7 +60,7 @@ class TuneResult:
 
 class Autotuner:
     def __init__(self, cache_path: Optional[str] = None, reps: int = 3,
-                 sample_bases: int = 32 << 20):
+                 sample_bases: int = 128 << 20):
         self.cache: Dict[str, TuneResult] = {}
         self.cache_path = cache_path
         self.reps = reps
