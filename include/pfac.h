@@ -163,8 +163,12 @@ void pfac_free_table(pfac_table* table);
  *               (may exceed hit_cap: the caller can retry with a larger buffer),
  *               [1] = total (pattern, position) occurrences, every pattern ID counted
  *   plan        NULL for the library's choice
- * Scratch memory (tile status words for the ordered hit list) is owned by the
- * library, one area per (device, stream); calls on one stream reuse it in order.
+ * Scratch memory (per-tile hit counts, occurrence counts and hit slots, the
+ * finish kernel's look-back words, the buffer of deferred walks) is owned by
+ * the library, one area per (device, stream); calls on one stream reuse it in
+ * order, calls on different streams may overlap.  A call on a larger text
+ * than any before on its stream grows the area (hipMalloc, synchronous), so
+ * pfac_match is not meant for graph capture; prepared batches are.
  */
 int pfac_match(const pfac_table* table, const void* d_text, uint64_t n, int enc,
                int32_t* d_match, pfac_hit* d_hits, uint64_t hit_cap, uint64_t* d_counters,
