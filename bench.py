@@ -5,7 +5,11 @@ One step = one pfac_match call over the whole text of the plain large-text
 workload (256 Mbase first-order Markov ASCII text, 10,000 patterns of 16-64
 bases, 70 % cut from the text): text ingest, per-position walks, dense int32
 match array, ordered hit list and occurrence count.  The text and the table
-are resident in HBM before the timed region.  Prints one JSON line.
+are resident in HBM before the timed region; untimed calls for 50 ms (the
+GPU raises its clocks under load) and W warm-up steps come first, then K
+steps back to back between two synchronisations, with two HIP events on the
+launching stream around them.  Prints one JSON line (with --paper-ladder
+instead the paper's placement ladder, one line per case and a table).
 """
 import argparse
 import hashlib
