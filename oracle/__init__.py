@@ -48,13 +48,15 @@ def build_mutant(k: int, out_dir: str) -> str:
 
 def _declare(lib):
     P = ctypes.c_void_p
-    lib.oracle_scan.argtypes = [P, P, ctypes.c_uint32, P, ctypes.c_uint64, P, P, P]
+    u32, u64, i64 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int64
+    lib.oracle_scan.argtypes = [P, P, u32, P, u64, P, P, P]
     lib.oracle_scan.restype = ctypes.c_int
-    lib.oracle_scan_mt.argtypes = [P, P, ctypes.c_uint32, P, ctypes.c_uint64, P, P, P,
-                                   ctypes.c_int]
+    lib.oracle_scan_mt.argtypes = [P, P, u32, P, u64, P, P, P, ctypes.c_int, P]
     lib.oracle_scan_mt.restype = ctypes.c_int
-    lib.oracle_goto.argtypes = [P, P, ctypes.c_uint32, P, P, ctypes.c_int64]
-    lib.oracle_goto.restype = ctypes.c_int64
+    lib.oracle_occurrences.argtypes = [P, P, u32, P, u64, P, P, P, P, u64, P, P, P]
+    lib.oracle_occurrences.restype = ctypes.c_int
+    lib.oracle_goto.argtypes = [P, P, u32, P, P, i64]
+    lib.oracle_goto.restype = i64
     return lib
 
 
@@ -64,16 +66,7 @@ def _load():
         if _lib is None:
             if not os.path.exists(_LIB_PATH):
                 build(force=False)
-            lib = ctypes.CDLL(_LIB_PATH)
-            P = ctypes.c_void_p
-            lib.oracle_scan.argtypes = [P, P, ctypes.c_uint32, P, ctypes.c_uint64, P, P, P]
-            lib.oracle_scan.restype = ctypes.c_int
-            lib.oracle_scan_mt.argtypes = [P, P, ctypes.c_uint32, P, ctypes.c_uint64, P, P, P,
-                                           ctypes.c_int]
-            lib.oracle_scan_mt.restype = ctypes.c_int
-            lib.oracle_goto.argtypes = [P, P, ctypes.c_uint32, P, P, ctypes.c_int64]
-            lib.oracle_goto.restype = ctypes.c_int64
-            _lib = lib
+            _lib = _declare(ctypes.CDLL(_LIB_PATH))
     return _lib
 
 
@@ -103,8 +96,9 @@ def _as_text(text) -> np.ndarray:
     return t
 
 
-def scan(patterns, text, threads: int = 1, lib=None):
-    """Run the oracle.  Returns (match int32[n], total occurrences).
+def scan(patterns, text, threads: int = 1, lib=None, counts: bool = False):
+    """Run the oracle.  Returns (match int32[n], total occurrences), and with
+    ``counts`` also count uint32[n] = occurrences starting at each position.
 
     ``patterns`` is a sequence of ASCII byte strings (IDs 1..P in order);
     ``text`` is ASCII bytes or a uint8 array.  ``threads`` > 1 uses the
@@ -116,9 +110,10 @@ def scan(patterns, text, threads: int = 1, lib=None):
     t = _as_text(text)
     n = int(t.size)
     match = np.zeros(n, dtype=np.int32)
+    count = np.zeros(n, dtype=np.uint32) if counts else None
     total = ctypes.c_uint64(0)
     bad = ctypes.c_int64(-1)
-    if threads <= 1:
+    if threads <= 1 and not counts:
         rc = lib.oracle_scan(ctypes.cast(arr, ctypes.c_void_p), lens.ctypes.data, num,
                              t.ctypes.data if n else None, n,
                              match.ctypes.data if n else None,
@@ -127,11 +122,52 @@ def scan(patterns, text, threads: int = 1, lib=None):
         rc = lib.oracle_scan_mt(ctypes.cast(arr, ctypes.c_void_p), lens.ctypes.data, num,
                                 t.ctypes.data if n else None, n,
                                 match.ctypes.data if n else None,
-                                ctypes.addressof(total), ctypes.addressof(bad), int(threads))
+                                ctypes.addressof(total), ctypes.addressof(bad),
+                                int(max(1, threads)),
+                                count.ctypes.data if (counts and n) else None)
     del keep
     if rc != 0:
         raise OracleError(rc, bad.value)
+    if counts:
+        return match, int(total.value), count
     return match, int(total.value)
+
+
+def occurrences(patterns, text, lib=None):
+    """Every (start position, pattern ID) pair with the pattern at that start,
+    sub-patterns included: an int64 array (k, 2) in ascending position, then
+    ascending pattern length, then ascending ID.  The scan reports them by
+    end position; the order above is a plain sort of that list."""
+    lib = lib or _load()
+    arr, lens, keep, num = _pattern_args(patterns)
+    t = _as_text(text)
+    n = int(t.size)
+    match = np.zeros(max(1, n), dtype=np.int32)
+    total = ctypes.c_uint64(0)
+    nocc = ctypes.c_uint64(0)
+    bad = ctypes.c_int64(-1)
+    cap = 0
+    pos = np.zeros(1, dtype=np.uint32)
+    ids = np.zeros(1, dtype=np.int32)
+    for _ in range(2):              # first pass sizes the list
+        rc = lib.oracle_occurrences(ctypes.cast(arr, ctypes.c_void_p), lens.ctypes.data, num,
+                                    t.ctypes.data if n else None, n, match.ctypes.data, None,
+                                    pos.ctypes.data, ids.ctypes.data, cap,
+                                    ctypes.addressof(nocc), ctypes.addressof(total),
+                                    ctypes.addressof(bad))
+        if rc != 0:
+            raise OracleError(rc, bad.value)
+        if nocc.value <= cap:
+            break
+        cap = int(nocc.value)
+        pos = np.zeros(cap, dtype=np.uint32)
+        ids = np.zeros(cap, dtype=np.int32)
+    del keep
+    k = int(nocc.value)
+    plen = np.array([len(p) for p in patterns] or [0], dtype=np.int64)
+    out = np.stack([pos[:k].astype(np.int64), ids[:k].astype(np.int64)], axis=1)
+    order = np.lexsort((out[:, 1], plen[out[:, 1] - 1] if k else out[:, 1], out[:, 0]))
+    return out[order]
 
 
 def hits_of(match: np.ndarray):

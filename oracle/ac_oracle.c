@@ -18,6 +18,10 @@
  *                pattern ID counted (duplicates included).
  *   Only the four upper-case bytes A, C, G and T are bases (the table has
  *   four columns, Sec. V.A); any other text byte has no transition.
+ *   Optionally also
+ *     count[i] = number of pattern IDs k with T[i..i+|p_k|) == p_k, and
+ *     the list of every such pair (i, k) -- the sub-patterns too, which PFAC
+ *     itself does not report (Sec. IV names that limitation).
  *
  * How it computes it: the classic sequential Aho-Corasick machine the paper
  * summarises in Sec. III -- goto function built by inserting the keywords
@@ -185,17 +189,39 @@ static int build_failure(machine *m) {
   return OR_OK;
 }
 
+/* Where the occurrences of one scan go: the longest-wins match array
+ * (PFAC's report, Sec. IV), the total, and optionally the number of
+ * occurrences per start position and the list of every occurrence. */
+typedef struct {
+  int32_t *match;
+  uint32_t *bestlen;
+  uint64_t total;
+  uint32_t *count;     /* NULL or [n]: occurrences starting at each position */
+  uint32_t *occ_pos;   /* NULL or [cap]: start of each occurrence, in scan order */
+  int32_t *occ_id;     /* NULL or [cap]: its pattern ID */
+  uint64_t cap, nocc;  /* room in occ_pos/occ_id; occurrences seen (may exceed cap) */
+} sink;
+
 /* Record keyword k of length l ending at text index j. */
-static void record(int32_t *match, uint32_t *bestlen, uint64_t *total,
-                   uint64_t lo, uint64_t hi, uint64_t j, uint32_t k, uint32_t l) {
+static void record(sink *o, uint64_t lo, uint64_t hi, uint64_t j, uint32_t k, uint32_t l) {
 #if ORACLE_MUTANT == 3
   uint64_t s = j - l + (l > j ? 1 : 0);
 #else
   uint64_t s = j + 1 - l;
 #endif
   if (s < lo || s >= hi) return;
-  *total += 1;
+  o->total += 1;
   int32_t id = (int32_t)k + 1;
+  if (o->count) o->count[s] += 1;
+  if (o->occ_pos) {
+    if (o->nocc < o->cap) {
+      o->occ_pos[o->nocc] = (uint32_t)s;
+      o->occ_id[o->nocc] = id;
+    }
+    o->nocc += 1;
+  }
+  int32_t *match = o->match;
+  uint32_t *bestlen = o->bestlen;
 #if ORACLE_MUTANT == 2
   if (l > bestlen[s] || (l == bestlen[s] && id > match[s])) {
 #elif ORACLE_MUTANT == 5
@@ -211,8 +237,7 @@ static void record(int32_t *match, uint32_t *bestlen, uint64_t *total,
 /* One left-to-right pass (Sec. III) over text[lo .. min(n, hi+max_len-1)),
  * starting from the root at lo, keeping occurrences that start in [lo, hi). */
 static void scan_range(const machine *m, const uint8_t *text, uint64_t n,
-                       uint64_t lo, uint64_t hi, int32_t *match, uint32_t *bestlen,
-                       uint64_t *total) {
+                       uint64_t lo, uint64_t hi, sink *o) {
   uint64_t end = hi + (m->max_len ? m->max_len - 1 : 0);
   if (end > n) end = n;
   int64_t s = 0;
@@ -229,7 +254,7 @@ static void scan_range(const machine *m, const uint8_t *text, uint64_t n,
     int64_t t = (m->out_head[s] >= 0) ? s : m->dict[s];
     while (t >= 0) {
       for (int64_t k = m->out_head[t]; k >= 0; k = m->out_next[k])
-        record(match, bestlen, total, lo, hi, j, (uint32_t)k, m->kw_len[k]);
+        record(o, lo, hi, j, (uint32_t)k, m->kw_len[k]);
 #if ORACLE_MUTANT == 1
       t = -1;
 #else
@@ -258,8 +283,41 @@ int oracle_scan(const char *const *pats, const uint32_t *lens, uint32_t num,
   uint32_t *bestlen = (uint32_t *)calloc(n ? n : 1, sizeof(uint32_t));
   if (!bestlen) { machine_free(&m); return OR_E_NOMEM; }
   memset(match, 0, n * sizeof(int32_t));
-  *total = 0;
-  scan_range(&m, text, n, 0, n, match, bestlen, total);
+  sink o = {match, bestlen, 0, NULL, NULL, NULL, 0, 0};
+  scan_range(&m, text, n, 0, n, &o);
+  *total = o.total;
+  free(bestlen);
+  machine_free(&m);
+  return OR_OK;
+}
+
+/* Every occurrence, one scan (single thread): match[] and *total as in
+ * oracle_scan; count[i] (optional, n entries) = occurrences starting at i;
+ * occ_pos/occ_id (optional, cap entries) = start and pattern ID of every
+ * occurrence in the order the scan reports them (by end position, then
+ * along the dictionary links); *num_occ = the number of occurrences, which
+ * may exceed cap (only the first cap are written). */
+int oracle_occurrences(const char *const *pats, const uint32_t *lens, uint32_t num,
+                       const uint8_t *text, uint64_t n, int32_t *match, uint32_t *count,
+                       uint32_t *occ_pos, int32_t *occ_id, uint64_t cap, uint64_t *num_occ,
+                       uint64_t *total, int64_t *bad_index) {
+  if ((num && (!pats || !lens)) || (n && (!text || !match)) || !total || !num_occ ||
+      (cap && (!occ_pos || !occ_id)))
+    return OR_E_ARG;
+  machine m;
+  int rc = build_machine(&m, pats, lens, num, bad_index);
+  if (rc != OR_OK) return rc;
+  uint32_t *bestlen = (uint32_t *)calloc(n ? n : 1, sizeof(uint32_t));
+  if (!bestlen) { machine_free(&m); return OR_E_NOMEM; }
+  memset(match, 0, n * sizeof(int32_t));
+  if (count) memset(count, 0, n * sizeof(uint32_t));
+  uint32_t dummy_pos = 0;
+  int32_t dummy_id = 0;
+  sink o = {match, bestlen, 0, count, cap ? occ_pos : &dummy_pos, cap ? occ_id : &dummy_id,
+            cap, 0};
+  scan_range(&m, text, n, 0, n, &o);
+  *total = o.total;
+  *num_occ = o.nocc;
   free(bestlen);
   machine_free(&m);
   return OR_OK;
@@ -269,22 +327,21 @@ typedef struct {
   const machine *m;
   const uint8_t *text;
   uint64_t n, lo, hi;
-  int32_t *match;
-  uint32_t *bestlen;
-  uint64_t total;
+  sink o;
 } chunk_job;
 
 static void *chunk_main(void *arg) {
   chunk_job *jb = (chunk_job *)arg;
-  scan_range(jb->m, jb->text, jb->n, jb->lo, jb->hi, jb->match, jb->bestlen, &jb->total);
+  scan_range(jb->m, jb->text, jb->n, jb->lo, jb->hi, &jb->o);
   return NULL;
 }
 
 /* Multi-threaded oracle scan: contiguous chunks of start positions, one
- * thread each.  Identical result to oracle_scan. */
+ * thread each.  Identical result to oracle_scan; count (optional, n
+ * entries) receives the occurrences starting at each position. */
 int oracle_scan_mt(const char *const *pats, const uint32_t *lens, uint32_t num,
                    const uint8_t *text, uint64_t n, int32_t *match, uint64_t *total,
-                   int64_t *bad_index, int nthreads) {
+                   int64_t *bad_index, int nthreads, uint32_t *count) {
   if ((num && (!pats || !lens)) || (n && (!text || !match)) || !total || nthreads < 1)
     return OR_E_ARG;
   machine m;
@@ -297,18 +354,19 @@ int oracle_scan_mt(const char *const *pats, const uint32_t *lens, uint32_t num,
     free(bestlen); free(jobs); free(th); machine_free(&m); return OR_E_NOMEM;
   }
   memset(match, 0, n * sizeof(int32_t));
+  if (count) memset(count, 0, n * sizeof(uint32_t));
   uint64_t per = (n + (uint64_t)nthreads - 1) / (uint64_t)nthreads;
   for (int t = 0; t < nthreads; ++t) {
     uint64_t lo = per * (uint64_t)t, hi = lo + per;
     if (lo > n) lo = n;
     if (hi > n) hi = n;
-    jobs[t] = (chunk_job){&m, text, n, lo, hi, match, bestlen, 0};
+    jobs[t] = (chunk_job){&m, text, n, lo, hi, {match, bestlen, 0, count, NULL, NULL, 0, 0}};
     pthread_create(&th[t], NULL, chunk_main, &jobs[t]);
   }
   *total = 0;
   for (int t = 0; t < nthreads; ++t) {
     pthread_join(th[t], NULL);
-    *total += jobs[t].total;
+    *total += jobs[t].o.total;
   }
   free(bestlen); free(jobs); free(th);
   machine_free(&m);

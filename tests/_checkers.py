@@ -35,6 +35,19 @@ def brute(patterns, text):
     return match, total
 
 
+def brute_pairs(patterns, text):
+    """Every (start, pattern ID) pair with the pattern at that start, sorted
+    by start, then pattern length, then ID."""
+    text = bytes(text)
+    out = []
+    for i in range(len(text)):
+        for k, p in enumerate(patterns, start=1):
+            if text.startswith(p, i):
+                out.append((i, len(p), k))
+    out.sort()
+    return [(i, k) for i, _, k in out]
+
+
 def kmer_check(patterns, text):
     """(match int32[n], total) by per-length packed-key lookup."""
     t = np.asarray(np.frombuffer(bytes(text), dtype=np.uint8) if isinstance(text, (bytes, bytearray))

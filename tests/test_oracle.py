@@ -9,7 +9,7 @@ import pytest
 import oracle
 import workloads as W
 from oracle.pointwise import PointOracle
-from _checkers import brute, kmer_check, read_golden
+from _checkers import brute, brute_pairs, kmer_check, read_golden
 
 COLS_ACGT = {c: i for i, c in enumerate("ACGT")}
 
@@ -88,6 +88,20 @@ def test_worked_examples(name):
     assert bm == m.tolist() and bt == total
 
 
+@pytest.mark.parametrize("name", ["ex1_fig1_text.txt", "ex2_table1_text.txt"])
+def test_worked_examples_every_occurrence(name):
+    """The all-occurrence list and per-position counts on the hand-derived examples."""
+    ex = read_golden(name)
+    pats = _pats(ex["patterns"])
+    text = ex["text"].encode()
+    occ = oracle.occurrences(pats, text)
+    want = [tuple(int(x) for x in c.split(",")) for c in ex["occurrences"].split()]
+    assert [tuple(r) for r in occ.tolist()] == want
+    m, total, cnt = oracle.scan(pats, text, counts=True)
+    assert int(cnt.sum()) == total == len(want)
+    assert cnt.tolist() == [sum(1 for i, _ in want if i == q) for q in range(len(text))]
+
+
 # ---------------------------------------------------------------- brute force
 
 PATTERN_SETS = [
@@ -113,6 +127,12 @@ def test_exhaustive_short_texts(pset):
     bm, bt = brute(pats, big)
     assert m.tolist() == bm
     assert total == bt
+    occ = oracle.occurrences(pats, big)
+    assert [tuple(r) for r in occ.tolist()] == brute_pairs(pats, big)
+    m2, t2, cnt = oracle.scan(pats, big, counts=True, threads=3)
+    assert m2.tolist() == bm and t2 == bt
+    assert cnt.tolist() == np.bincount(occ[:, 0], minlength=len(big)).tolist() if len(occ) else \
+        not cnt.any()
 
 
 def test_random_tiny_cases():
@@ -141,6 +161,8 @@ def test_random_tiny_cases():
         assert total == bt, (case, pats, text)
         mt, tt = oracle.scan(pats, text, threads=3)
         assert mt.tolist() == bm and tt == bt
+        occ = oracle.occurrences(pats, text)
+        assert [tuple(r) for r in occ.tolist()] == brute_pairs(pats, text), (case, pats, text)
 
 
 # ---------------------------------------------------------------- special cases

@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import workloads as W
-from _checkers import brute, read_golden
+from _checkers import brute, brute_pairs, read_golden
 
 MUTANTS = {
     1: "no dictionary links",
@@ -58,3 +58,29 @@ def test_planted_mistake_is_caught(k, tmp_path):
     path = oracle.build_mutant(k, str(tmp_path))
     lib = oracle._declare(ctypes.CDLL(path))
     assert not _pins_pass(lib), "mutant %d (%s) passed every pin" % (k, MUTANTS[k])
+
+
+def _occurrence_pins_pass(lib) -> bool:
+    """The all-occurrence list against brute force, on its own."""
+    texts = []
+    for L in range(0, 6):
+        texts += ["".join(x) for x in itertools.product("ACGT", repeat=L)]
+    big = ("N".join(texts) + "NACGTnacgtACGT").encode()
+    for pats in PATTERN_SETS:
+        occ = oracle.occurrences(pats, big, lib=lib)
+        if [tuple(r) for r in occ.tolist()] != brute_pairs(pats, big):
+            return False
+    return True
+
+
+def test_reference_build_passes_the_occurrence_pins():
+    assert _occurrence_pins_pass(None)
+
+
+@pytest.mark.parametrize("k", [1, 3, 4, 6])
+def test_planted_mistake_in_the_scan_breaks_the_occurrence_list(k, tmp_path):
+    """Mistakes in the scan itself (not in the longest-wins rule) show in the
+    list of every occurrence."""
+    path = oracle.build_mutant(k, str(tmp_path))
+    lib = oracle._declare(ctypes.CDLL(path))
+    assert not _occurrence_pins_pass(lib), "mutant %d (%s) passed" % (k, MUTANTS[k])
