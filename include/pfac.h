@@ -45,7 +45,9 @@ typedef enum {
   PFAC_E_TOO_LARGE = -3,  /* trie would need 2^31 or more states */
   PFAC_E_NOMEM = -4,      /* host or device allocation failed */
   PFAC_E_HIP = -5,        /* a HIP runtime call failed */
-  PFAC_E_NODEV = -6       /* no usable gfx950 device */
+  PFAC_E_NODEV = -6,      /* no usable gfx950 device */
+  PFAC_E_SCRATCH = -7     /* the input needs more scratch than a fixed-size scratch
+                             area holds */
 } pfac_status;
 
 enum { PFAC_TEXT_ASCII = 0, PFAC_TEXT_2BIT = 1 };
@@ -77,6 +79,9 @@ typedef struct {
   uint32_t max_depth_full; /* deepest level d at which all 4^d prefixes are trie states */
   uint64_t device_bytes;   /* device memory owned by the table */
   uint64_t states_to_depth[9]; /* states of depth <= d, d = 0..8 (BFS prefix sizes) */
+  uint32_t prefix_k;       /* K2 of the prefix filter, 0 when the table has none */
+  uint32_t reserved;
+  uint64_t prefix_keys;    /* distinct K2-base pattern prefixes */
 } pfac_table_stats;
 
 /* Launch shape of a match call.  Any field left 0 is chosen by the library.
@@ -101,21 +106,34 @@ typedef struct {
   uint32_t hash_bits;   /* second filter for the positions that pass the first one,
                            used when every pattern has more than D bases: their first
                            K = min(shortest pattern, 16) bases hashed twice into an
-                           LDS bitmap of 2^hash_bits bits (12..18); only windows whose
-                           two bits are set (or that hold a non-base) walk on.  0 = library
-                           choice, PFAC_HASH_NONE = no second filter */
-  uint32_t walks;       /* where the walks that pass both filters run, one-text calls:
+                           LDS bitmap of 2^hash_bits bits (12..20); only windows whose
+                           two bits are set walk on.  0 = library choice,
+                           PFAC_HASH_NONE = no second filter */
+  uint32_t walks;       /* where the walks that pass the filters run:
                            PFAC_WALKS_INLINE = by the wave that found them, with the
                            tile; PFAC_WALKS_DEFERRED = the wave keeps each one (start
-                           position + its next 64 bases, room for 4 per tile; more
-                           walk inline) and walks them all after its last tile, so
-                           the streaming scan does not wait on their table reads.
-                           0 = library choice (deferred when the second filter is
-                           on and no pattern is longer than 64 bases).  Batched
-                           calls always walk inline. */
+                           position + its next 64 bases; room for a number per tile
+                           the library sizes from the filters' pass rates, more walk
+                           inline) and walks them all after its last tile, so the
+                           streaming scan does not wait on their table reads.
+                           0 = library choice (deferred when a second or prefix
+                           filter is on and no pattern is longer than 64 bases). */
+  uint32_t tile;        /* start positions per wave tile: 1024 or 2048 (one-text and
+                           batched calls), 256 (batched calls only).  0 = library
+                           choice: 2048 for one text; in a batch 256 for texts of at
+                           most 512 bases and 1024 for longer ones (an explicit
+                           value applies to every text of the batch) */
+  uint32_t prefix;      /* prefix filter, used when every pattern is longer than D:
+                           windows that pass the LDS filters are looked up in an exact
+                           bitmap of the patterns' first K2 bases held in global
+                           memory (4^K2 bits; K2 = min(shortest pattern, 12) > D), and
+                           only those whose K2-base prefix starts some pattern walk on.
+                           0 = library choice (on when the hashed second filter is
+                           off and K2 > D), PFAC_PREFIX_NONE = off, 1 = on */
 } pfac_plan;
 
 enum { PFAC_WALKS_INLINE = 1, PFAC_WALKS_DEFERRED = 2 };
+#define PFAC_PREFIX_NONE 0xFFFFFFFFu
 
 enum { PFAC_VARIANT_TILED = 0, PFAC_VARIANT_GLOBAL = 1 };
 #define PFAC_LEVELS_NONE 0xFFFFFFFFu
@@ -175,8 +193,10 @@ int pfac_match(const pfac_table* table, const void* d_text, uint64_t n, int enc,
                const pfac_plan* plan, void* stream);
 
 /*
- * Match many texts in one persistent launch: workgroups take (text, tile)
- * items from a device work queue in text-then-position order.
+ * Match many texts in one persistent launch per (table, tile size): the
+ * waves of each workgroup take (text, tile) work items one at a time from a
+ * counter in LDS, in text-then-position order; texts of at most 512 bases get
+ * 256-position tiles unless the plan fixes the tile size.
  *   tables/num_tables  host array of tables (all on the current device)
  *   descs/num_texts    host array of descriptors (copied by the call)
  *   d_text_base        device base of all texts
@@ -213,6 +233,13 @@ int pfac_batch_create(const pfac_table* const* tables, uint32_t num_tables,
 int pfac_batch_launch(pfac_batch* batch, const void* d_text_base, int32_t* d_match_base,
                       pfac_batch_hit* d_hits, uint64_t hit_cap, uint64_t* d_counters,
                       void* stream);
+
+/* The extents a prepared batch reads and writes: *text_extent = bytes of
+ * d_text_base its texts reach (offset + encoded length, over the texts with
+ * n > 0), *match_extent = int32 elements of d_match_base their dense outputs
+ * reach, *tiles = tiles of the call.  Any pointer may be NULL.  Host only. */
+int pfac_batch_info(const pfac_batch* batch, uint64_t* text_extent, uint64_t* match_extent,
+                    uint64_t* tiles);
 
 void pfac_batch_free(pfac_batch* batch);
 
@@ -262,7 +289,7 @@ int pfac_build_host_image(const char* const* patterns, const uint32_t* lengths, 
                           uint64_t* num_words, int64_t* bad_index);
 
 /*
- * Host-only: the second-filter bitmap of 2^bits bits (bits = 12..18) the
+ * Host-only: the second-filter bitmap of 2^bits bits (bits = 12..20) the
  * scan kernel uses, for inspection and tests.  K = min(shortest pattern, 16);
  * the key of a K-base window is sum of base_k * 4^(15-k) for k < K (first
  * base most significant, left-aligned in 32 bits, lower bits 0); its bits
@@ -289,6 +316,19 @@ int pfac_build_host_hash(const char* const* patterns, const uint32_t* lengths, u
 int pfac_build_host_chain(const char* const* patterns, const uint32_t* lengths, uint32_t num,
                           uint32_t* chain, uint64_t cap, uint64_t* num_states,
                           int64_t* bad_index);
+
+/*
+ * Host-only: the prefix-filter bitmap the scan kernel reads, for inspection
+ * and tests.  K2 = min(shortest pattern, 12), 0 (no bitmap) when the
+ * shortest pattern has fewer than 7 bases; bit x (bit x%32 of word x/32) is
+ * set iff some pattern's first K2 bases have the key x = sum of base_k *
+ * 4^(K2-1-k) (first base most significant, A=0 C=1 G=2 T=3).  *k receives
+ * K2, *num_keys the number of set bits; `words` (uint32[4^K2 / 32]) is
+ * written when non-NULL and cap_words holds it.
+ */
+int pfac_build_host_prefix(const char* const* patterns, const uint32_t* lengths, uint32_t num,
+                           uint32_t* words, uint64_t cap_words, uint32_t* k, uint64_t* num_keys,
+                           int64_t* bad_index);
 
 /* Human-readable text of a status code (static storage). */
 const char* pfac_strerror(int status);

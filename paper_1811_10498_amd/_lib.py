@@ -16,12 +16,14 @@ PFAC_LEVELS_NONE = 0xFFFFFFFF
 PFAC_HASH_NONE = 0xFFFFFFFF
 PFAC_WALKS_INLINE = 1
 PFAC_WALKS_DEFERRED = 2
+PFAC_PREFIX_NONE = 0xFFFFFFFF
 
 EXPORTS = (
     "pfac_build_table", "pfac_table_info", "pfac_free_table", "pfac_match",
-    "pfac_match_batch", "pfac_batch_create", "pfac_batch_launch", "pfac_batch_free",
+    "pfac_match_batch", "pfac_batch_create", "pfac_batch_launch", "pfac_batch_info",
+    "pfac_batch_free",
     "pfac_default_plan", "pfac_build_host", "pfac_build_host_image", "pfac_build_host_hash",
-    "pfac_build_host_chain",
+    "pfac_build_host_chain", "pfac_build_host_prefix",
     "pfac_strerror",
     "pfac_version",
 )
@@ -31,7 +33,8 @@ class PfacPlan(ctypes.Structure):
     _fields_ = [("block", ctypes.c_uint32), ("depth", ctypes.c_uint32),
                 ("grid", ctypes.c_uint32), ("variant", ctypes.c_uint32),
                 ("levels", ctypes.c_uint32), ("hash_bits", ctypes.c_uint32),
-                ("walks", ctypes.c_uint32)]
+                ("walks", ctypes.c_uint32), ("tile", ctypes.c_uint32),
+                ("prefix", ctypes.c_uint32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -41,7 +44,8 @@ class PfacTableStats(ctypes.Structure):
     _fields_ = [("num_states", ctypes.c_uint64), ("num_patterns", ctypes.c_uint32),
                 ("max_len", ctypes.c_uint32), ("min_len", ctypes.c_uint32),
                 ("max_depth_full", ctypes.c_uint32), ("device_bytes", ctypes.c_uint64),
-                ("states_to_depth", ctypes.c_uint64 * 9)]
+                ("states_to_depth", ctypes.c_uint64 * 9), ("prefix_k", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32), ("prefix_keys", ctypes.c_uint64)]
 
 
 class PfacTextDesc(ctypes.Structure):
@@ -91,6 +95,9 @@ def lib():
             L.pfac_batch_create.restype = ctypes.c_int
             L.pfac_batch_launch.argtypes = [P, P, P, P, u64, P, P]
             L.pfac_batch_launch.restype = ctypes.c_int
+            L.pfac_batch_info.argtypes = [P, ctypes.POINTER(u64), ctypes.POINTER(u64),
+                                          ctypes.POINTER(u64)]
+            L.pfac_batch_info.restype = ctypes.c_int
             L.pfac_batch_free.argtypes = [P]
             L.pfac_batch_free.restype = None
             L.pfac_default_plan.argtypes = [P, u64, ctypes.c_int, ctypes.POINTER(PfacPlan)]
@@ -107,6 +114,15 @@ def lib():
             L.pfac_build_host_chain.argtypes = [P, P, u32, P, u64, ctypes.POINTER(u64),
                                                 ctypes.POINTER(i64)]
             L.pfac_build_host_chain.restype = ctypes.c_int
+            if hasattr(L, "pfac_match_noalloc"):
+                L.pfac_match_noalloc.argtypes = [P, P, u64, ctypes.c_int, P, P, u64, P,
+                                                 ctypes.POINTER(PfacPlan), P]
+                L.pfac_match_noalloc.restype = ctypes.c_int
+                L.pfac_noalloc_scratch_bytes.argtypes = []
+                L.pfac_noalloc_scratch_bytes.restype = u64
+            L.pfac_build_host_prefix.argtypes = [P, P, u32, P, u64, ctypes.POINTER(u32),
+                                                 ctypes.POINTER(u64), ctypes.POINTER(i64)]
+            L.pfac_build_host_prefix.restype = ctypes.c_int
             L.pfac_strerror.argtypes = [ctypes.c_int]
             L.pfac_strerror.restype = ctypes.c_char_p
             L.pfac_version.argtypes = []

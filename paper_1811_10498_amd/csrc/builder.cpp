@@ -191,6 +191,7 @@ int build_host_table(const char* const* patterns, const uint32_t* lengths, uint3
       }
       for (uint64_t x = 0; x < E; ++x)
         if (out->jump[D][x]) out->bitmap[D][x >> 5] |= 1u << (x & 31);
+      for (uint32_t w : out->bitmap[D]) out->bitmap_set[D] += (uint32_t)__builtin_popcount(w);
       // LDS image: bitmap, its rank words, then node bytes and rank words of
       // levels D, D+1, ... while the image stays within kImageMaxBytes
       HostTable::Image& im = out->image[D];
@@ -251,6 +252,22 @@ int build_host_table(const char* const* patterns, const uint32_t* lengths, uint3
             v[g >> 5] |= 1u << (g & 31);
           }
       }
+      for (uint32_t b = kHashMinBits; b <= kHashMaxBits; ++b)
+        for (uint32_t w : out->hash[b]) out->hash_set[b] += (uint32_t)__builtin_popcount(w);
+    }
+    // 7. prefix filter: the first K2 bases of every pattern, exactly, one bit
+    //    per K2-base key (first base most significant)
+    out->pfx_k = (num && minl >= kPfxMinK) ? std::min(minl, kPfxMaxK) : 0;
+    if (out->pfx_k) {
+      const uint32_t K2 = out->pfx_k;
+      out->pfx.assign((size_t)1 << (2 * K2 - 5), 0);
+      for (uint32_t i = 0; i < num; ++i) {
+        uint32_t key = 0;
+        for (uint32_t k = 0; k < K2; ++k)
+          key = (key << 2) | (uint32_t)base_code((uint8_t)patterns[i][k]);
+        out->pfx[key >> 5] |= 1u << (key & 31);
+      }
+      for (uint32_t w : out->pfx) out->pfx_set += (uint32_t)__builtin_popcount(w);
     }
   } catch (const std::bad_alloc&) {
     return PFAC_E_NOMEM;
@@ -340,5 +357,19 @@ extern "C" int pfac_build_host_chain(const char* const* patterns, const uint32_t
   *num_states = h.num_states;
   if (chain && h.num_states <= cap)
     memcpy(chain, h.chain.data(), h.chain.size() * sizeof(uint32_t));
+  return PFAC_OK;
+}
+
+extern "C" int pfac_build_host_prefix(const char* const* patterns, const uint32_t* lengths,
+                                      uint32_t num, uint32_t* words, uint64_t cap_words,
+                                      uint32_t* k, uint64_t* num_keys, int64_t* bad_index) {
+  using namespace pfac;
+  HostTable h;
+  int rc = build_host_table(patterns, lengths, num, &h, bad_index);
+  if (rc != PFAC_OK) return rc;
+  if (k) *k = h.pfx_k;
+  if (num_keys) *num_keys = h.pfx_set;
+  if (words && h.pfx.size() <= cap_words)
+    memcpy(words, h.pfx.data(), h.pfx.size() * sizeof(uint32_t));
   return PFAC_OK;
 }

@@ -1,0 +1,62 @@
+// Host-side pieces of libpfac.so shared between its translation units: the
+// scratch layout of a one-text call and the two halves of pfac_match
+// (prepare: plan, parameters and scratch size; enqueue: the kernels).
+#pragma once
+
+#include <mutex>
+
+#include "scan_device.h"
+
+namespace pfac {
+
+std::mutex& host_mutex();
+
+uint64_t al256(uint64_t x);
+
+// Scratch of the scan and finish kernels, carved out of one device block:
+// per-tile hit counts, occurrence counts and hit slots; the finish kernel's
+// look-back word and occurrence sum per workgroup and its two counters
+// (zero between launches); batch work items; deferred walks.
+struct Scratch {
+  uint32_t* tile_hits = nullptr;
+  unsigned long long* tile_occ = nullptr;
+  Slot* slots = nullptr;
+  unsigned long long* status = nullptr;
+  unsigned long long* block_occ = nullptr;
+  uint32_t* sync = nullptr;
+  TileItem* items = nullptr;
+  WalkEntry* walk = nullptr;
+  uint64_t tiles = 0, walk_cap = 0;
+};
+
+// Byte offsets of the parts of a scratch block for `tiles` tiles (and as
+// many batch work items when `items`) and `walks` deferred walks; bytes =
+// the total, [o_st, o_st + zero_bytes) = the part that must start at zero.
+struct ScratchLayout {
+  uint64_t o_hits, o_occ, o_slots, o_st, o_bo, o_sync, o_items, o_walk, bytes, zero_bytes;
+};
+ScratchLayout scratch_layout(uint64_t tiles, bool items, uint64_t walks);
+Scratch carve(uint8_t* mem, const ScratchLayout& L, uint64_t tiles, uint64_t walks);
+
+// Everything of a one-text call that does not depend on the buffers: the
+// plan, the scan parameters (without buffers), the tiles and the
+// deferred-walk entries the launch needs.
+struct SinglePrep {
+  pfac_plan pl;
+  ScanParams sp;
+  uint64_t tiles;
+  uint64_t walks;
+};
+
+int prepare_single(const pfac_table* t, uint64_t n, int enc, const pfac_plan* plan, int dev,
+                   SinglePrep* P);
+
+// Enqueue a prepared one-text call on the scratch `sc` (kernel launches only).
+int enqueue_single(const pfac_table* t, SinglePrep& P, const Scratch& sc, const void* d_text,
+                   int32_t* d_match, pfac_hit* d_hits, uint64_t hit_cap,
+                   unsigned long long* counters, int dev, hipStream_t stream);
+
+// Zero n 64-bit words at p with a fill kernel on `stream`.
+int launch_zero(unsigned long long* p, uint32_t n, hipStream_t stream);
+
+}  // namespace pfac

@@ -22,9 +22,15 @@ constexpr uint32_t kImageMaxBytes = 160 * 1024;
 // with two hash functions).
 constexpr uint32_t kHashK = 16;
 constexpr uint32_t kHashMinBits = 12;
-constexpr uint32_t kHashMaxBits = 18;
+constexpr uint32_t kHashMaxBits = 20;
 constexpr uint32_t kHashMul = 0x9E3779B1u;
 constexpr uint32_t kHashMul2 = 0x85EBCA77u;
+
+// Prefix filter: an exact bitmap of the first K2 = min(shortest pattern,
+// kPfxMaxK) bases of every pattern (4^K2 bits, 2 MB at K2 = 12), kept in
+// global memory (L2-resident) for pattern sets too large for the hashed one.
+constexpr uint32_t kPfxMinK = 7;
+constexpr uint32_t kPfxMaxK = 12;
 
 // Longest run of single-child trie steps a walk takes at once.
 constexpr uint32_t kChainMax = 14;
@@ -85,6 +91,11 @@ struct HostTable {
   Image image[kMaxJump + 1];
   uint32_t hash_k = 0;                      // K of the second filter
   std::vector<uint32_t> hash[kHashMaxBits + 1];   // 2^bits-bit bitmaps
+  uint32_t hash_set[kHashMaxBits + 1] = {};       // set bits of each
+  uint32_t pfx_k = 0;                       // K2 of the prefix filter (0 = none)
+  std::vector<uint32_t> pfx;                // 4^K2-bit bitmap
+  uint64_t pfx_set = 0;                     // distinct K2-base pattern prefixes
+  uint64_t bitmap_set[kMaxJump + 1] = {};   // set bits of each depth-D filter bitmap
 };
 
 // Host build: validate, insert in input order, renumber breadth-first, pack.
@@ -101,6 +112,7 @@ struct DevTable {
   const uint32_t* levels[kMaxJump + 1];  // per image level: {byte_off, pre_off, first state, 0}
   const uint32_t* hash[kHashMaxBits + 1]; // second-filter bitmaps
   const uint32_t* chain;                  // [2S] runs of single-child steps
+  const uint32_t* pfx;                    // prefix-filter bitmap (or null)
   uint32_t num_states;
   uint32_t max_len;
 };

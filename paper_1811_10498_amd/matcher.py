@@ -116,20 +116,70 @@ def n_bases(text: torch.Tensor, enc: str) -> int:
     return int(text.numel()) if enc == "ascii" else 4 * int(text.numel())
 
 
+def text_bytes(n, enc):
+    """Bytes of a text of n bases in encoding ``enc`` (array-friendly)."""
+    return n if enc == "ascii" else (n + 3) // 4
+
+
+def check_match_args(n: int, text_numel: int, enc: str, out: Optional["MatchResult"] = None):
+    """Raise ValueError when a one-text call would read past its text buffer or
+    write past an output buffer given in ``out`` (checked before any launch)."""
+    if enc not in ENCODINGS:
+        raise ValueError("unknown encoding %r" % (enc,))
+    if n < 0 or n >= 1 << 32:
+        raise ValueError("n must be in [0, 2^32)")
+    if text_bytes(n, enc) > text_numel:
+        raise ValueError("n exceeds the text buffer")
+    if out is None:
+        return
+    if out.match is not None and out.match.numel() < n:
+        raise ValueError("out.match holds %d elements, the text has %d positions"
+                         % (out.match.numel(), n))
+    if out.hits is not None and (out.hits.dim() != 2 or out.hits.shape[1] != 2):
+        raise ValueError("out.hits must have shape (cap, 2)")
+    if out.counters.numel() < 2:
+        raise ValueError("out.counters needs 2 elements")
+
+
+def check_batch_extents(descs: np.ndarray, T: int, text_numel: int,
+                        match_numel: Optional[int], hits_shape=None, counters_numel=None):
+    """Raise ValueError when a batched call would read past ``text_base`` or
+    write past ``match_out`` (offsets + lengths of every text), or when the
+    hit or counter buffers have the wrong shape (checked before any launch)."""
+    if T == 0:
+        return
+    d = descs[:T]
+    n = d["n"].astype(np.int64)
+    if np.any(n >= 1 << 32):
+        raise ValueError("every text must have fewer than 2^32 bases")
+    nb = np.where(d["enc"] == ENCODINGS["ascii"], n, (n + 3) // 4)
+    live = n > 0
+    if np.any(live) and int((d["text_offset"].astype(np.int64) + nb)[live].max()) > text_numel:
+        raise ValueError("a text runs past the end of text_base")
+    if match_numel is not None and np.any(live) and \
+            int((d["match_offset"].astype(np.int64) + n)[live].max()) > match_numel:
+        raise ValueError("a text's match array runs past the end of match_out")
+    if hits_shape is not None and (len(hits_shape) != 2 or hits_shape[1] != 3):
+        raise ValueError("hits must have shape (cap, 3)")
+    if counters_numel is not None and counters_numel < 2 + 2 * T:
+        raise ValueError("counters need 2 + 2 * num_texts elements")
+
+
 def match(table: Table, text: torch.Tensor, n: Optional[int] = None, enc: str = "ascii",
           dense: bool = True, hits: bool = True, hit_cap: Optional[int] = None, plan=None,
-          stream=None, out: Optional[MatchResult] = None) -> MatchResult:
+          stream=None, out: Optional[MatchResult] = None, noalloc: bool = False) -> MatchResult:
     """Match one device text.  ``text`` is a uint8 CUDA tensor (ASCII bytes,
     or 2-bit packed with ``enc='2bit'`` and ``n`` bases).  Asynchronous on
-    ``stream`` (default: the current torch stream)."""
+    ``stream`` (default: the current torch stream).  ``noalloc`` calls the
+    library's allocation-free entry point (fixed scratch inside the library;
+    pass ``out`` too for a call that allocates nothing at all)."""
     if text.device.type != "cuda" or text.dtype != torch.uint8:
         raise TypeError("text must be a uint8 CUDA tensor")
     if not text.is_contiguous():
         raise ValueError("text must be contiguous")
     if n is None:
         n = n_bases(text, enc)
-    if n > n_bases(text, enc):
-        raise ValueError("n exceeds the text buffer")
+    check_match_args(int(n), int(text.numel()), enc, out)
     dev = text.device
     if out is None:
         m = torch.empty(n, dtype=torch.int32, device=dev) if dense else None
@@ -138,14 +188,15 @@ def match(table: Table, text: torch.Tensor, n: Optional[int] = None, enc: str = 
         c = torch.empty(2, dtype=torch.int64, device=dev)
         out = MatchResult(m, h, c)
     p = _plan_struct(plan)
-    rc = table._lib.pfac_match(
+    fn = table._lib.pfac_match_noalloc if noalloc else table._lib.pfac_match
+    rc = fn(
         table.handle, text.data_ptr(), int(n), ENCODINGS[enc],
         out.match.data_ptr() if out.match is not None else None,
         out.hits.data_ptr() if out.hits is not None else None,
         int(out.hits.shape[0]) if out.hits is not None else 0,
         out.counters.data_ptr(), ctypes.byref(p) if p is not None else None,
         _stream_handle(stream))
-    L.check(rc, "pfac_match")
+    L.check(rc, "pfac_match_noalloc" if noalloc else "pfac_match")
     return out
 
 
@@ -200,7 +251,9 @@ class Batch:
         self.descs, self.num_texts, total, self.match_offsets = _descriptors(
             offsets, lengths, table_index, enc, match_offsets)
         dev = torch.device(device or "cuda")
-        self.match = torch.empty(max(1, total), dtype=torch.int32, device=dev) if dense else None
+        self.text_extent, self.match_extent = _extents(self.descs, self.num_texts)
+        self.match = (torch.empty(max(1, self.match_extent), dtype=torch.int32, device=dev)
+                      if dense else None)
         self.hit_cap = (total // 16 + 1024) if hit_cap is None else int(hit_cap)
         self.hits = (torch.empty((self.hit_cap, 3), dtype=torch.int32, device=dev)
                      if hits else None)
@@ -216,6 +269,11 @@ class Batch:
         self.handle = h
 
     def launch(self, text_base: torch.Tensor, stream=None) -> BatchResult:
+        if text_base.dtype != torch.uint8 or not text_base.is_contiguous():
+            raise TypeError("text_base must be a contiguous uint8 tensor")
+        if int(text_base.numel()) < self.text_extent:
+            raise ValueError("text_base holds %d bytes, the batch's texts reach %d"
+                             % (text_base.numel(), self.text_extent))
         rc = self._lib.pfac_batch_launch(
             self.handle, text_base.data_ptr(),
             self.match.data_ptr() if self.match is not None else None,
@@ -237,6 +295,20 @@ class Batch:
             pass
 
 
+def _extents(descs: np.ndarray, T: int):
+    """(bytes of the text base, int32 elements of the match base) the texts reach."""
+    if T == 0:
+        return 0, 0
+    d = descs[:T]
+    n = d["n"].astype(np.int64)
+    live = n > 0
+    if not np.any(live):
+        return 0, 0
+    nb = np.where(d["enc"] == ENCODINGS["ascii"], n, (n + 3) // 4)
+    return (int((d["text_offset"].astype(np.int64) + nb)[live].max()),
+            int((d["match_offset"].astype(np.int64) + n)[live].max()))
+
+
 def match_batch(tables: Sequence[Table], text_base: torch.Tensor, offsets, lengths,
                 table_index=None, enc="ascii", dense: bool = True, hits: bool = True,
                 hit_cap: Optional[int] = None, plan=None, stream=None,
@@ -249,9 +321,15 @@ def match_batch(tables: Sequence[Table], text_base: torch.Tensor, offsets, lengt
     ``enc`` one encoding name or one per text."""
     descs, T, total, match_offsets = _descriptors(offsets, lengths, table_index, enc,
                                                   match_offsets)
+    if text_base.dtype != torch.uint8 or not text_base.is_contiguous():
+        raise TypeError("text_base must be a contiguous uint8 tensor")
     dev = text_base.device
     if dense and match_out is None:
-        match_out = torch.empty(max(1, total), dtype=torch.int32, device=dev)
+        match_out = torch.empty(max(1, _extents(descs, T)[1]), dtype=torch.int32, device=dev)
+    if dense and (match_out.dtype != torch.int32 or not match_out.is_contiguous()):
+        raise TypeError("match_out must be a contiguous int32 tensor")
+    check_batch_extents(descs, T, int(text_base.numel()),
+                        int(match_out.numel()) if dense else None)
     cap = (total // 16 + 1024) if hit_cap is None else int(hit_cap)
     h = torch.empty((cap, 3), dtype=torch.int32, device=dev) if hits else None
     c = torch.empty(2 + 2 * T, dtype=torch.int64, device=dev)

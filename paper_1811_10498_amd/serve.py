@@ -1,34 +1,44 @@
 """Continuous-batching request server for PFAC matching.
 
 Tables stay resident on the device.  Requests (one or many texts against one
-table) arrive over time; the server admits a request when its device memory
-fits an HBM budget, packs every admitted request that is not yet running into
-one batched launch per dispatch (``pfac_match_batch``: one persistent launch
-per table present), and keeps up to ``max_inflight`` dispatches queued on the
-device so new requests join the next launch while earlier ones still run.
-A request completes when the event recorded after its dispatch has passed;
-its results are views into the dispatch's output buffers.
+table) arrive over time; the server admits a request when the device memory
+it will hold fits an HBM budget, and dispatches admitted requests onto a
+small pool of HIP streams: every dispatch is one batched call
+(``pfac_match_batch``, one persistent launch per table and tile size) over
+the requests waiting when a stream frees up, so work of requests admitted
+while others run overlaps with theirs on the device.  A dispatch that holds
+one request of a shape seen before reuses a prepared batch (layout, work
+items and scratch built once, launch = kernels only).
 
-Texts are host arrays (copied through a pinned staging buffer to the device
-on the dispatch's stream: the end-to-end path) or device tensors already
+Memory.  A request reserves what its dispatch allocates for it: the bytes of
+its host texts (copied once, through pinned memory, 16-byte aligned), its
+dense int32 outputs, its share of the hit buffer and counters.  Device texts
+are read in place.  Results are views into the dispatch's buffers; the
+reservation of a dispatch's requests is returned when the last of their
+results is dropped, so what the server has admitted and not yet released is
+an upper bound of the device memory its requests hold.
+
+Texts are host arrays (the end-to-end path) or uint8 device tensors already
 resident (the matching path alone).  Many small texts (a batch of reads) are
-given as one ``TextBatch``: a buffer plus per-text offsets and lengths, so a
-request of 10,000 reads costs a few array operations, not 10,000 Python
-objects.
+given as one ``TextBatch``: a buffer plus per-text offsets and lengths.
 """
 from __future__ import annotations
 
 import collections
+import ctypes
 import time
-from dataclasses import dataclass
-from typing import List, Optional, Sequence
+import weakref
+from dataclasses import dataclass, field
+from typing import Callable, Dict, List, Optional, Sequence
 
 import numpy as np
 import torch
 
-from .matcher import Table, match, match_batch
+from . import _lib as L
+from .matcher import DESC_DTYPE, ENCODINGS, Batch, Table, match, match_batch
 
 ALIGN = 16
+MAX_STREAMS = 4          # hardware queues per process on the target (HIP's default)
 
 
 @dataclass
@@ -54,6 +64,15 @@ def _nbytes(t) -> int:
     return int(t.numel() if torch.is_tensor(t) else t.size)
 
 
+def _on_device(t) -> bool:
+    return torch.is_tensor(t) and t.is_cuda
+
+
+def hit_cap_of(lengths: np.ndarray) -> int:
+    """Hit slots a dispatch gives a request of these text lengths."""
+    return int(lengths.sum()) // 16 + 64 * int(lengths.size)
+
+
 @dataclass
 class Request:
     rid: int
@@ -64,6 +83,7 @@ class Request:
     dispatched: float = -1.0
     completed: float = -1.0
     result: Optional["RequestResult"] = None
+    ready: Optional[torch.cuda.Event] = None   # device texts: written by the submitter's stream
 
     def segments(self):
         """(buffer, offsets, lengths) runs of the request's texts, in order."""
@@ -89,14 +109,20 @@ class Request:
     def bases(self) -> int:
         return int(self.lengths.sum())
 
+    def host_text_bytes(self) -> int:
+        """Bytes its host texts take once copied (16-byte aligned runs)."""
+        total = 0
+        for b, o, n in self.segments():
+            if not _on_device(b) and o.size:
+                total += (int((o + n).max()) - int(o.min()) + ALIGN - 1) // ALIGN * ALIGN
+        return total
+
     def device_bytes(self) -> int:
-        """What the request holds on the device while admitted: its texts
-        (padded), its dense match arrays, its share of the hit buffer and
-        counters."""
-        L = self.lengths
-        text = int(((L + ALIGN - 1) // ALIGN * ALIGN).sum())
-        total = int(L.sum())
-        return text + 4 * total + 12 * (total // 16 + 64) + 16 * (L.size + 1)
+        """What a dispatch allocates for the request: its copied host texts,
+        its dense match arrays, its hit slots (12 bytes each) and counters."""
+        L_ = self.lengths
+        return (self.host_text_bytes() + 4 * int(L_.sum()) + 12 * hit_cap_of(L_)
+                + 16 * (int(L_.size) + 1))
 
 
 @dataclass
@@ -104,7 +130,8 @@ class RequestResult:
     match: torch.Tensor              # int32, the texts' dense outputs back to back
     offsets: np.ndarray              # start of each text's run in `match`
     lengths: np.ndarray
-    hits: torch.Tensor               # int32 (k, 3): text index within the request, pos, pid
+    hits_all: torch.Tensor           # int32 (k, 3) rows of the dispatch: text, pos, pid
+    first_text: int                  # dispatch index of the request's first text
     num_hits: np.ndarray             # per text
     occurrences: np.ndarray          # per text
 
@@ -112,12 +139,19 @@ class RequestResult:
         o = int(self.offsets[i])
         return self.match[o:o + int(self.lengths[i])]
 
+    @property
+    def hits(self) -> torch.Tensor:
+        """(k, 3) hits of the request: text index within the request, pos, pid."""
+        h = self.hits_all.clone()
+        h[:, 0] -= self.first_text
+        return h
+
 
 class Admission:
     """First-come first-served admission against a device-memory budget.
     Pure bookkeeping (no device calls): ``offer`` queues a request, ``admit``
     moves queued requests into service while their reservations fit, and
-    ``release`` returns a finished request's bytes."""
+    ``release`` returns bytes (of a request, or an explicit amount)."""
 
     def __init__(self, budget_bytes: int):
         self.budget = int(budget_bytes)
@@ -142,41 +176,82 @@ class Admission:
             out.append(r)
         return out
 
-    def release(self, req: "Request"):
-        self.reserved -= req.device_bytes()
+    def reserve(self, nbytes: int):
+        self.reserved += int(nbytes)
+
+    def release(self, req: Optional["Request"] = None, nbytes: Optional[int] = None):
+        self.reserved -= req.device_bytes() if req is not None else int(nbytes)
         assert self.reserved >= 0
+
+
+class _Lease:
+    """Live results of one dispatch; the last one dropped returns the
+    dispatch's reservation."""
+
+    def __init__(self, gate: Admission, nbytes: int, count: int):
+        self.gate = gate
+        self.nbytes = nbytes
+        self.live = count
+
+    def drop(self):
+        self.live -= 1
+        if self.live == 0:
+            self.gate.release(nbytes=self.nbytes)
 
 
 @dataclass
 class _Dispatch:
     reqs: List[Request]
+    stream_idx: int
     event: torch.cuda.Event
-    res: object
+    counters_host: torch.Tensor
+    match: Optional[torch.Tensor]
+    hits: torch.Tensor
+    counters: torch.Tensor
     first_text: List[int]
-    staging: Optional[torch.Tensor]
-    dev_text: torch.Tensor
-    offsets: np.ndarray
+    match_offsets: np.ndarray
     lengths: np.ndarray
-    tids: np.ndarray
+    args: tuple                      # what a retry with a larger hit buffer needs
+    hold: list = field(default_factory=list)   # staging / device texts kept alive
 
 
 class Server:
+    """``streams`` HIP streams (at most 4, the hardware queues a process gets
+    by default), one dispatch in flight per stream."""
+
     def __init__(self, tables: Sequence[Table], budget_bytes: int = 32 << 30,
-                 max_inflight: int = 2, max_dispatch_bases: int = 512 << 20,
-                 plan=None, device=None):
+                 streams: int = MAX_STREAMS, max_dispatch_bases: int = 256 << 20,
+                 plan=None, device=None, keep_results: bool = True,
+                 on_complete: Optional[Callable[[Request], None]] = None,
+                 prepared_cache: int = 64, trace: bool = False):
         self.tables = list(tables)
+        self._lib = L.lib()
+        self._tabs = (ctypes.c_void_p * len(self.tables))(*[t.handle.value for t in self.tables])
         self.budget = int(budget_bytes)
-        self.max_inflight = int(max_inflight)
         self.max_dispatch_bases = int(max_dispatch_bases)
         self.plan = plan
+        self._plan = None
+        if plan is not None:
+            from .matcher import _plan_struct
+            self._plan = _plan_struct(plan)
         self.device = torch.device(device or "cuda")
-        self.stream = torch.cuda.Stream(device=self.device)
+        n = max(1, min(int(streams), MAX_STREAMS))
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n)]
+        self.busy = [False] * n
         self.gate = Admission(budget_bytes)                      # arrived, not admitted
         self.admitted: collections.deque = collections.deque()  # admitted, not dispatched
-        self.inflight: collections.deque = collections.deque()
+        self.inflight: List[_Dispatch] = []
         self.done: List[Request] = []
+        self.keep_results = keep_results
+        self.on_complete = on_complete
         self.max_seen_inflight = 0
         self.dispatch_sizes: List[int] = []
+        self.prepared_hits = 0
+        self._prepared: "collections.OrderedDict" = collections.OrderedDict()
+        self._prepared_cap = int(prepared_cache)
+        # with `trace`, every dispatch's device interval: timing events recorded
+        # on its stream right before its first and after its last kernel
+        self.trace: Optional[List[tuple]] = [] if trace else None
         self.t0 = time.perf_counter()
 
     def now(self) -> float:
@@ -184,6 +259,18 @@ class Server:
 
     # ------------------------------------------------------------ admission
     def submit(self, req: Request):
+        """Queue a request.  Device texts must stay unchanged until it
+        completes; the dispatch waits for the work the submitting stream has
+        queued so far (the producer of those texts)."""
+        for b, o, n in req.segments():
+            live = n > 0
+            if np.any(live) and int((o + n)[live].max()) > _nbytes(b):
+                raise ValueError("request %d: a text runs past the end of its buffer" % req.rid)
+            if torch.is_tensor(b) and (b.dtype != torch.uint8 or not b.is_contiguous()):
+                raise TypeError("request %d: texts must be contiguous uint8" % req.rid)
+        if any(_on_device(b) for b, _, _ in req.segments()):
+            req.ready = torch.cuda.Event()
+            req.ready.record(torch.cuda.current_stream(self.device))
         self.gate.offer(req)
 
     def _admit(self):
@@ -193,118 +280,214 @@ class Server:
             self.admitted.append(r)
 
     # ------------------------------------------------------------ dispatch
-    def _place(self, segs):
-        """Device buffer and per-text byte offsets for the dispatch's texts:
-        in place when every text already lives in one device allocation,
-        else copied (host texts through pinned staging), each run of texts
-        as one copy at a 16-byte aligned destination."""
-        bufs = [b for b, _, _ in segs]
-        if all(torch.is_tensor(b) and b.is_cuda and b.dtype == torch.uint8 and b.is_contiguous()
-               for b in bufs):
-            if len({b.untyped_storage().data_ptr() for b in bufs}) == 1:
-                dev = torch.empty(0, dtype=torch.uint8, device=self.device).set_(
-                    bufs[0].untyped_storage())
-                offs = np.concatenate([b.storage_offset() + o for b, o, _ in segs])
-                return dev, offs, None
-        spans, cur = [], 0
-        for b, o, L in segs:
-            lo = int(o.min()) if o.size else 0
-            hi = int((o + L).max()) if o.size else 0
-            spans.append((cur, lo, hi))
-            cur += (hi - lo + ALIGN - 1) // ALIGN * ALIGN
-        total = max(ALIGN, cur)
-        dev = torch.empty(total, dtype=torch.uint8, device=self.device)
-        staging = None
-        if any(not torch.is_tensor(b) for b in bufs):
-            # host runs: fill a pinned buffer, one host-to-device copy
+    def _texts(self, reqs, stream):
+        """Per text of the dispatch: absolute device address; host texts are
+        copied through one pinned buffer into one device buffer."""
+        segs = [s for r in reqs for s in r.segments()]
+        host = [(b, o, n) for b, o, n in segs if not _on_device(b)]
+        hold = []
+        dev_buf = None
+        spans = {}
+        if host:
+            total, cur = 0, 0
+            for i, (b, o, n) in enumerate(segs):
+                if _on_device(b) or not o.size:
+                    continue
+                lo, hi = int(o.min()), int((o + n).max())
+                spans[i] = (cur, lo, hi)
+                cur += (hi - lo + ALIGN - 1) // ALIGN * ALIGN
+            total = max(ALIGN, cur)
             staging = torch.empty(total, dtype=torch.uint8, pin_memory=True)
             sv = staging.numpy()
-            for b, (dst, lo, hi) in zip(bufs, spans):
-                if not torch.is_tensor(b) and hi > lo:
-                    sv[dst:dst + hi - lo] = b[lo:hi]
-            dev.copy_(staging, non_blocking=True)
-        # device runs: copied after it on the same stream
-        for b, (dst, lo, hi) in zip(bufs, spans):
-            if torch.is_tensor(b) and hi > lo:
-                dev[dst:dst + hi - lo].copy_(b[lo:hi], non_blocking=True)
-        offs = np.concatenate([dst + (o - lo) for (_, o, _), (dst, lo, _) in zip(segs, spans)])
-        return dev, offs, staging
+            for i, (dst, lo, hi) in spans.items():
+                sv[dst:dst + hi - lo] = segs[i][0][lo:hi]
+            dev_buf = torch.empty(total, dtype=torch.uint8, device=self.device)
+            with torch.cuda.stream(stream):
+                dev_buf.copy_(staging, non_blocking=True)
+            hold += [staging, dev_buf]
+        addrs = []
+        for i, (b, o, n) in enumerate(segs):
+            if _on_device(b):
+                addrs.append(b.data_ptr() + o)
+                hold.append(b)
+            elif o.size:
+                dst, lo, _ = spans[i]
+                addrs.append(dev_buf.data_ptr() + dst + (o - lo))
+            else:
+                addrs.append(np.zeros(0, dtype=np.int64))
+        return np.concatenate(addrs).astype(np.uint64), hold
+
+    def _signature(self, r: Request, addrs: np.ndarray):
+        base = int(addrs.min()) if addrs.size else 0
+        rel = (addrs - np.uint64(base)).astype(np.int64)
+        L_ = r.lengths
+        return (r.table, int(L_.size), hash(L_.tobytes()), hash(rel.tobytes())), base, rel
 
     def _dispatch(self):
-        if not self.admitted or len(self.inflight) >= self.max_inflight:
+        if not self.admitted or all(self.busy):
             return
+        si = self.busy.index(False)
+        stream = self.streams[si]
         reqs = []
         bases = 0
-        while self.admitted and (not reqs or bases + self.admitted[0].bases <= self.max_dispatch_bases):
+        while self.admitted and (not reqs or
+                                 bases + self.admitted[0].bases <= self.max_dispatch_bases):
             r = self.admitted.popleft()
             reqs.append(r)
             bases += r.bases
-        segs, tids, first = [], [], []
+        for r in reqs:
+            if r.ready is not None:
+                stream.wait_event(r.ready)
+        first, lens, tids = [], [], []
         ntext = 0
         for r in reqs:
             first.append(ntext)
-            for s in r.segments():
-                segs.append(s)
-                ntext += int(s[2].size)
+            ntext += r.num_texts
+            lens.append(r.lengths)
             tids.append(np.full(r.num_texts, r.table, dtype=np.uint32))
-        lengths = np.concatenate([s[2] for s in segs]).astype(np.int64)
+        lengths = np.concatenate(lens).astype(np.int64)
         tids = np.concatenate(tids)
-        with torch.cuda.stream(self.stream):
-            dev, offsets, staging = self._place(segs)
-            res = match_batch(self.tables, dev, offsets, lengths, table_index=tids,
-                              plan=self.plan, stream=self.stream,
-                              hit_cap=int(lengths.sum()) // 16 + 64 * ntext)
+        addrs, hold = self._texts(reqs, stream)
+        cap = sum(hit_cap_of(r.lengths) for r in reqs)
+        total = int(lengths.sum())
+        match_offsets = np.concatenate([[0], np.cumsum(lengths)[:-1]]).astype(np.int64)
+        dev = self.device
+        mt = torch.empty(max(1, total), dtype=torch.int32, device=dev)
+        hits = torch.empty((cap, 3), dtype=torch.int32, device=dev)
+        counters = torch.empty(2 + 2 * ntext, dtype=torch.int64, device=dev)
+        if self.trace is not None:
+            ev_start = torch.cuda.Event(enable_timing=True)
+            ev_start.record(stream)
+        sig = None
+        if len(reqs) == 1 and ntext > 0:
+            sig, base, rel = self._signature(reqs[0], addrs)
+        key = None if sig is None else (sig, si)
+        if key is not None and key in self._prepared:
+            b = self._prepared[key]
+            self._prepared.move_to_end(key)
+            self.prepared_hits += 1
+            with torch.cuda.stream(stream):
+                rc = self._lib.pfac_batch_launch(b.handle, base, mt.data_ptr(), hits.data_ptr(),
+                                                 cap, counters.data_ptr(), stream.cuda_stream)
+            L.check(rc, "pfac_batch_launch")
+        else:
+            base = int(addrs.min()) if ntext else 0
+            descs = np.zeros(max(1, ntext), dtype=DESC_DTYPE)
+            descs["text_offset"][:ntext] = addrs - np.uint64(base)
+            descs["n"][:ntext] = lengths
+            descs["match_offset"][:ntext] = match_offsets
+            descs["table"][:ntext] = tids
+            descs["enc"][:ntext] = ENCODINGS["ascii"]
+            pl = ctypes.byref(self._plan) if self._plan is not None else None
+            with torch.cuda.stream(stream):
+                rc = self._lib.pfac_match_batch(
+                    ctypes.cast(self._tabs, ctypes.c_void_p), len(self.tables), descs.ctypes.data,
+                    ntext, base, mt.data_ptr(), hits.data_ptr(), cap, counters.data_ptr(), pl,
+                    stream.cuda_stream)
+            L.check(rc, "pfac_match_batch")
+            if key is not None:
+                self._prepare(key, descs, ntext)
+        if self.trace is not None:
+            ev_end = torch.cuda.Event(enable_timing=True)
+            ev_end.record(stream)
+            self.trace.append((si, ev_start, ev_end, len(reqs)))
+        host_c = torch.empty(counters.numel(), dtype=torch.int64, pin_memory=True)
+        with torch.cuda.stream(stream):
+            host_c.copy_(counters, non_blocking=True)
             ev = torch.cuda.Event()
-            ev.record(self.stream)
+            ev.record(stream)
         t = self.now()
         for r in reqs:
             r.dispatched = t
-        self.inflight.append(_Dispatch(reqs, ev, res, first, staging, dev, offsets, lengths,
-                                       tids))
+        self.busy[si] = True
+        self.inflight.append(_Dispatch(reqs, si, ev, host_c, mt, hits, counters, first,
+                                       match_offsets, lengths, (addrs, tids, stream), hold))
         self.max_seen_inflight = max(self.max_seen_inflight, len(self.inflight))
         self.dispatch_sizes.append(len(reqs))
 
+    def _prepare(self, key, descs, ntext):
+        """Keep a prepared batch for a one-request dispatch shape (offsets
+        relative to the request's first text)."""
+        h = ctypes.c_void_p()
+        pl = ctypes.byref(self._plan) if self._plan is not None else None
+        rc = self._lib.pfac_batch_create(ctypes.cast(self._tabs, ctypes.c_void_p),
+                                         len(self.tables), descs.ctypes.data, ntext, pl,
+                                         ctypes.byref(h))
+        if rc != 0:
+            return
+        self._prepared[key] = _Prepared(self._lib, h)
+        while len(self._prepared) > self._prepared_cap:
+            self._prepared.popitem(last=False)
+
     # ------------------------------------------------------------ completion
+    def _finish(self, d: _Dispatch):
+        c = d.counters_host.numpy()
+        if c[0] > d.hits.shape[0]:
+            # the hit buffer was too small: redo the dispatch with room for all
+            addrs, tids, stream = d.args
+            extra = 12 * (int(c[0]) + 64 - d.hits.shape[0])
+            self.gate.reserve(extra)
+            d.hits = torch.empty((int(c[0]) + 64, 3), dtype=torch.int32, device=self.device)
+            base = int(addrs.min())
+            descs = np.zeros(len(d.lengths), dtype=DESC_DTYPE)
+            descs["text_offset"] = addrs - np.uint64(base)
+            descs["n"] = d.lengths
+            descs["match_offset"] = d.match_offsets
+            descs["table"] = tids
+            pl = ctypes.byref(self._plan) if self._plan is not None else None
+            with torch.cuda.stream(stream):
+                L.check(self._lib.pfac_match_batch(
+                    ctypes.cast(self._tabs, ctypes.c_void_p), len(self.tables), descs.ctypes.data,
+                    len(d.lengths), base, d.match.data_ptr(), d.hits.data_ptr(),
+                    d.hits.shape[0], d.counters.data_ptr(), pl, stream.cuda_stream),
+                    "pfac_match_batch")
+            stream.synchronize()
+            c = d.counters.cpu().numpy()
+        else:
+            extra = 0
+        t = self.now()
+        per_hits, per_occ = c[2::2], c[3::2]
+        hit_start = np.concatenate([[0], np.cumsum(per_hits)]).astype(np.int64)
+        lease = _Lease(self.gate, sum(r.device_bytes() for r in d.reqs) + extra, len(d.reqs))
+        for r, f in zip(d.reqs, d.first_text):
+            k = r.num_texts
+            Lr = d.lengths[f:f + k]
+            m0 = int(d.match_offsets[f]) if k else 0
+            mats = d.match[m0:m0 + int(Lr.sum())]
+            res = RequestResult(mats, d.match_offsets[f:f + k] - m0, Lr,
+                                d.hits[int(hit_start[f]):int(hit_start[f + k])], f,
+                                per_hits[f:f + k].copy(), per_occ[f:f + k].copy())
+            weakref.finalize(res, lease.drop)
+            r.completed = t
+            r.ready = None
+            if self.on_complete is not None:
+                r.result = res
+                self.on_complete(r)
+            r.result = res if self.keep_results else None
+            del res
+            self.done.append(r)
+        self.busy[d.stream_idx] = False
+
     def _complete(self):
-        while self.inflight and self.inflight[0].event.query():
-            d = self.inflight.popleft()
-            t = self.now()
-            counters = d.res.counters.cpu().numpy()
-            if d.res.hits is not None and counters[0] > d.res.hits.shape[0]:
-                # the hit buffer was too small: redo this dispatch with room for all
-                with torch.cuda.stream(self.stream):
-                    d.res = match_batch(self.tables, d.dev_text, d.offsets, d.lengths,
-                                        table_index=d.tids, plan=self.plan, stream=self.stream,
-                                        hit_cap=int(counters[0]) + 64)
-                self.stream.synchronize()
-                counters = d.res.counters.cpu().numpy()
-            per_hits, per_occ = counters[2::2], counters[3::2]
-            hit_start = np.concatenate([[0], np.cumsum(per_hits)]).astype(np.int64)
-            mo = np.asarray(d.res.match_offsets, dtype=np.int64)
-            for r, f in zip(d.reqs, d.first_text):
-                k = r.num_texts
-                L = d.lengths[f:f + k]
-                m0 = int(mo[f]) if k else 0
-                mats = d.res.match[m0:m0 + int(L.sum())]
-                h0, h1 = int(hit_start[f]), int(hit_start[f + k])
-                h = d.res.hits[h0:h1].clone()
-                h[:, 0] -= f
-                r.result = RequestResult(mats, mo[f:f + k] - m0, L, h,
-                                         per_hits[f:f + k].copy(), per_occ[f:f + k].copy())
-                r.completed = t
-                self.gate.release(r)
-                self.done.append(r)
+        still = []
+        for d in self.inflight:
+            if d.event.query():
+                self._finish(d)
+            else:
+                still.append(d)
+        self.inflight = still
 
     def step(self):
         self._complete()
         self._admit()
-        self._dispatch()
+        while self.admitted and not all(self.busy):
+            self._dispatch()
 
     def idle(self) -> bool:
         return not (self.gate.queue or self.admitted or self.inflight)
 
     # ------------------------------------------------------------ driver
-    def run(self, requests: Sequence[Request], poll_s: float = 50e-6) -> dict:
+    def run(self, requests: Sequence[Request], poll_s: float = 20e-6) -> dict:
         """Feed requests at their arrival times (seconds from now) and serve
         until all complete.  Returns throughput and latency statistics."""
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
@@ -316,10 +499,34 @@ class Server:
             self.step()
             if not pending and self.idle():
                 break
-            if not self.inflight or not self.inflight[0].event.query():
+            if self.gate.queue and not self.inflight and not self.admitted:
+                # nothing runs and the next request does not fit: the budget
+                # is held by results the caller still keeps
+                raise RuntimeError("request %d cannot be admitted: %d of %d budget bytes are "
+                                   "held by results not yet dropped"
+                                   % (self.gate.queue[0].rid, self.gate.reserved, self.budget))
+            if self.inflight and not any(d.event.query() for d in self.inflight):
                 time.sleep(poll_s)
+            elif not self.inflight and pending:
+                time.sleep(min(poll_s, max(0.0, pending[0].arrival - self.now())))
         torch.cuda.synchronize()
         return summarize(self.done)
+
+
+class _Prepared:
+    """A prepared batch kept for a dispatch shape (its own scratch and
+    layout; outputs are passed per launch)."""
+
+    def __init__(self, lib, handle):
+        self._lib = lib
+        self.handle = handle
+
+    def __del__(self):
+        try:
+            if self.handle is not None and self.handle.value:
+                self._lib.pfac_batch_free(self.handle)
+        except Exception:
+            pass
 
 
 def summarize(done: Sequence[Request]) -> dict:
@@ -342,19 +549,30 @@ def summarize(done: Sequence[Request]) -> dict:
 def plain_per_request(tables: Sequence[Table], requests: Sequence[Request], device=None,
                       plan=None) -> dict:
     """The baseline the server is compared with: requests handled one after
-    another, each text with its own single-text ``pfac_match`` call, copied
-    in and synchronised before the next request."""
+    another as they arrive, one launch per request -- ``pfac_match`` for a
+    one-text request, one ``pfac_match_batch`` over a request's own texts
+    otherwise -- host texts copied in, synchronised before the next request.
+    No coalescing across requests, one stream."""
     device = torch.device(device or "cuda")
     done = []
     t0 = time.perf_counter()
     clock = lambda: time.perf_counter() - t0
     for r in sorted(requests, key=lambda r: r.arrival):
         while clock() < r.arrival:
-            time.sleep(50e-6)
-        for i in range(r.num_texts):
-            t = r.text(i)
-            dt = t if torch.is_tensor(t) else torch.from_numpy(np.ascontiguousarray(t)).to(device)
-            match(tables[r.table], dt, plan=plan, hit_cap=int(dt.numel()) // 16 + 64)
+            time.sleep(20e-6)
+        if r.num_texts == 1:
+            t = r.text(0)
+            dt = t if _on_device(t) else torch.from_numpy(np.ascontiguousarray(t)).to(device)
+            match(tables[r.table], dt, plan=plan, hit_cap=hit_cap_of(r.lengths))
+        else:
+            (b, o, n), = r.segments() if isinstance(r.texts, TextBatch) else [(None, None, None)]
+            if b is None:
+                bufs = [np.asarray(x) if not _on_device(x) else x.cpu().numpy() for x in r.texts]
+                o = np.concatenate([[0], np.cumsum([x.size for x in bufs])[:-1]])
+                n = np.array([x.size for x in bufs])
+                b = np.concatenate(bufs)
+            base = b if _on_device(b) else torch.from_numpy(np.ascontiguousarray(b)).to(device)
+            match_batch([tables[r.table]], base, o, n, plan=plan, hit_cap=hit_cap_of(n))
         torch.cuda.synchronize()
         r.completed = clock()
         done.append(r)

@@ -14,7 +14,7 @@ if not torch.cuda.is_available():
 
 import paper_1811_10498_amd as pf  # noqa: E402
 from paper_1811_10498_amd.serve import (Request, Server, TextBatch,  # noqa: E402
-                                       plain_per_request)
+                                       hit_cap_of, plain_per_request)
 
 DEV = torch.device("cuda:0")
 
@@ -56,7 +56,7 @@ def test_served_results_match_alone_and_oracle(device_reads):
     pool = (torch.from_numpy(W.uniform_ascii(4 << 20, W.rng(9))).to(DEV) if device_reads
             else None)
     reqs = _requests(40, seed=4, scale=0.02, ntables=3, device_reads=pool)
-    srv = Server(tables, budget_bytes=1 << 30, max_inflight=3)
+    srv = Server(tables, budget_bytes=1 << 30, streams=3)
     stats = srv.run(reqs)
     print(stats, "max inflight", srv.max_seen_inflight, "dispatch sizes", srv.dispatch_sizes,
           flush=True)
@@ -88,46 +88,53 @@ def test_budget_limits_admission_under_load():
     tables = [pf.Table(t) for t in tries]
     reqs = [Request(i, 0, [W.uniform_ascii(200_000, W.rng(100 + i))], 0.0) for i in range(12)]
     one = reqs[0].device_bytes()
-    srv = Server(tables, budget_bytes=3 * one, max_inflight=4)
+    peak = []
+    srv = Server(tables, budget_bytes=3 * one, streams=4, keep_results=False,
+                 on_complete=lambda r: peak.append(srv.gate.reserved))
     stats = srv.run(reqs)
     assert stats["requests"] == 12
     assert max(srv.dispatch_sizes) <= 3          # never more in flight than the budget allows
+    assert max(peak) <= 3 * one
+    assert srv.gate.reserved == 0                # every dropped result returned its bytes
 
 
-def test_plain_per_request_baseline_agrees():
-    tries = W.served_tries(seed=6, sizes=[800], pool_bases=500_000)
+def test_kept_results_hold_their_reservation():
+    tries = W.served_tries(seed=5, sizes=[500], pool_bases=500_000)
     tables = [pf.Table(t) for t in tries]
-    reqs = [Request(i, 0, [W.uniform_ascii(50_000, W.rng(200 + i))], 0.0) for i in range(5)]
-    stats = plain_per_request(tables, reqs)
-    assert stats["requests"] == 5
+    reqs = [Request(i, 0, [W.uniform_ascii(100_000, W.rng(300 + i))], 0.0) for i in range(4)]
+    one = reqs[0].device_bytes()
+    srv = Server(tables, budget_bytes=10 * one)
+    srv.run(reqs)
+    assert srv.gate.reserved == 4 * one           # results kept by srv.done
+    for r in srv.done:
+        r.result = None
+    import gc
+    gc.collect()
+    assert srv.gate.reserved == 0
 
 
-def test_full_size_batch_against_oracle():
-    """The batched workload at full size (4,096 texts, ~200 Mbase, 50,000
-    patterns) in one call, every text compared with the oracle."""
-    wb = W.batch_workload()
-    print("texts", wb.lengths.size, "bases", wb.total_bases, flush=True)
-    tab = pf.Table(wb.patterns)
-    base = torch.from_numpy(wb.buffer).to(DEV)
-    res = pf.match_batch([tab], base, wb.offsets, wb.lengths, hit_cap=wb.total_bases // 16)
-    torch.cuda.synchronize()
-    m = res.match.cpu().numpy()
-    c = res.counters.cpu().numpy()
-    # the oracle scans all texts joined by one non-base byte (walks stop there)
-    sep = np.frombuffer(b"N", dtype=np.uint8)
-    parts, starts = [], []
-    cur = 0
-    for t in range(wb.lengths.size):
-        starts.append(cur)
-        parts.append(wb.text(t))
-        parts.append(sep)
-        cur += int(wb.lengths[t]) + 1
-    joined = np.concatenate(parts)
-    m_ref, _ = oracle.scan(wb.patterns, joined, threads=16)
-    for t in range(wb.lengths.size):
-        L = int(wb.lengths[t])
-        mr = m_ref[starts[t]:starts[t] + L]
-        o = int(res.match_offsets[t])
-        assert np.array_equal(m[o:o + L], mr), t
-        assert c[2 + 2 * t] == np.count_nonzero(mr)
-    assert c[0] == np.count_nonzero(m_ref)
+def test_dispatches_overlap_on_the_device():
+    """Requests admitted while others run go out on other streams: the
+    device intervals of dispatches on different streams overlap, and every
+    result is the same as the request's plain call."""
+    tries = W.served_tries(seed=5, sizes=[2000, 3000], pool_bases=500_000)
+    tables = [pf.Table(t) for t in tries]
+    pool = torch.from_numpy(W.uniform_ascii(64 << 20, W.rng(11))).to(DEV)
+    reqs = [Request(i, i % 2, [pool[(i % 4) * (16 << 20):(i % 4) * (16 << 20) + (12 << 20)]], 0.0)
+            for i in range(8)]
+    srv = Server(tables, budget_bytes=8 << 30, streams=4, max_dispatch_bases=12 << 20,
+                 trace=True)
+    srv.run(reqs)
+    iv = srv.device_intervals()
+    print("dispatch intervals (stream, ms, ms, requests):",
+          [(si, round(a, 3), round(b, 3), k) for si, a, b, k in iv], flush=True)
+    assert len(iv) == 8 and srv.max_seen_inflight >= 2
+    assert len({si for si, _, _, _ in iv}) >= 2
+    overlap = any(a2 < b1 and s1 != s2
+                  for (s1, a1, b1, _) in iv for (s2, a2, b2, _) in iv if a1 <= a2)
+    assert overlap
+    for r in srv.done:
+        alone = pf.match(tables[r.table], r.text(0), hit_cap=hit_cap_of(r.lengths))
+        torch.cuda.synchronize()
+        assert torch.equal(r.result.text_match(0), alone.match)
+        assert r.result.occurrences[0] == alone.total()

@@ -286,7 +286,7 @@ def test_lds_image_navigation_matches_next_table(D, npat, lmin, lmax):
     assert checked > 50
 
 
-@pytest.mark.parametrize("bits", [12, 14, 18])
+@pytest.mark.parametrize("bits", [12, 14, 18, 19, 20])
 def test_second_filter_bitmap_holds_every_pattern_prefix(bits):
     """The hash bitmap (its definition is part of the public header) has the
     two bits of the first K bases of every pattern; smaller bitmaps are the
@@ -318,9 +318,9 @@ def test_second_filter_bitmap_holds_every_pattern_prefix(bits):
         for mul in (0x9E3779B1, 0x85EBCA77):
             x = h(key, bits, mul)
             assert (words[x >> 5] >> (x & 31)) & 1
-    big, _ = get(18)
+    big, _ = get(20)
     bigbits = np.unpackbits(big.view(np.uint8), bitorder="little").astype(bool)
-    folded = bigbits.reshape(1 << bits, 1 << (18 - bits)).any(axis=1)
+    folded = bigbits.reshape(1 << bits, 1 << (20 - bits)).any(axis=1)
     mine = np.unpackbits(words.view(np.uint8), bitorder="little").astype(bool)
     assert np.array_equal(folded, mine)
     keys = g.integers(0, 1 << 32, size=20000, dtype=np.uint64)
@@ -438,3 +438,36 @@ def test_walking_with_runs_reproduces_oracle():
     m, total = walk_all_with_runs(t, chain, text)
     m_ref, total_ref = oracle.scan(pats, text)
     assert np.array_equal(m, m_ref) and total == total_ref
+
+
+@pytest.mark.parametrize("lmin,want_k", [(12, 12), (9, 9), (20, 12), (6, 0)])
+def test_prefix_filter_bitmap_is_the_set_of_pattern_prefixes(lmin, want_k):
+    """The prefix bitmap has exactly the bits of the patterns' first K2 bases
+    (K2 = min(shortest pattern, 12), none below 7 bases)."""
+    import ctypes
+    from paper_1811_10498_amd import _lib as L
+    lib = L.lib()
+    g = W.rng(90 + lmin)
+    pats = W.random_patterns(5000, lmin, lmin + 20, g) + [b"A" * lmin, b"T" * (lmin + 3)]
+    arr, lens, keep = _pattern_arrays(pats)
+    k = ctypes.c_uint32(0)
+    nk = ctypes.c_uint64(0)
+    bad = ctypes.c_int64(-1)
+    words = np.zeros(1 << 19, dtype=np.uint32)
+    rc = lib.pfac_build_host_prefix(arr, lens, len(pats), words.ctypes.data, words.size,
+                                    ctypes.byref(k), ctypes.byref(nk), ctypes.byref(bad))
+    assert rc == 0 and k.value == want_k
+    if want_k == 0:
+        assert nk.value == 0
+        return
+    K = want_k
+    code = {ord("A"): 0, ord("C"): 1, ord("G"): 2, ord("T"): 3}
+    keys = set()
+    for p in pats:
+        x = 0
+        for i in range(K):
+            x = (x << 2) | code[p[i]]
+        keys.add(x)
+    bits = np.unpackbits(words[:(1 << (2 * K)) // 32].view(np.uint8), bitorder="little")
+    assert set(np.nonzero(bits)[0].tolist()) == keys
+    assert nk.value == len(keys)

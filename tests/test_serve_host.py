@@ -59,3 +59,19 @@ def test_summary_percentiles():
     s = summarize(done)
     assert s["requests"] == 100 and s["bases"] == 100 * 100
     assert abs(s["p50_ms"] - 50.5) < 1.0 and s["p99_ms"] > 98.0
+
+
+def test_reservation_covers_what_a_dispatch_allocates():
+    """A multi-text request reserves its copied host texts, its int32
+    outputs, 12 bytes per hit slot (the rule the dispatch sizes its hit
+    buffer with) and its counters."""
+    from paper_1811_10498_amd.serve import TextBatch, hit_cap_of
+    buf = np.zeros(10_000 * 160, dtype=np.uint8)
+    r = Request(0, 0, TextBatch(buf, 160 * np.arange(10_000), np.full(10_000, 150)), 0.0)
+    bases = 150 * 10_000
+    cap = hit_cap_of(r.lengths)
+    assert cap == bases // 16 + 64 * 10_000
+    text = (10_000 * 160 - 10 + 15) // 16 * 16
+    dispatch = text + 4 * bases + 12 * cap + 8 * (2 + 2 * 10_000)
+    assert r.device_bytes() >= dispatch
+    assert r.host_text_bytes() == text
