@@ -193,6 +193,27 @@ int pfac_match(const pfac_table* table, const void* d_text, uint64_t n, int enc,
                const pfac_plan* plan, void* stream);
 
 /*
+ * Every occurrence of every pattern in one text: all pairs (start position,
+ * pattern ID) with the pattern starting there, including the shorter
+ * patterns PFAC's own report leaves out at a position where a longer one
+ * matches (the limitation Sec. IV names), and every ID of duplicate
+ * patterns.  Computed as a count pass (the scan of pfac_match, which sums
+ * the occurrences of each tile), a scan of the per-tile counts, and a write
+ * pass that walks again at the positions with a match.
+ *   d_occ       device pfac_hit[occ_cap] or NULL: the pairs in ascending
+ *               position, then ascending pattern length, then ascending ID;
+ *               only the first occ_cap are written
+ *   d_counters  device uint64[2] (required): [0] = positions with a match,
+ *               [1] = total occurrences (the full list length, may exceed
+ *               occ_cap: the caller can retry with a larger buffer)
+ *   plan        NULL for the library's choice (as pfac_match)
+ * Asynchronous on `stream`; scratch as in pfac_match, plus 8 bytes per tile.
+ */
+int pfac_match_all(const pfac_table* table, const void* d_text, uint64_t n, int enc,
+                   pfac_hit* d_occ, uint64_t occ_cap, uint64_t* d_counters,
+                   const pfac_plan* plan, void* stream);
+
+/*
  * Match many texts in one persistent launch per (table, tile size): the
  * waves of each workgroup take (text, tile) work items one at a time from a
  * counter in LDS, in text-then-position order; texts of at most 512 bases get

@@ -20,7 +20,7 @@ PFAC_PREFIX_NONE = 0xFFFFFFFF
 
 EXPORTS = (
     "pfac_build_table", "pfac_table_info", "pfac_free_table", "pfac_match",
-    "pfac_match_batch", "pfac_batch_create", "pfac_batch_launch", "pfac_batch_info",
+    "pfac_match_all", "pfac_match_batch", "pfac_batch_create", "pfac_batch_launch", "pfac_batch_info",
     "pfac_batch_free",
     "pfac_default_plan", "pfac_build_host", "pfac_build_host_image", "pfac_build_host_hash",
     "pfac_build_host_chain", "pfac_build_host_prefix",
@@ -87,6 +87,9 @@ def lib():
             L.pfac_match.argtypes = [P, P, u64, ctypes.c_int, P, P, u64, P,
                                      ctypes.POINTER(PfacPlan), P]
             L.pfac_match.restype = ctypes.c_int
+            L.pfac_match_all.argtypes = [P, P, u64, ctypes.c_int, P, u64, P,
+                                         ctypes.POINTER(PfacPlan), P]
+            L.pfac_match_all.restype = ctypes.c_int
             L.pfac_match_batch.argtypes = [P, u32, P, u32, P, P, P, u64, P,
                                            ctypes.POINTER(PfacPlan), P]
             L.pfac_match_batch.restype = ctypes.c_int

@@ -17,6 +17,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpfac.so")
+PROBE_SRC = os.path.join(CSRC, "probe", "stream_probe.hip")
+PROBE_LIB = os.path.join(HERE, "libpfac_probe.so")
 
 BLOCKS = (256, 512, 768, 1024)
 
@@ -90,7 +92,19 @@ def build(verbose: bool = False, jobs: int | None = None) -> str:
     if rc != 0:
         raise RuntimeError("link failed:\n" + out)
     os.replace(tmp, LIB)
+    build_probe()
     return LIB
+
+
+def build_probe() -> str:
+    """The bandwidth reference kernels of the benchmark's roofline
+    (measurement only, a library of their own)."""
+    tmp = PROBE_LIB + ".tmp%d" % os.getpid()
+    rc, out = _run([hipcc(), *HIPCC_FLAGS, "-shared", PROBE_SRC, "-o", tmp])
+    if rc != 0:
+        raise RuntimeError("probe build failed:\n" + out)
+    os.replace(tmp, PROBE_LIB)
+    return PROBE_LIB
 
 
 if __name__ == "__main__":

@@ -17,6 +17,7 @@
 #include <algorithm>
 #include <array>
 #include <new>
+#include <utility>
 
 #include "pfac_internal.h"
 
@@ -50,6 +51,7 @@ int build_host_table(const char* const* patterns, const uint32_t* lengths, uint3
     std::vector<std::array<uint32_t, 4>> kids(1, {0, 0, 0, 0});
     std::vector<int32_t> fin_pid(1, 0);
     std::vector<uint32_t> fin_mult(1, 0);
+    std::vector<std::pair<uint32_t, int32_t>> dups;   // (insertion-order state, id)
     uint32_t maxl = 0, minl = UINT32_MAX;
     for (uint32_t k = 0; k < num; ++k) {
       uint32_t s = 0;
@@ -65,6 +67,7 @@ int build_host_table(const char* const* patterns, const uint32_t* lengths, uint3
         s = kids[s][a];
       }
       if (fin_pid[s] == 0) fin_pid[s] = (int32_t)(k + 1);   // smallest ID wins
+      else dups.emplace_back(s, (int32_t)(k + 1));          // a further ID of the same string
       fin_mult[s] += 1;
       maxl = std::max(maxl, lengths[k]);
       minl = std::min(minl, lengths[k]);
@@ -101,6 +104,14 @@ int build_host_table(const char* const* patterns, const uint32_t* lengths, uint3
         if (c) out->next[i * 4 + a] = newid[c] | (fin_pid[c] ? kFinalBit : 0u);
       }
       out->out[i] = OutEntry{fin_pid[o], fin_mult[o]};
+    }
+    for (auto& d : dups) d.first = newid[d.first];
+    std::sort(dups.begin(), dups.end());
+    out->dup_state.resize(dups.size());
+    out->dup_id.resize(dups.size());
+    for (size_t i = 0; i < dups.size(); ++i) {
+      out->dup_state[i] = dups[i].first;
+      out->dup_id[i] = dups[i].second;
     }
     out->num_states = S;
     out->num_patterns = num;

@@ -407,6 +407,8 @@ struct Workspace {
   uint8_t* stage = nullptr;        // pinned host copy of `batch` being uploaded
   hipEvent_t staged = nullptr;     // recorded after the upload that read `stage`
   bool staged_pending = false;
+  uint8_t* extra = nullptr;        // scratch of passes after the scan (all occurrences)
+  uint64_t extra_cap = 0;
 };
 
 static std::map<std::pair<int, void*>, Workspace*> g_ws;
@@ -478,7 +480,40 @@ static Workspace* get_workspace(int dev, hipStream_t stream) {
   return ws;
 }
 
+static int ensure_extra(Workspace* ws, uint64_t bytes, hipStream_t stream) {
+  if (bytes <= ws->extra_cap && (ws->extra || bytes == 0)) return PFAC_OK;
+  const uint64_t cap = std::max<uint64_t>(bytes + bytes / 4, 1 << 16);
+  if (ws->extra) {
+    if (hipStreamSynchronize(stream) != hipSuccess) return PFAC_E_HIP;
+    (void)hipFree(ws->extra);
+    ws->extra = nullptr;
+    ws->extra_cap = 0;
+  }
+  void* m = nullptr;
+  if (hipMalloc(&m, cap) != hipSuccess) return PFAC_E_NOMEM;
+  ws->extra = static_cast<uint8_t*>(m);
+  ws->extra_cap = cap;
+  return PFAC_OK;
+}
+
+Workspace* workspace_for(int dev, hipStream_t stream, uint64_t tiles, uint64_t walks,
+                         uint64_t extra, int* rc) {
+  Workspace* ws = get_workspace(dev, stream);
+  if (!ws) {
+    *rc = PFAC_E_NOMEM;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lk(g_mu);
+  *rc = ensure_scratch(ws, tiles, false, walks, stream);
+  if (!*rc) *rc = ensure_extra(ws, extra, stream);
+  return *rc ? nullptr : ws;
+}
+
+const Scratch& workspace_scratch(const Workspace* ws) { return ws->sc; }
+uint8_t* workspace_extra(const Workspace* ws) { return ws->extra; }
+
 static void free_workspace(Workspace* ws) {
+  if (ws->extra) (void)hipFree(ws->extra);
   if (ws->mem) (void)hipFree(ws->mem);
   if (ws->batch) (void)hipFree(ws->batch);
   if (ws->stage) (void)hipHostFree(ws->stage);
@@ -883,6 +918,8 @@ int pfac_build_table(const char* const* patterns, const uint32_t* lengths, uint3
     o_hash[b] = off; off = al256(off + h.hash[b].size() * 4);
   }
   const uint64_t o_pfx = off; off = al256(off + h.pfx.size() * 4);
+  const uint64_t o_dups = off; off = al256(off + h.dup_state.size() * 4);
+  const uint64_t o_dupi = off; off = al256(off + h.dup_id.size() * 4);
   if (hipMalloc(&t->dmem, off) != hipSuccess) {
     delete t;
     return PFAC_E_NOMEM;
@@ -895,13 +932,18 @@ int pfac_build_table(const char* const* patterns, const uint32_t* lengths, uint3
   bool ok = put(o_next, h.next.data(), h.next.size() * 4) &&
             put(o_out, h.out.data(), h.out.size() * sizeof(OutEntry)) &&
             put(o_chain, h.chain.data(), h.chain.size() * 4) &&
-            put(o_pfx, h.pfx.data(), h.pfx.size() * 4);
+            put(o_pfx, h.pfx.data(), h.pfx.size() * 4) &&
+            put(o_dups, h.dup_state.data(), h.dup_state.size() * 4) &&
+            put(o_dupi, h.dup_id.data(), h.dup_id.size() * 4);
   DevTable& v = t->dev;
   memset(&v, 0, sizeof(v));
   v.next = reinterpret_cast<const uint32_t*>(base + o_next);
   v.out = reinterpret_cast<const OutEntry*>(base + o_out);
   v.chain = reinterpret_cast<const uint32_t*>(base + o_chain);
   v.pfx = h.pfx.empty() ? nullptr : reinterpret_cast<const uint32_t*>(base + o_pfx);
+  v.dup_state = reinterpret_cast<const uint32_t*>(base + o_dups);
+  v.dup_id = reinterpret_cast<const int32_t*>(base + o_dupi);
+  v.num_dups = (uint32_t)h.dup_state.size();
   v.num_states = (uint32_t)h.num_states;
   v.max_len = h.max_len;
   for (uint32_t D = kMinJump; D <= kMaxJump; ++D) {
@@ -1002,13 +1044,14 @@ int prepare_single(const pfac_table* t, uint64_t n, int enc, const pfac_plan* pl
 
 int enqueue_single(const pfac_table* t, SinglePrep& P, const Scratch& sc, const void* d_text,
                           int32_t* d_match, pfac_hit* d_hits, uint64_t hit_cap,
-                          unsigned long long* counters, int dev, hipStream_t stream) {
+                          unsigned long long* counters, int dev, hipStream_t stream,
+                          bool keep_slots) {
   ScanParams& sp = P.sp;
   sp.text = static_cast<const uint8_t*>(d_text);
   sp.match = d_match;
   sp.tile_hits = sc.tile_hits;
   sp.tile_occ = sc.tile_occ;
-  sp.slots = d_hits ? sc.slots : nullptr;
+  sp.slots = (d_hits || keep_slots) ? sc.slots : nullptr;
   sp.wq = sc.walk;
   int rc = launch_scan(sp, P.pl, true, P.pl.tile, dev, stream);
   if (rc) return rc;

@@ -51,10 +51,22 @@ struct SinglePrep {
 int prepare_single(const pfac_table* t, uint64_t n, int enc, const pfac_plan* plan, int dev,
                    SinglePrep* P);
 
-// Enqueue a prepared one-text call on the scratch `sc` (kernel launches only).
+// Enqueue a prepared one-text call on the scratch `sc` (kernel launches
+// only).  `keep_slots`: the scan parks each tile's hits in its slots even
+// when no hit list is asked for (the all-occurrence pass reads them).
 int enqueue_single(const pfac_table* t, SinglePrep& P, const Scratch& sc, const void* d_text,
                    int32_t* d_match, pfac_hit* d_hits, uint64_t hit_cap,
-                   unsigned long long* counters, int dev, hipStream_t stream);
+                   unsigned long long* counters, int dev, hipStream_t stream,
+                   bool keep_slots = false);
+
+// Workspace of (device, stream) holding scratch for `tiles` tiles and
+// `walks` deferred walks, plus `extra` bytes after it; nullptr on failure
+// (*rc says why).
+struct Workspace;
+Workspace* workspace_for(int dev, hipStream_t stream, uint64_t tiles, uint64_t walks,
+                         uint64_t extra, int* rc);
+const Scratch& workspace_scratch(const Workspace* ws);
+uint8_t* workspace_extra(const Workspace* ws);
 
 // Zero n 64-bit words at p with a fill kernel on `stream`.
 int launch_zero(unsigned long long* p, uint32_t n, hipStream_t stream);

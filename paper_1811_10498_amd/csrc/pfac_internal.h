@@ -96,6 +96,10 @@ struct HostTable {
   std::vector<uint32_t> pfx;                // 4^K2-bit bitmap
   uint64_t pfx_set = 0;                     // distinct K2-base pattern prefixes
   uint64_t bitmap_set[kMaxJump + 1] = {};   // set bits of each depth-D filter bitmap
+  // every pattern ID of a final state but its smallest (the output entry
+  // holds that one), as (state, id) pairs sorted by state, then id
+  std::vector<uint32_t> dup_state;
+  std::vector<int32_t> dup_id;
 };
 
 // Host build: validate, insert in input order, renumber breadth-first, pack.
@@ -113,6 +117,9 @@ struct DevTable {
   const uint32_t* hash[kHashMaxBits + 1]; // second-filter bitmaps
   const uint32_t* chain;                  // [2S] runs of single-child steps
   const uint32_t* pfx;                    // prefix-filter bitmap (or null)
+  const uint32_t* dup_state;              // further IDs of final states (HostTable)
+  const int32_t* dup_id;
+  uint32_t num_dups;
   uint32_t num_states;
   uint32_t max_len;
 };

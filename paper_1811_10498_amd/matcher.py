@@ -201,6 +201,54 @@ def match(table: Table, text: torch.Tensor, n: Optional[int] = None, enc: str = 
 
 
 @dataclass
+class AllResult:
+    occ: Optional[torch.Tensor]          # int32[cap, 2] (pos, pid) or None
+    counters: torch.Tensor               # int64[2]: positions with a match, total occurrences
+
+    def total(self) -> int:
+        return int(self.counters[1].item())
+
+    def occurrences(self) -> np.ndarray:
+        """(k, 2) array of (position, pattern id), k = min(total, cap): ascending
+        position, then pattern length, then ID."""
+        k = min(self.total(), 0 if self.occ is None else self.occ.shape[0])
+        o = self.occ[:k].cpu().numpy().astype(np.int64)
+        o[:, 0] &= 0xFFFFFFFF
+        return o
+
+
+def match_all(table: Table, text: torch.Tensor, n: Optional[int] = None, enc: str = "ascii",
+              cap: Optional[int] = None, plan=None, stream=None) -> AllResult:
+    """Every (position, pattern ID) occurrence in one device text, the
+    sub-patterns PFAC's longest-only report skips included.  With ``cap``
+    None the call is made twice when needed: once to count, again with room
+    for every occurrence."""
+    if text.device.type != "cuda" or text.dtype != torch.uint8 or not text.is_contiguous():
+        raise TypeError("text must be a contiguous uint8 CUDA tensor")
+    if n is None:
+        n = n_bases(text, enc)
+    check_match_args(int(n), int(text.numel()), enc)
+    dev = text.device
+    c = torch.empty(2, dtype=torch.int64, device=dev)
+    p = _plan_struct(plan)
+    want = int(n) // 64 + 1024 if cap is None else int(cap)
+    for _ in range(2):
+        occ = torch.empty((max(1, want), 2), dtype=torch.int32, device=dev)
+        rc = table._lib.pfac_match_all(table.handle, text.data_ptr(), int(n), ENCODINGS[enc],
+                                       occ.data_ptr(), want, c.data_ptr(),
+                                       ctypes.byref(p) if p is not None else None,
+                                       _stream_handle(stream))
+        L.check(rc, "pfac_match_all")
+        if cap is not None:
+            break
+        total = int(c[1].item())
+        if total <= want:
+            break
+        want = total
+    return AllResult(occ, c)
+
+
+@dataclass
 class BatchResult:
     match: Optional[torch.Tensor]        # int32, per-text arrays at match offsets
     hits: Optional[torch.Tensor]         # int32[hit_cap, 3] (text, pos, pid)

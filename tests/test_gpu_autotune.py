@@ -13,7 +13,8 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
 import paper_1811_10498_amd as pf  # noqa: E402
-from paper_1811_10498_amd.autotune import Autotuner, candidate_plans  # noqa: E402
+from paper_1811_10498_amd.autotune import Autotuner, candidate_plans, focused_plans  # noqa: E402
+from _gpu_common import check_batch, joined_oracle  # noqa: E402
 
 DEV = torch.device("cuda:0")
 
@@ -22,7 +23,8 @@ def test_tuned_plan_is_a_candidate_and_gives_the_oracle_result(tmp_path):
     w = W.plain_workload(1, n=3_000_001, num_patterns=2000)
     tab = pf.Table(w.patterns)
     text = torch.from_numpy(w.text).to(DEV)
-    cands = candidate_plans(blocks=(512, 1024), depths=(8, 9))
+    cands = candidate_plans(blocks=(512, 1024), depths=(8, 9),
+                            hashes=(0, pf.PFAC_HASH_NONE), prefixes=(0,), tiles=(2048, 1024))
     tuner = Autotuner(cache_path=str(tmp_path / "tune.json"), reps=2, sample_bases=1 << 20)
     res = tuner.tune(tab, text, candidates=cands)
     print("tuned", res.plan, "%.3f ms" % res.ms, "tried", len(res.tried), flush=True)
@@ -35,3 +37,23 @@ def test_tuned_plan_is_a_candidate_and_gives_the_oracle_result(tmp_path):
         assert r.total() == total_ref
     again = Autotuner(cache_path=str(tmp_path / "tune.json"))
     assert again.tune(tab, text, candidates=cands).plan == res.plan   # from the file cache
+
+
+def test_batch_tuning_keeps_a_plan_that_gives_the_oracle_result(tmp_path):
+    wb = W.batch_workload(num_texts=400, num_patterns=20000, median=4000.0, hi=200_000, seed=61)
+    tab = pf.Table(wb.patterns)
+    base = torch.from_numpy(wb.buffer).to(DEV)
+    tuner = Autotuner(cache_path=str(tmp_path / "tune.json"), reps=2)
+    cands = focused_plans(tab, batch=True)
+    res = tuner.tune_batch([tab], base, wb.offsets, wb.lengths, candidates=cands)
+    print("batch tuned", res.plan, "%.3f ms" % res.ms, "tried", len(res.tried), flush=True)
+    assert res.plan in cands and len(res.tried) >= 8
+    texts = [wb.text(t) for t in range(wb.lengths.size)]
+    refs = joined_oracle(wb.patterns, texts)
+    for plan, _ in [(res.plan, 0)] + res.tried[:4]:
+        r = pf.match_batch([tab], base, wb.offsets, wb.lengths, plan=plan,
+                           hit_cap=wb.total_bases // 8)
+        torch.cuda.synchronize()
+        check_batch(r, refs, wb.lengths)
+    again = Autotuner(cache_path=str(tmp_path / "tune.json"))
+    assert again.tune_batch([tab], base, wb.offsets, wb.lengths).plan == res.plan
