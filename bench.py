@@ -582,10 +582,15 @@ def part_floor(pf, torch, args):
 # memory, then the table through the texture cache, each with the table as
 # two arrays or one merged array (Sec. VI, Tables II and III; Sec. VII).
 # --paper-ladder runs that structure with paper-shaped synthetic inputs over
-# the placements this library has (merged table throughout; no texture path
-# on this GPU), every plan checked bit for bit against the first:
-#   global      every position walks from the root, text and table in global
-#               memory (the paper's one-thread-per-character kernel);
+# the placements this library has (no texture path on this GPU: loads of any
+# array go through the same caches), every plan checked bit for bit against
+# the first:
+#   global-2arr every position walks from the root, text and table in global
+#               memory (the paper's one-thread-per-character kernel), the table
+#               as the paper's two arrays (next state, matched pattern ID);
+#   global-merged  the same with the two merged into one array of cells;
+#   global      the same with this library's edge words (child + final bit,
+#               pattern IDs per state);
 #   lds-d6      text tile and a depth-6 window bitmap in LDS, deep walks in
 #               the global table;
 #   lds-d9      the same with a depth-9 bitmap;
@@ -596,11 +601,14 @@ def part_floor(pf, torch, args):
 #   default     the library's plan (the same filters, walks deferred to the
 #               end of each wave).
 
-LADDER_NAMES = ("global", "lds-d6", "lds-d9", "lds-levels", "d9-hash", "default")
+LADDER_NAMES = ("global-2arr", "global-merged", "global", "lds-d6", "lds-d9", "lds-levels",
+                "d9-hash", "default")
 
 
 def ladder_plans(pf):
     return (
+        ("global-2arr", dict(variant=pf.PFAC_VARIANT_GLOBAL_TWO_ARRAYS)),
+        ("global-merged", dict(variant=pf.PFAC_VARIANT_GLOBAL_MERGED)),
         ("global", dict(variant=pf.PFAC_VARIANT_GLOBAL)),
         ("lds-d6", dict(depth=6, levels=pf.PFAC_LEVELS_NONE, hash_bits=pf.PFAC_HASH_NONE,
                         walks=pf.PFAC_WALKS_INLINE)),

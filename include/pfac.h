@@ -93,9 +93,9 @@ typedef struct {
                            whose walk continues past depth D (or passes a final state
                            within D bases) go on to the global-memory trie */
   uint32_t grid;        /* persistent workgroups (0 = fill the device; at most 2048) */
-  uint32_t variant;     /* PFAC_VARIANT_TILED (LDS text tile + filter bitmap) or
-                           PFAC_VARIANT_GLOBAL (every walk from the root, text and
-                           table read straight from global memory) */
+  uint32_t variant;     /* PFAC_VARIANT_TILED (LDS text tile + filter bitmap) or one
+                           of the global-memory variants below (every walk from the
+                           root, text and table read straight from global memory) */
   uint32_t levels;      /* when every pattern is longer than D: trie levels from
                            depth D down kept in LDS, found by rank from the filter
                            bit (0 = as many as fit, possibly none); the walk goes on
@@ -135,7 +135,21 @@ typedef struct {
 enum { PFAC_WALKS_INLINE = 1, PFAC_WALKS_DEFERRED = 2 };
 #define PFAC_PREFIX_NONE 0xFFFFFFFFu
 
-enum { PFAC_VARIANT_TILED = 0, PFAC_VARIANT_GLOBAL = 1 };
+/* Variants.  TILED: text tile in LDS, filters, deep walks (the library's).
+ * GLOBAL: the paper's kernel (Sec. V.B): every position walks from the root,
+ * text and table read from global memory; the table as edge words with a
+ * final bit and per-state pattern IDs.  The two other global-memory variants
+ * use the paper's own table layouts (Sec. VII): GLOBAL_TWO_ARRAYS reads the
+ * next state and the matched pattern ID of each cell from two S x 4 arrays,
+ * GLOBAL_MERGED from one array of {next state, pattern ID} cells; their
+ * arrays are built on the device from the table the first time a call asks
+ * for them (one-text calls only). */
+enum {
+  PFAC_VARIANT_TILED = 0,
+  PFAC_VARIANT_GLOBAL = 1,
+  PFAC_VARIANT_GLOBAL_TWO_ARRAYS = 2,
+  PFAC_VARIANT_GLOBAL_MERGED = 3
+};
 #define PFAC_LEVELS_NONE 0xFFFFFFFFu
 #define PFAC_HASH_NONE 0xFFFFFFFFu
 

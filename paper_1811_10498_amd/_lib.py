@@ -12,6 +12,8 @@ PFAC_TEXT_ASCII = 0
 PFAC_TEXT_2BIT = 1
 PFAC_VARIANT_TILED = 0
 PFAC_VARIANT_GLOBAL = 1
+PFAC_VARIANT_GLOBAL_TWO_ARRAYS = 2
+PFAC_VARIANT_GLOBAL_MERGED = 3
 PFAC_LEVELS_NONE = 0xFFFFFFFF
 PFAC_HASH_NONE = 0xFFFFFFFF
 PFAC_WALKS_INLINE = 1

@@ -318,6 +318,22 @@ __global__ void pfac_zero_kernel(unsigned long long* c, uint32_t n) {
   for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) c[i] = 0;
 }
 
+// The paper's layouts of the transition table from the edge words: per
+// cell the child state and the smallest ID of the patterns ending at it.
+__global__ __launch_bounds__(256) void pfac_cells_kernel(const uint32_t* next, const OutEntry* out,
+                                                         uint64_t cells, uint32_t* next2,
+                                                         int32_t* cell_pid, u32x2* merged) {
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < cells;
+       i += (uint64_t)gridDim.x * 256) {
+    const uint32_t e = next[i];
+    const uint32_t child = e & kStateMask;
+    const int32_t id = (e & kFinalBit) ? out[child].pid : 0;
+    next2[i] = child;
+    cell_pid[i] = id;
+    merged[i] = u32x2{child, (uint32_t)id};
+  }
+}
+
 // Batch work items: one wave per text writes the items of its tiles,
 // {text index, tile index within the text}, from item_start[text] on.
 __global__ __launch_bounds__(256) void pfac_items_kernel(const DevSeg* segs,
@@ -335,6 +351,13 @@ __global__ __launch_bounds__(256) void pfac_items_kernel(const DevSeg* segs,
 
 static std::mutex g_mu;
 std::mutex& host_mutex() { return g_mu; }
+
+// The variants that walk every position from the root in global memory.
+static bool global_variant(uint32_t v) {
+  return v == PFAC_VARIANT_GLOBAL || v == PFAC_VARIANT_GLOBAL_TWO_ARRAYS ||
+         v == PFAC_VARIANT_GLOBAL_MERGED;
+}
+
 
 struct DeviceInfo {
   int cus = 0;
@@ -623,7 +646,9 @@ static int resolve_plan(const pfac_plan* in, const HostTable& h, int dev, bool s
   const DeviceInfo di = device_info(dev);
   if (!di.ok) return PFAC_E_NODEV;
   pfac_plan p = in ? *in : pfac_plan{0, 0, 0, 0, 0, 0, 0, 0, 0};
-  if (p.variant != PFAC_VARIANT_TILED && p.variant != PFAC_VARIANT_GLOBAL) return PFAC_E_ARG;
+  if (p.variant != PFAC_VARIANT_TILED && !global_variant(p.variant)) return PFAC_E_ARG;
+  if (!single && p.variant != PFAC_VARIANT_TILED && p.variant != PFAC_VARIANT_GLOBAL)
+    return PFAC_E_ARG;
   if (p.tile != 0 && p.tile != 1024 && p.tile != 2048 && !(p.tile == 256 && !single))
     return PFAC_E_ARG;
   if (p.prefix != 0 && p.prefix != 1 && p.prefix != PFAC_PREFIX_NONE) return PFAC_E_ARG;
@@ -655,7 +680,7 @@ static int resolve_plan(const pfac_plan* in, const HostTable& h, int dev, bool s
   if (p.block != 256 && p.block != 512 && p.block != 768 && p.block != 1024) return PFAC_E_ARG;
   if (p.walks != 0 && p.walks != PFAC_WALKS_INLINE && p.walks != PFAC_WALKS_DEFERRED)
     return PFAC_E_ARG;
-  if (p.variant == PFAC_VARIANT_GLOBAL) {
+  if (global_variant(p.variant)) {
     if (p.tile != 0 && p.tile != (single ? kTileSingle : kTileBatch)) return PFAC_E_ARG;
     p.depth = 0;
     p.levels = PFAC_LEVELS_NONE;
@@ -754,7 +779,7 @@ static uint64_t grid_for(ScanFn fn, const pfac_plan& plan, uint32_t lds, int dev
 // Kernel, dynamic LDS and grid of a scan launch of `tile`-position tiles.
 static int scan_shape(const ScanParams& sp, const pfac_plan& plan, bool single, uint32_t tile,
                       int dev, ScanFn* fn, uint32_t* lds, uint64_t* grid) {
-  const bool global = plan.variant == PFAC_VARIANT_GLOBAL;
+  const bool global = global_variant(plan.variant);
   *fn = pick_scan(plan.block, global, sp.D, single, sp.defer != 0, tile);
   if (!*fn) return PFAC_E_ARG;
   *lds = global ? 4u * ((plan.block / 64) * kGlobalWaveWords + kCtlWords)
@@ -796,10 +821,41 @@ static int launch_tail(const Scratch& sc, uint64_t tiles, unsigned long long* co
   return hipGetLastError() == hipSuccess ? PFAC_OK : PFAC_E_HIP;
 }
 
+// The two-array and merged-cell tables of `t`, built once (synchronously).
+static int ensure_cells(const pfac_table* t) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (t->cells_mem) return PFAC_OK;
+  const uint64_t cells = t->host.num_states * 4;
+  const uint64_t o_cp = al256(cells * 4), o_m = o_cp + al256(cells * 4);
+  void* m = nullptr;
+  if (hipMalloc(&m, o_m + cells * 8) != hipSuccess) return PFAC_E_NOMEM;
+  uint8_t* b = static_cast<uint8_t*>(m);
+  const uint64_t grid = std::min<uint64_t>((cells + 255) / 256, 65536);
+  hipLaunchKernelGGL(pfac_cells_kernel, dim3((uint32_t)grid), dim3(256), 0, nullptr, t->dev.next,
+                     t->dev.out, cells, reinterpret_cast<uint32_t*>(b),
+                     reinterpret_cast<int32_t*>(b + o_cp), reinterpret_cast<u32x2*>(b + o_m));
+  if (hipGetLastError() != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+    (void)hipFree(m);
+    return PFAC_E_HIP;
+  }
+  t->next2 = reinterpret_cast<const uint32_t*>(b);
+  t->cell_pid = reinterpret_cast<const int32_t*>(b + o_cp);
+  t->cells = b + o_m;
+  t->cells_mem = m;
+  return PFAC_OK;
+}
+
 static void fill_table(ScanParams& sp, const pfac_table* t, const pfac_plan& pl) {
   sp.next = t->dev.next;
   sp.out = t->dev.out;
   sp.chain = t->dev.chain;
+  if (pl.variant == PFAC_VARIANT_GLOBAL_TWO_ARRAYS || pl.variant == PFAC_VARIANT_GLOBAL_MERGED) {
+    // the kernel's depth parameter names the layout for global variants
+    sp.D = pl.variant == PFAC_VARIANT_GLOBAL_TWO_ARRAYS ? 1u : 2u;
+    sp.next2 = t->next2;
+    sp.cell_pid = t->cell_pid;
+    sp.cells = static_cast<const u32x2*>(t->cells);
+  }
   if (pl.variant == PFAC_VARIANT_TILED) {
     const HostTable& h = t->host;
     const uint32_t D = pl.depth;
@@ -993,6 +1049,7 @@ void pfac_free_table(pfac_table* t) {
   (void)hipSetDevice(t->device);
   (void)hipDeviceSynchronize();
   (void)hipFree(t->dmem);
+  if (t->cells_mem) (void)hipFree(t->cells_mem);
   (void)hipSetDevice(cur);
   delete t;
 }
@@ -1012,6 +1069,10 @@ int prepare_single(const pfac_table* t, uint64_t n, int enc, const pfac_plan* pl
   int rc = resolve_plan(plan, t->host, dev, true, &P->pl);
   if (rc) return rc;
   const pfac_plan& pl = P->pl;
+  if (pl.variant == PFAC_VARIANT_GLOBAL_TWO_ARRAYS || pl.variant == PFAC_VARIANT_GLOBAL_MERGED) {
+    rc = ensure_cells(t);
+    if (rc) return rc;
+  }
   const uint32_t tile = pl.tile;
   P->tiles = (n + tile - 1) / tile;
   P->walks = 0;
@@ -1141,7 +1202,7 @@ struct BatchLayout {
 };
 
 static uint32_t text_tile(const pfac_plan& pl, uint64_t n) {
-  if (pl.variant == PFAC_VARIANT_GLOBAL) return kTileBatch;
+  if (global_variant(pl.variant)) return kTileBatch;
   if (pl.tile) return pl.tile;
   return n <= kShortText ? kTileShort : kTileBatch;
 }

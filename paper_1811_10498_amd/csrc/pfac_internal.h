@@ -132,4 +132,9 @@ struct pfac_table {
   void* dmem = nullptr;             // one device allocation for every array
   uint64_t dbytes = 0;
   pfac::DevTable dev{};             // device pointers into dmem
+  // the paper's two-array and merged-cell layouts, built on first use
+  mutable void* cells_mem = nullptr;
+  mutable const uint32_t* next2 = nullptr;
+  mutable const int32_t* cell_pid = nullptr;
+  mutable const void* cells = nullptr;
 };

@@ -118,6 +118,11 @@ struct ScanParams {
   uint32_t hash_shift;            // 32 - bits
   uint32_t hash_kmask;            // key bits of the K-base window (top 2K bits)
   uint32_t hash_imask;            // invalid bits of the K-base window ((1 << K) - 1)
+  // the paper's layouts of the transition table (global-memory variants):
+  // next state and matched pattern ID per cell as two arrays, or merged
+  const uint32_t* next2;          // [S*4] child state, 0 = none
+  const int32_t* cell_pid;        // [S*4] ID of the pattern ending at the child, 0 = none
+  const u32x2* cells;             // [S*4] {child state, pattern ID}
   const uint32_t* pfx;            // prefix filter: 4^K2-bit bitmap in global memory
   uint32_t pfx_on;
   uint32_t pfx_shift;             // 32 - 2*K2 (the K2-base key is the top 2*K2 bits)
@@ -270,6 +275,39 @@ __device__ __forceinline__ void walk(uint32_t s, uint64_t q, const uint32_t* __r
       const OutEntry o = out[s];
       best = o.pid;
       occ += o.mult;
+    }
+    ++q;
+  }
+}
+
+// The walk from the root over the text in global memory with the paper's
+// transition table layouts (Sec. V.B, VII): LAYOUT 1 reads the next state and
+// the matched pattern ID of a cell from two arrays, LAYOUT 2 from one array
+// of merged cells; a cell with an ID also reads the state's occurrence count.
+template <int LAYOUT>
+__device__ __forceinline__ void walk_cells(uint64_t q, const ScanParams& p, const uint8_t* gtext,
+                                           uint64_t gn, uint32_t genc, int32_t& best,
+                                           unsigned long long& occ) {
+  uint32_t s = 0;
+  for (;;) {
+    const int b = global_base(gtext, gn, genc, q);
+    if (b < 0) break;
+    const uint64_t cell = (uint64_t)s * 4 + (uint32_t)b;
+    uint32_t nx;
+    int32_t id;
+    if (LAYOUT == 1) {
+      nx = p.next2[cell];
+      id = p.cell_pid[cell];
+    } else {
+      const u32x2 c = p.cells[cell];
+      nx = c.x;
+      id = (int32_t)c.y;
+    }
+    if (nx == 0) break;
+    s = nx;
+    if (id) {
+      best = id;
+      occ += p.out[s].mult;
     }
     ++q;
   }
@@ -823,7 +861,10 @@ __device__ __forceinline__ bool pfx_locate(uint32_t e, const uint32_t* __restric
   return true;
 }
 
-// Main scan.  Each wave takes whole tiles of TILE positions.  A lane owns
+// Main scan.  GLOBAL: the paper's kernel, every position walks from the root
+// with text and table in global memory, DT = the table layout (0 edge words
+// with a final bit, 1 two arrays, 2 merged cells); otherwise DT = the filter
+// depth D.  Each wave takes whole tiles of TILE positions.  A lane owns
 // 4*NG positions of a tile, NG = TILE/256 groups of four consecutive ones:
 // q = g*256 + 4*lane + r.  Positions whose walk goes on past the filters are
 // queued and walked by all lanes together (or kept for the end of the wave);
@@ -1121,7 +1162,11 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
         const uint32_t qt = e & 0x7FFFu;                 // index within the tile
         int32_t best = 0;
         if (GLOBAL) {
-          walk<true>(0u, t0 + qt, nullptr, nullptr, p.next, p.out, text, n, enc, best, occ);
+          // the global-memory variants: DT names the table layout
+          if (DT == 1 || DT == 2)
+            walk_cells<DT>(t0 + qt, p, text, n, enc, best, occ);
+          else
+            walk<true>(0u, t0 + qt, nullptr, nullptr, p.next, p.out, text, n, enc, best, occ);
         } else {
           best = deep_walk(e, D, p.lds_trie, p.levels, lds, bmpre, lvl, pk, iv, p.next, p.out,
                            p.jump, p.jres, p.chain, occ);

@@ -37,16 +37,25 @@ static ScanFn by_walks(uint32_t D, bool defer) {
 
 ScanFn PFAC_PICK(bool global, uint32_t D, bool defer, uint32_t tile) {
 #if PFAC_SINGLE
-  if (global) return tile == kTileSingle ? pfac_scan_kernel<PFAC_BLOCK, true, 0, true, false, kTileSingle>
-                                         : nullptr;
+  // global-memory variants: D names the transition table layout
+  if (global) {
+    if (tile != kTileSingle) return nullptr;
+    switch (D) {
+      case 0: return pfac_scan_kernel<PFAC_BLOCK, true, 0, true, false, kTileSingle>;
+      case 1: return pfac_scan_kernel<PFAC_BLOCK, true, 1, true, false, kTileSingle>;
+      case 2: return pfac_scan_kernel<PFAC_BLOCK, true, 2, true, false, kTileSingle>;
+      default: return nullptr;
+    }
+  }
   switch (tile) {
     case 2048: return by_walks<2048>(D, defer);
     case 1024: return by_walks<1024>(D, defer);
     default: return nullptr;
   }
 #else
-  if (global) return tile == kTileBatch ? pfac_scan_kernel<PFAC_BLOCK, true, 0, false, false, kTileBatch>
-                                        : nullptr;
+  if (global) return (tile == kTileBatch && D == 0)
+                        ? pfac_scan_kernel<PFAC_BLOCK, true, 0, false, false, kTileBatch>
+                        : nullptr;
   switch (tile) {
     case 2048: return by_walks<2048>(D, defer);
     case 1024: return by_walks<1024>(D, defer);

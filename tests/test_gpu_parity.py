@@ -525,6 +525,8 @@ def test_deferred_walks_with_optional_outputs():
 
 
 READS_PLANS = [
+    dict(variant=pf.PFAC_VARIANT_GLOBAL_TWO_ARRAYS),
+    dict(variant=pf.PFAC_VARIANT_GLOBAL_MERGED),
     dict(variant=pf.PFAC_VARIANT_GLOBAL),
     dict(depth=6, levels=pf.PFAC_LEVELS_NONE, hash_bits=pf.PFAC_HASH_NONE,
          walks=pf.PFAC_WALKS_INLINE),
@@ -546,6 +548,24 @@ def test_paper_shaped_reads_every_ladder_plan(plan):
                                                          READS_PLANS[plan]), flush=True)
     res = _gpu(w.patterns, w.text, plan=READS_PLANS[plan])
     _check(res, w.patterns, w.text)
+
+
+def test_paper_layouts_on_nested_duplicates_and_non_bases():
+    """The two-array and merged-cell layouts (per-cell smallest ID, state
+    occurrence counts) on duplicates, nested prefixes and non-base bytes."""
+    g = W.rng(72)
+    text = W.uniform_ascii(200_003, g)
+    pats = (W.cut_patterns(text, 500, 3, 30, g) + [b"A", b"AC", b"ACG", b"ACG", b"CG", b"CG"]
+            + W.random_patterns(300, 5, 12, g))
+    text[777:790] = ord("N")
+    text[5000] = ord("\n")
+    for v in (pf.PFAC_VARIANT_GLOBAL_TWO_ARRAYS, pf.PFAC_VARIANT_GLOBAL_MERGED):
+        res = _gpu(pats, text, plan=dict(variant=v))
+        _check(res, pats, text)
+    tab = pf.Table(pats)
+    base = torch.zeros(64, dtype=torch.uint8, device=DEV)
+    with pytest.raises(pf.PfacError):       # one-text calls only
+        pf.match_batch([tab], base, [0], [10], plan=dict(variant=pf.PFAC_VARIANT_GLOBAL_MERGED))
 
 
 def test_default_plan_defers_walks_only_within_the_copied_window():
