@@ -55,6 +55,10 @@ def _declare(lib):
     lib.oracle_scan_mt.restype = ctypes.c_int
     lib.oracle_occurrences.argtypes = [P, P, u32, P, u64, P, P, P, P, u64, P, P, P]
     lib.oracle_occurrences.restype = ctypes.c_int
+    lib.oracle_scan_bytes_mt.argtypes = [P, P, u32, P, u64, P, P, P, ctypes.c_int, P]
+    lib.oracle_scan_bytes_mt.restype = ctypes.c_int
+    lib.oracle_occurrences_bytes.argtypes = [P, P, u32, P, u64, P, P, P, P, u64, P, P, P]
+    lib.oracle_occurrences_bytes.restype = ctypes.c_int
     lib.oracle_goto.argtypes = [P, P, u32, P, P, i64]
     lib.oracle_goto.restype = i64
     return lib
@@ -96,6 +100,32 @@ def _as_text(text) -> np.ndarray:
     return t
 
 
+def scan_bytes(patterns, text, threads: int = 1, lib=None, counts: bool = False):
+    """The oracle over the byte alphabet (the general-purpose PFAC setting):
+    every byte value is a symbol, patterns are any non-empty byte strings.
+    Returns (match int32[n], total) and with ``counts`` the per-position
+    occurrence counts, as ``scan``."""
+    lib = lib or _load()
+    arr, lens, keep, num = _pattern_args(patterns)
+    t = _as_text(text)
+    n = int(t.size)
+    match = np.zeros(n, dtype=np.int32)
+    count = np.zeros(n, dtype=np.uint32) if counts else None
+    total = ctypes.c_uint64(0)
+    bad = ctypes.c_int64(-1)
+    rc = lib.oracle_scan_bytes_mt(ctypes.cast(arr, ctypes.c_void_p), lens.ctypes.data, num,
+                                  t.ctypes.data if n else None, n, match.ctypes.data if n else None,
+                                  ctypes.addressof(total), ctypes.addressof(bad),
+                                  int(max(1, threads)),
+                                  count.ctypes.data if (counts and n) else None)
+    del keep
+    if rc != 0:
+        raise OracleError(rc, bad.value)
+    if counts:
+        return match, int(total.value), count
+    return match, int(total.value)
+
+
 def scan(patterns, text, threads: int = 1, lib=None, counts: bool = False):
     """Run the oracle.  Returns (match int32[n], total occurrences), and with
     ``counts`` also count uint32[n] = occurrences starting at each position.
@@ -133,12 +163,14 @@ def scan(patterns, text, threads: int = 1, lib=None, counts: bool = False):
     return match, int(total.value)
 
 
-def occurrences(patterns, text, lib=None):
+def occurrences(patterns, text, lib=None, alphabet: str = "dna"):
     """Every (start position, pattern ID) pair with the pattern at that start,
     sub-patterns included: an int64 array (k, 2) in ascending position, then
     ascending pattern length, then ascending ID.  The scan reports them by
-    end position; the order above is a plain sort of that list."""
+    end position; the order above is a plain sort of that list.  ``alphabet``
+    "bytes": every byte value a symbol (as ``scan_bytes``)."""
     lib = lib or _load()
+    entry = lib.oracle_occurrences_bytes if alphabet == "bytes" else lib.oracle_occurrences
     arr, lens, keep, num = _pattern_args(patterns)
     t = _as_text(text)
     n = int(t.size)
@@ -150,7 +182,7 @@ def occurrences(patterns, text, lib=None):
     pos = np.zeros(1, dtype=np.uint32)
     ids = np.zeros(1, dtype=np.int32)
     for _ in range(2):              # first pass sizes the list
-        rc = lib.oracle_occurrences(ctypes.cast(arr, ctypes.c_void_p), lens.ctypes.data, num,
+        rc = entry(ctypes.cast(arr, ctypes.c_void_p), lens.ctypes.data, num,
                                     t.ctypes.data if n else None, n, match.ctypes.data, None,
                                     pos.ctypes.data, ids.ctypes.data, cap,
                                     ctypes.addressof(nocc), ctypes.addressof(total),

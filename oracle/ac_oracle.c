@@ -18,6 +18,9 @@
  *                pattern ID counted (duplicates included).
  *   Only the four upper-case bytes A, C, G and T are bases (the table has
  *   four columns, Sec. V.A); any other text byte has no transition.
+ *   The same definitions over the byte alphabet (every byte value a symbol,
+ *   patterns any non-empty byte strings) are computed by the *_bytes entry
+ *   points: the general-purpose setting of the original PFAC library.
  *   Optionally also
  *     count[i] = number of pattern IDs k with T[i..i+|p_k|) == p_k, and
  *     the list of every such pair (i, k) -- the sub-patterns too, which PFAC
@@ -70,7 +73,11 @@ static int sym(uint8_t b) {
   }
 }
 
-static int text_sym(uint8_t b) {
+/* symbol of a pattern byte under alphabet A: DNA codes, or the byte itself */
+static int pat_sym(int A, uint8_t b) { return A == 4 ? sym(b) : (int)b; }
+
+static int text_sym(int A, uint8_t b) {
+  if (A != 4) return (int)b;
 #if ORACLE_MUTANT == 4
   return sym(b) < 0 ? 0 : sym(b);
 #else
@@ -79,9 +86,10 @@ static int text_sym(uint8_t b) {
 }
 
 typedef struct {
+  int A;               /* alphabet size: 4 (DNA: A,C,G,T) or 256 (every byte a symbol) */
   int64_t nstates;     /* states allocated so far, root = 0 */
   int64_t cap;
-  int64_t *go;         /* go[4*s + a]: goto(s, a), -1 = fail */
+  int64_t *go;         /* go[A*s + a]: goto(s, a), -1 = fail */
   int64_t *fail;       /* failure function */
   int64_t *dict;       /* nearest failure-chain state with output, -1 = none */
   int64_t *out_head;   /* first keyword index (0-based) ending at s, -1 = none */
@@ -100,7 +108,7 @@ static void machine_free(machine *m) {
 static int new_state(machine *m) {
   if (m->nstates == m->cap) {
     int64_t nc = m->cap ? 2 * m->cap : 64;
-    int64_t *g = (int64_t *)realloc(m->go, (size_t)nc * 4 * sizeof(int64_t));
+    int64_t *g = (int64_t *)realloc(m->go, (size_t)nc * m->A * sizeof(int64_t));
     if (!g) return OR_E_NOMEM;
     m->go = g;
     int64_t *h = (int64_t *)realloc(m->out_head, (size_t)nc * sizeof(int64_t));
@@ -109,7 +117,7 @@ static int new_state(machine *m) {
     m->cap = nc;
   }
   int64_t s = m->nstates++;
-  for (int a = 0; a < 4; ++a) m->go[4 * s + a] = -1;
+  for (int a = 0; a < m->A; ++a) m->go[(int64_t)m->A * s + a] = -1;
   m->out_head[s] = -1;
   return OR_OK;
 }
@@ -117,9 +125,10 @@ static int new_state(machine *m) {
 /* Goto function and output function: insert each keyword in input order;
  * a new state is created for every character that has no transition yet
  * (Sec. III, Fig. 1 numbering; Sec. V.A insertion). */
-static int build_goto(machine *m, const char *const *pats, const uint32_t *lens,
+static int build_goto(machine *m, int A, const char *const *pats, const uint32_t *lens,
                       uint32_t num, int64_t *bad_index) {
   memset(m, 0, sizeof(*m));
+  m->A = A;
   m->nkw = num;
   m->out_next = (int64_t *)malloc((size_t)(num ? num : 1) * sizeof(int64_t));
   m->kw_len = (uint32_t *)malloc((size_t)(num ? num : 1) * sizeof(uint32_t));
@@ -128,17 +137,17 @@ static int build_goto(machine *m, const char *const *pats, const uint32_t *lens,
   for (uint32_t k = 0; k < num; ++k) {
     if (lens[k] == 0) { if (bad_index) *bad_index = k; return OR_E_PATTERN; }
     for (uint32_t t = 0; t < lens[k]; ++t)
-      if (sym((uint8_t)pats[k][t]) < 0) { if (bad_index) *bad_index = k; return OR_E_PATTERN; }
+      if (pat_sym(A, (uint8_t)pats[k][t]) < 0) { if (bad_index) *bad_index = k; return OR_E_PATTERN; }
   }
   for (uint32_t k = 0; k < num; ++k) {
     int64_t s = 0;
     for (uint32_t t = 0; t < lens[k]; ++t) {
-      int a = sym((uint8_t)pats[k][t]);
-      if (m->go[4 * s + a] < 0) {
+      int a = pat_sym(A, (uint8_t)pats[k][t]);
+      if (m->go[(int64_t)A * s + a] < 0) {
         if (new_state(m) != OR_OK) return OR_E_NOMEM;
-        m->go[4 * s + a] = m->nstates - 1;
+        m->go[(int64_t)A * s + a] = m->nstates - 1;
       }
-      s = m->go[4 * s + a];
+      s = m->go[(int64_t)A * s + a];
     }
     /* append keyword k to output(s), keeping keyword order */
     m->kw_len[k] = lens[k];
@@ -166,20 +175,21 @@ static int build_failure(machine *m) {
   int64_t head = 0, tail = 0;
   m->fail[0] = 0;
   m->dict[0] = -1;
-  for (int a = 0; a < 4; ++a) {
+  const int64_t A = m->A;
+  for (int a = 0; a < A; ++a) {
     int64_t u = m->go[a];
     if (u >= 0) { m->fail[u] = 0; m->dict[u] = -1; queue[tail++] = u; }
   }
   while (head < tail) {
     int64_t r = queue[head++];
-    for (int a = 0; a < 4; ++a) {
-      int64_t u = m->go[4 * r + a];
+    for (int a = 0; a < A; ++a) {
+      int64_t u = m->go[A * r + a];
       if (u < 0) continue;
       queue[tail++] = u;
       /* f(u): longest proper suffix of u's string that is a trie state */
       int64_t v = m->fail[r];
-      while (v != 0 && m->go[4 * v + a] < 0) v = m->fail[v];
-      int64_t w = m->go[4 * v + a];
+      while (v != 0 && m->go[A * v + a] < 0) v = m->fail[v];
+      int64_t w = m->go[A * v + a];
       m->fail[u] = (w >= 0 && w != u) ? w : 0;
       int64_t f = m->fail[u];
       m->dict[u] = (m->out_head[f] >= 0) ? f : m->dict[f];
@@ -241,15 +251,16 @@ static void scan_range(const machine *m, const uint8_t *text, uint64_t n,
   uint64_t end = hi + (m->max_len ? m->max_len - 1 : 0);
   if (end > n) end = n;
   int64_t s = 0;
+  const int64_t A = m->A;
   for (uint64_t j = lo; j < end; ++j) {
-    int a = text_sym(text[j]);
+    int a = text_sym(m->A, text[j]);
     if (a < 0) { s = 0; continue; }          /* no transition: restart at the root */
 #if ORACLE_MUTANT == 6
-    if (s != 0 && m->go[4 * s + a] < 0) s = 0;
+    if (s != 0 && m->go[A * s + a] < 0) s = 0;
 #else
-    while (s != 0 && m->go[4 * s + a] < 0) s = m->fail[s];
+    while (s != 0 && m->go[A * s + a] < 0) s = m->fail[s];
 #endif
-    int64_t nx = m->go[4 * s + a];
+    int64_t nx = m->go[A * s + a];
     s = nx >= 0 ? nx : 0;
     int64_t t = (m->out_head[s] >= 0) ? s : m->dict[s];
     while (t >= 0) {
@@ -264,9 +275,9 @@ static void scan_range(const machine *m, const uint8_t *text, uint64_t n,
   }
 }
 
-static int build_machine(machine *m, const char *const *pats, const uint32_t *lens,
+static int build_machine(machine *m, int A, const char *const *pats, const uint32_t *lens,
                          uint32_t num, int64_t *bad_index) {
-  int rc = build_goto(m, pats, lens, num, bad_index);
+  int rc = build_goto(m, A, pats, lens, num, bad_index);
   if (rc == OR_OK) rc = build_failure(m);
   if (rc != OR_OK) machine_free(m);
   return rc;
@@ -278,7 +289,7 @@ int oracle_scan(const char *const *pats, const uint32_t *lens, uint32_t num,
                 int64_t *bad_index) {
   if ((num && (!pats || !lens)) || (n && (!text || !match)) || !total) return OR_E_ARG;
   machine m;
-  int rc = build_machine(&m, pats, lens, num, bad_index);
+  int rc = build_machine(&m, 4, pats, lens, num, bad_index);
   if (rc != OR_OK) return rc;
   uint32_t *bestlen = (uint32_t *)calloc(n ? n : 1, sizeof(uint32_t));
   if (!bestlen) { machine_free(&m); return OR_E_NOMEM; }
@@ -297,15 +308,15 @@ int oracle_scan(const char *const *pats, const uint32_t *lens, uint32_t num,
  * occurrence in the order the scan reports them (by end position, then
  * along the dictionary links); *num_occ = the number of occurrences, which
  * may exceed cap (only the first cap are written). */
-int oracle_occurrences(const char *const *pats, const uint32_t *lens, uint32_t num,
-                       const uint8_t *text, uint64_t n, int32_t *match, uint32_t *count,
-                       uint32_t *occ_pos, int32_t *occ_id, uint64_t cap, uint64_t *num_occ,
-                       uint64_t *total, int64_t *bad_index) {
+static int occurrences_alpha(int A, const char *const *pats, const uint32_t *lens, uint32_t num,
+                             const uint8_t *text, uint64_t n, int32_t *match, uint32_t *count,
+                             uint32_t *occ_pos, int32_t *occ_id, uint64_t cap,
+                             uint64_t *num_occ, uint64_t *total, int64_t *bad_index) {
   if ((num && (!pats || !lens)) || (n && (!text || !match)) || !total || !num_occ ||
       (cap && (!occ_pos || !occ_id)))
     return OR_E_ARG;
   machine m;
-  int rc = build_machine(&m, pats, lens, num, bad_index);
+  int rc = build_machine(&m, A, pats, lens, num, bad_index);
   if (rc != OR_OK) return rc;
   uint32_t *bestlen = (uint32_t *)calloc(n ? n : 1, sizeof(uint32_t));
   if (!bestlen) { machine_free(&m); return OR_E_NOMEM; }
@@ -321,6 +332,24 @@ int oracle_occurrences(const char *const *pats, const uint32_t *lens, uint32_t n
   free(bestlen);
   machine_free(&m);
   return OR_OK;
+}
+
+int oracle_occurrences(const char *const *pats, const uint32_t *lens, uint32_t num,
+                       const uint8_t *text, uint64_t n, int32_t *match, uint32_t *count,
+                       uint32_t *occ_pos, int32_t *occ_id, uint64_t cap, uint64_t *num_occ,
+                       uint64_t *total, int64_t *bad_index) {
+  return occurrences_alpha(4, pats, lens, num, text, n, match, count, occ_pos, occ_id, cap,
+                           num_occ, total, bad_index);
+}
+
+/* The same over the byte alphabet: every byte value (0..255) is a symbol,
+ * patterns are any non-empty byte strings, no text byte stops a scan. */
+int oracle_occurrences_bytes(const char *const *pats, const uint32_t *lens, uint32_t num,
+                             const uint8_t *text, uint64_t n, int32_t *match, uint32_t *count,
+                             uint32_t *occ_pos, int32_t *occ_id, uint64_t cap,
+                             uint64_t *num_occ, uint64_t *total, int64_t *bad_index) {
+  return occurrences_alpha(256, pats, lens, num, text, n, match, count, occ_pos, occ_id, cap,
+                           num_occ, total, bad_index);
 }
 
 typedef struct {
@@ -339,13 +368,13 @@ static void *chunk_main(void *arg) {
 /* Multi-threaded oracle scan: contiguous chunks of start positions, one
  * thread each.  Identical result to oracle_scan; count (optional, n
  * entries) receives the occurrences starting at each position. */
-int oracle_scan_mt(const char *const *pats, const uint32_t *lens, uint32_t num,
-                   const uint8_t *text, uint64_t n, int32_t *match, uint64_t *total,
-                   int64_t *bad_index, int nthreads, uint32_t *count) {
+static int scan_mt_alpha(int A, const char *const *pats, const uint32_t *lens, uint32_t num,
+                         const uint8_t *text, uint64_t n, int32_t *match, uint64_t *total,
+                         int64_t *bad_index, int nthreads, uint32_t *count) {
   if ((num && (!pats || !lens)) || (n && (!text || !match)) || !total || nthreads < 1)
     return OR_E_ARG;
   machine m;
-  int rc = build_machine(&m, pats, lens, num, bad_index);
+  int rc = build_machine(&m, A, pats, lens, num, bad_index);
   if (rc != OR_OK) return rc;
   uint32_t *bestlen = (uint32_t *)calloc(n ? n : 1, sizeof(uint32_t));
   chunk_job *jobs = (chunk_job *)calloc((size_t)nthreads, sizeof(chunk_job));
@@ -373,6 +402,19 @@ int oracle_scan_mt(const char *const *pats, const uint32_t *lens, uint32_t num,
   return OR_OK;
 }
 
+int oracle_scan_mt(const char *const *pats, const uint32_t *lens, uint32_t num,
+                   const uint8_t *text, uint64_t n, int32_t *match, uint64_t *total,
+                   int64_t *bad_index, int nthreads, uint32_t *count) {
+  return scan_mt_alpha(4, pats, lens, num, text, n, match, total, bad_index, nthreads, count);
+}
+
+/* The chunked scan over the byte alphabet (see oracle_occurrences_bytes). */
+int oracle_scan_bytes_mt(const char *const *pats, const uint32_t *lens, uint32_t num,
+                         const uint8_t *text, uint64_t n, int32_t *match, uint64_t *total,
+                         int64_t *bad_index, int nthreads, uint32_t *count) {
+  return scan_mt_alpha(256, pats, lens, num, text, n, match, total, bad_index, nthreads, count);
+}
+
 /* Expose the insertion-order goto function, before any renumbering, so
  * tests can compare it with the state numbering of Sec. III, Fig. 1 and the
  * edges of Sec. V.A, Table I.  go_out gets 4*cap entries (A,C,G,T order,
@@ -382,7 +424,7 @@ int64_t oracle_goto(const char *const *pats, const uint32_t *lens, uint32_t num,
                     int64_t *go_out, int32_t *final_out, int64_t cap) {
   machine m;
   int64_t bad = -1;
-  int rc = build_goto(&m, pats, lens, num, &bad);
+  int rc = build_goto(&m, 4, pats, lens, num, &bad);
   if (rc != OR_OK) { machine_free(&m); return rc; }
   int64_t S = m.nstates;
   if (S <= cap) {

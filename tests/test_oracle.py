@@ -337,3 +337,52 @@ def test_pack2bit_layout():
     assert p.tolist() == [0b11100100, 0b1011]
     assert W.unpack2bit_ascii(p, 0, 6).tobytes() == b"ACGTTG"
     assert W.unpack2bit_ascii(p, 3, 2).tobytes() == b"TT"
+
+
+# ---------------------------------------------------------------- byte alphabet
+
+def test_byte_alphabet_worked_example():
+    ex = read_golden("bytes_ushers.txt")
+    pats = _pats(ex["patterns"])
+    m, total = oracle.scan_bytes(pats, ex["text"].encode())
+    assert m.tolist() == [int(x) for x in ex["match"].split()]
+    assert total == int(ex["total"])
+    occ = oracle.occurrences(pats, ex["text"].encode(), alphabet="bytes")
+    want = [tuple(int(x) for x in c.split(",")) for c in ex["occurrences"].split()]
+    assert [tuple(r) for r in occ.tolist()] == want
+
+
+def test_byte_alphabet_against_brute_force():
+    """Random byte patterns (any of 256 values, small alphabets for many
+    matches, nested prefixes and duplicates) over random byte texts."""
+    g = W.rng(4321)
+    for case in range(300):
+        k = int(g.integers(2, 257)) if case % 3 else 3
+        symbols = g.choice(256, size=min(k, 256), replace=False).astype(np.uint8)
+        P = int(g.integers(1, 15))
+        pats = []
+        for _ in range(P):
+            if pats and g.random() < 0.3:
+                src = pats[int(g.integers(0, len(pats)))]
+                pats.append(src[:int(g.integers(1, len(src) + 1))])
+            else:
+                pats.append(symbols[g.integers(0, symbols.size, size=int(g.integers(1, 7)))]
+                            .tobytes())
+        n = int(g.integers(0, 120))
+        text = symbols[g.integers(0, symbols.size, size=n)].tobytes()
+        m, total = oracle.scan_bytes(pats, text, threads=1 + case % 3)
+        bm, bt = brute(pats, text)
+        assert m.tolist() == bm and total == bt, (case, pats, text)
+        occ = oracle.occurrences(pats, text, alphabet="bytes")
+        assert [tuple(r) for r in occ.tolist()] == brute_pairs(pats, text), case
+
+
+def test_byte_alphabet_agrees_with_dna_oracle_on_dna():
+    """On A, C, G, T only (no other byte in text or patterns) the two
+    alphabets define the same thing."""
+    w = W.plain_workload(0, n=100_000)
+    m1, t1 = oracle.scan(w.patterns, w.text)
+    m2, t2 = oracle.scan_bytes(w.patterns, w.text, threads=4)
+    assert np.array_equal(m1, m2) and t1 == t2
+    with pytest.raises(oracle.OracleError):
+        oracle.scan_bytes([b"AC", b""], b"ACGT")          # empty pattern
