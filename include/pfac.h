@@ -180,6 +180,23 @@ typedef struct {
 int pfac_build_table(const char* const* patterns, const uint32_t* lengths, uint32_t num,
                      pfac_table** out, int64_t* bad_index);
 
+/*
+ * Build a table over the byte alphabet: every byte value 0..255 is a symbol
+ * and patterns are any non-empty byte strings (case, IUPAC codes, N, or
+ * non-DNA data) -- the general-purpose setting of the original PFAC library
+ * (Sec. I, II).  Same insertion and numbering as pfac_build_table; the
+ * transition table is hash-compressed (the hash method Sec. II names): the
+ * root's 256 edges form a dense row, every other edge is an entry of one
+ * open-addressing hash table keyed by (state, byte), load at most 1/2.
+ * Such a table works with pfac_match only (texts PFAC_TEXT_ASCII, read as
+ * raw bytes; no byte stops a walk except where no edge exists; plans may set
+ * the grid only, and block 1024); the other match calls return PFAC_E_ARG.
+ * At most 2^24 - 1 states (PFAC_E_TOO_LARGE beyond); PFAC_E_PATTERN for an
+ * empty pattern.
+ */
+int pfac_build_table_bytes(const char* const* patterns, const uint32_t* lengths, uint32_t num,
+                           pfac_table** out, int64_t* bad_index);
+
 int pfac_table_info(const pfac_table* table, pfac_table_stats* out);
 
 /* Frees host and device memory (synchronises the device first).  NULL is a no-op. */

@@ -21,7 +21,7 @@ PFAC_WALKS_DEFERRED = 2
 PFAC_PREFIX_NONE = 0xFFFFFFFF
 
 EXPORTS = (
-    "pfac_build_table", "pfac_table_info", "pfac_free_table", "pfac_match",
+    "pfac_build_table", "pfac_build_table_bytes", "pfac_table_info", "pfac_free_table", "pfac_match",
     "pfac_match_all", "pfac_match_batch", "pfac_batch_create", "pfac_batch_launch", "pfac_batch_info",
     "pfac_batch_free",
     "pfac_default_plan", "pfac_build_host", "pfac_build_host_image", "pfac_build_host_hash",
@@ -82,6 +82,9 @@ def lib():
             u32, u64, i32, i64 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int64
             L.pfac_build_table.argtypes = [P, P, u32, ctypes.POINTER(P), ctypes.POINTER(i64)]
             L.pfac_build_table.restype = ctypes.c_int
+            L.pfac_build_table_bytes.argtypes = [P, P, u32, ctypes.POINTER(P),
+                                                 ctypes.POINTER(i64)]
+            L.pfac_build_table_bytes.restype = ctypes.c_int
             L.pfac_table_info.argtypes = [P, ctypes.POINTER(PfacTableStats)]
             L.pfac_table_info.restype = ctypes.c_int
             L.pfac_free_table.argtypes = [P]

@@ -286,6 +286,104 @@ int build_host_table(const char* const* patterns, const uint32_t* lengths, uint3
   return PFAC_OK;
 }
 
+int build_host_bytes(const char* const* patterns, const uint32_t* lengths, uint32_t num,
+                     HostBytes* out, int64_t* bad_index) {
+  if (bad_index) *bad_index = -1;
+  if (!patterns || !lengths || num == 0 || !out) return PFAC_E_ARG;
+  for (uint32_t k = 0; k < num; ++k) {
+    if (lengths[k] == 0 || patterns[k] == nullptr) {
+      if (bad_index) *bad_index = k;
+      return PFAC_E_PATTERN;
+    }
+  }
+  try {
+    // 1. insertion-order trie, one new state per new byte (children kept as
+    //    sorted (byte, child) lists)
+    std::vector<std::vector<std::pair<uint8_t, uint32_t>>> kids(1);
+    std::vector<int32_t> fin_pid(1, 0);
+    std::vector<uint32_t> fin_mult(1, 0);
+    uint32_t maxl = 0, minl = UINT32_MAX;
+    for (uint32_t k = 0; k < num; ++k) {
+      uint32_t s = 0;
+      for (uint32_t t = 0; t < lengths[k]; ++t) {
+        const uint8_t a = (uint8_t)patterns[k][t];
+        auto& v = kids[s];
+        auto it = std::lower_bound(v.begin(), v.end(), std::make_pair(a, 0u),
+                                   [](const std::pair<uint8_t, uint32_t>& x,
+                                      const std::pair<uint8_t, uint32_t>& y) {
+                                     return x.first < y.first;
+                                   });
+        if (it == v.end() || it->first != a) {
+          if (kids.size() >= kBytesMaxStates) return PFAC_E_TOO_LARGE;
+          const uint32_t c = (uint32_t)kids.size();
+          it = kids[s].insert(it, std::make_pair(a, c));
+          kids.emplace_back();
+          fin_pid.push_back(0);
+          fin_mult.push_back(0);
+          s = c;
+        } else {
+          s = it->second;
+        }
+      }
+      if (fin_pid[s] == 0) fin_pid[s] = (int32_t)(k + 1);   // smallest ID wins
+      fin_mult[s] += 1;
+      maxl = std::max(maxl, lengths[k]);
+      minl = std::min(minl, lengths[k]);
+    }
+    const uint64_t S = kids.size();
+    // 2. breadth-first renumbering (children in byte order)
+    std::vector<uint32_t> order;
+    order.reserve(S);
+    std::vector<uint32_t> newid(S, 0);
+    std::vector<uint64_t> depth_start;
+    order.push_back(0);
+    depth_start.push_back(0);
+    size_t level_begin = 0;
+    while (level_begin < order.size()) {
+      const size_t level_end = order.size();
+      for (size_t i = level_begin; i < level_end; ++i)
+        for (const auto& e : kids[order[i]]) order.push_back(e.second);
+      if (order.size() > level_end) depth_start.push_back(level_end);
+      level_begin = level_end;
+    }
+    depth_start.push_back(S);
+    for (uint64_t i = 0; i < S; ++i) newid[order[i]] = (uint32_t)i;
+    // 3. outputs, root row, hash table of the other edges (load <= 1/2)
+    out->out.assign(S, OutEntry{0, 0});
+    uint64_t edges = 0;
+    for (uint64_t i = 0; i < S; ++i) {
+      out->out[i] = OutEntry{fin_pid[order[i]], fin_mult[order[i]]};
+      edges += kids[order[i]].size();
+    }
+    memset(out->root, 0, sizeof(out->root));
+    for (const auto& e : kids[0])
+      out->root[e.first] = newid[e.second] | (fin_pid[e.second] ? kFinalBit : 0u);
+    const uint64_t inner = edges - kids[0].size();
+    uint32_t bits = 8;
+    while ((1ull << bits) < 2 * inner) ++bits;
+    out->hash_bits = bits;
+    out->slots.assign(2ull << bits, kBytesEmptyKey);
+    for (uint64_t i = 1; i < S; ++i) {
+      for (const auto& e : kids[order[i]]) {
+        const uint32_t key = ((uint32_t)i << 8) | e.first;
+        uint32_t h = bytes_hash(key, bits);
+        while (out->slots[2 * h] != kBytesEmptyKey) h = (h + 1) & ((1u << bits) - 1);
+        out->slots[2 * h] = key;
+        out->slots[2 * h + 1] = newid[e.second] | (fin_pid[e.second] ? kFinalBit : 0u);
+      }
+    }
+    out->num_states = S;
+    out->num_patterns = num;
+    out->max_len = maxl;
+    out->min_len = minl;
+    out->depth_start = depth_start;
+    out->edges = edges;
+  } catch (const std::bad_alloc&) {
+    return PFAC_E_NOMEM;
+  }
+  return PFAC_OK;
+}
+
 }  // namespace pfac
 
 extern "C" int pfac_build_host(const char* const* patterns, const uint32_t* lengths, uint32_t num,

@@ -1057,6 +1057,12 @@ void pfac_free_table(pfac_table* t) {
 int pfac_default_plan(const pfac_table* t, uint64_t n, int enc, pfac_plan* out) {
   (void)n;
   if (!t || !out || (enc != PFAC_TEXT_ASCII && enc != PFAC_TEXT_2BIT)) return PFAC_E_ARG;
+  if (t->alphabet != 4) {
+    // byte tables have one kernel: 1024-thread workgroups, the grid by size
+    *out = pfac_plan{1024, 0, 0, PFAC_VARIANT_GLOBAL, PFAC_LEVELS_NONE, PFAC_HASH_NONE,
+                     PFAC_WALKS_INLINE, 2048, PFAC_PREFIX_NONE};
+    return enc == PFAC_TEXT_ASCII ? PFAC_OK : PFAC_E_ARG;
+  }
   return resolve_plan(nullptr, t->host, t->device, true, out);
 }
 
@@ -1066,6 +1072,7 @@ namespace pfac {
 
 int prepare_single(const pfac_table* t, uint64_t n, int enc, const pfac_plan* plan,
                           int dev, SinglePrep* P) {
+  if (t->alphabet != 4) return PFAC_E_ARG;      // byte tables: pfac_match only
   int rc = resolve_plan(plan, t->host, dev, true, &P->pl);
   if (rc) return rc;
   const pfac_plan& pl = P->pl;
@@ -1129,6 +1136,23 @@ int enqueue_single(const pfac_table* t, SinglePrep& P, const Scratch& sc, const 
   return launch_tail(sc, P.tiles, counters, &fp, d_hits != nullptr && hit_cap > 0, stream);
 }
 
+int launch_finish_single(const Scratch& sc, uint64_t tiles, uint32_t tile, uint64_t n,
+                         unsigned long long* counters, pfac_hit* d_hits, uint64_t hit_cap,
+                         const int32_t* match, hipStream_t stream) {
+  FinishParams fp;
+  memset(&fp, 0, sizeof(fp));
+  fp.hits = d_hits;
+  fp.hit_cap = hit_cap;
+  fp.single = 1;
+  fp.tile = tile;
+  fp.seg0 = DevSeg{0, 0, (uint32_t)n, 0, 0, 0, (uint16_t)__builtin_ctz(tile)};
+  fp.match = match;
+  return launch_tail(sc, tiles, counters, &fp, d_hits != nullptr && hit_cap > 0, stream);
+}
+
+bool device_ok(int dev) { return device_info(dev).ok; }
+uint32_t device_cus(int dev) { return (uint32_t)device_info(dev).cus; }
+
 int launch_zero(unsigned long long* p, uint32_t n, hipStream_t stream) {
   hipLaunchKernelGGL(pfac_zero_kernel, dim3(1), dim3(1024), 0, stream, p, n);
   return hipGetLastError() == hipSuccess ? PFAC_OK : PFAC_E_HIP;
@@ -1148,10 +1172,14 @@ int pfac_match(const pfac_table* t, const void* d_text, uint64_t n, int enc, int
   if (hipGetDevice(&dev) != hipSuccess) return PFAC_E_NODEV;
   if (dev != t->device) return PFAC_E_ARG;
   hipStream_t stream = static_cast<hipStream_t>(stream_);
+  unsigned long long* counters = reinterpret_cast<unsigned long long*>(d_counters);
+  if (t->alphabet != 4) {
+    if (enc != PFAC_TEXT_ASCII) return PFAC_E_ARG;      // texts of a byte table are bytes
+    return match_bytes(t, d_text, n, d_match, d_hits, hit_cap, counters, plan, dev, stream);
+  }
   SinglePrep P;
   int rc = prepare_single(t, n, enc, plan, dev, &P);
   if (rc) return rc;
-  unsigned long long* counters = reinterpret_cast<unsigned long long*>(d_counters);
   if (P.tiles == 0) {
     hipLaunchKernelGGL(pfac_zero_kernel, dim3(1), dim3(64), 0, stream, counters, 2u);
     return hipGetLastError() == hipSuccess ? PFAC_OK : PFAC_E_HIP;
@@ -1212,7 +1240,7 @@ static int layout_batch(const pfac_table* const* tables, uint32_t num_tables,
                         int dev, BatchLayout* L) {
   if (!tables || num_tables == 0 || (num_texts && !descs)) return PFAC_E_ARG;
   for (uint32_t i = 0; i < num_tables; ++i)
-    if (!tables[i] || tables[i]->device != dev) return PFAC_E_ARG;
+    if (!tables[i] || tables[i]->device != dev || tables[i]->alphabet != 4) return PFAC_E_ARG;
   for (uint32_t s = 0; s < num_texts; ++s) {
     const pfac_text_desc& d = descs[s];
     if (d.n >= (1ull << 32) || d.table >= num_tables ||

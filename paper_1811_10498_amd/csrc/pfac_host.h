@@ -71,4 +71,20 @@ uint8_t* workspace_extra(const Workspace* ws);
 // Zero n 64-bit words at p with a fill kernel on `stream`.
 int launch_zero(unsigned long long* p, uint32_t n, hipStream_t stream);
 
+// The finish kernel of a one-text call of `tiles` tiles of `tile` positions
+// over a text of n positions whose dense output `match` was written (tiles
+// with more hits than slots take them from it).
+int launch_finish_single(const Scratch& sc, uint64_t tiles, uint32_t tile, uint64_t n,
+                         unsigned long long* counters, pfac_hit* d_hits, uint64_t hit_cap,
+                         const int32_t* match, hipStream_t stream);
+
+// A gfx950 device, and its compute units.
+bool device_ok(int dev);
+uint32_t device_cus(int dev);
+
+// pfac_match on a byte-alphabet table (bytes.hip).
+int match_bytes(const pfac_table* t, const void* d_text, uint64_t n, int32_t* d_match,
+                pfac_hit* d_hits, uint64_t hit_cap, unsigned long long* counters,
+                const pfac_plan* plan, int dev, hipStream_t stream);
+
 }  // namespace pfac

@@ -106,6 +106,31 @@ struct HostTable {
 int build_host_table(const char* const* patterns, const uint32_t* lengths, uint32_t num,
                      HostTable* out, int64_t* bad_index);
 
+// Byte-alphabet trie (every byte value a symbol): states renumbered
+// breadth-first, the edges of every state but the root in one open-addressing
+// hash table keyed by (state, byte), the root's 256 edges in a dense row.
+// Edge value: child in bits 0..30, bit 31 set when the child is final.
+constexpr uint32_t kBytesMaxStates = (1u << 24) - 1;
+constexpr uint32_t kBytesEmptyKey = 0xFFFFFFFFu;
+struct HostBytes {
+  uint64_t num_states = 0;
+  uint32_t num_patterns = 0, max_len = 0, min_len = 0;
+  uint32_t root[256] = {};
+  uint32_t hash_bits = 0;
+  std::vector<uint32_t> slots;             // [2 << hash_bits]: key (state << 8 | byte), value
+  std::vector<OutEntry> out;               // [S]
+  std::vector<uint64_t> depth_start;
+  uint64_t edges = 0;
+};
+int build_host_bytes(const char* const* patterns, const uint32_t* lengths, uint32_t num,
+                     HostBytes* out, int64_t* bad_index);
+
+// Slot of (state, byte) in the byte trie's hash table: Fibonacci hashing of
+// the key, linear probing.
+inline uint32_t bytes_hash(uint32_t key, uint32_t bits) {
+  return (uint32_t)(key * 0x9E3779B1u) >> (32 - bits);
+}
+
 // Device arrays of one table.
 struct DevTable {
   const uint32_t* next;
@@ -128,7 +153,15 @@ struct DevTable {
 
 struct pfac_table {
   int device = 0;
+  uint32_t alphabet = 4;            // 4: DNA table; 256: byte table (`bytes`, `bdev`)
   pfac::HostTable host;             // kept for info queries
+  pfac::HostBytes bytes;
+  struct {
+    const uint32_t* root;           // [256]
+    const uint32_t* slots;          // [2 << hash_bits]
+    const pfac::OutEntry* out;      // [S]
+    uint32_t hash_bits;
+  } bdev{};
   void* dmem = nullptr;             // one device allocation for every array
   uint64_t dbytes = 0;
   pfac::DevTable dev{};             // device pointers into dmem

@@ -40,9 +40,15 @@ def _plan_struct(plan) -> Optional[L.PfacPlan]:
 
 
 class Table:
-    """Failure-less goto trie of a pattern set, resident on the current GPU."""
+    """Failure-less goto trie of a pattern set, resident on the current GPU.
+    ``alphabet`` "dna": patterns over A, C, G, T (every other text byte stops a
+    walk); "bytes": every byte value is a symbol (hash-compressed table,
+    one-text ``match`` only)."""
 
-    def __init__(self, patterns: Sequence[bytes]):
+    def __init__(self, patterns: Sequence[bytes], alphabet: str = "dna"):
+        if alphabet not in ("dna", "bytes"):
+            raise ValueError("alphabet is 'dna' or 'bytes'")
+        self.alphabet = alphabet
         pats = [bytes(p) for p in patterns]
         self.num_patterns = len(pats)
         bufs = [ctypes.create_string_buffer(p, max(1, len(p))) for p in pats]
@@ -52,9 +58,9 @@ class Table:
         lens = (ctypes.c_uint32 * max(1, len(pats)))(*[len(p) for p in pats])
         h = ctypes.c_void_p()
         bad = ctypes.c_int64(-1)
-        rc = L.lib().pfac_build_table(ctypes.cast(arr, ctypes.c_void_p),
-                                      ctypes.cast(lens, ctypes.c_void_p), len(pats),
-                                      ctypes.byref(h), ctypes.byref(bad))
+        build = L.lib().pfac_build_table_bytes if alphabet == "bytes" else L.lib().pfac_build_table
+        rc = build(ctypes.cast(arr, ctypes.c_void_p), ctypes.cast(lens, ctypes.c_void_p),
+                   len(pats), ctypes.byref(h), ctypes.byref(bad))
         if rc != 0:
             e = L.PfacError(rc, "pfac_build_table")
             e.bad_index = bad.value
