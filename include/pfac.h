@@ -197,6 +197,39 @@ int pfac_build_table(const char* const* patterns, const uint32_t* lengths, uint3
 int pfac_build_table_bytes(const char* const* patterns, const uint32_t* lengths, uint32_t num,
                            pfac_table** out, int64_t* bad_index);
 
+/*
+ * The same table as pfac_build_table, built on the device (the host only
+ * checks and packs the patterns; the trie, its breadth-first numbering and
+ * every derived array are computed by kernels): with the patterns sorted as
+ * strings, the states of depth d are their distinct d-base prefixes in
+ * breadth-first order, so a scan per depth numbers them.  `ids` (or NULL for
+ * 1..num) gives each pattern's ID (> 0; the smallest ID among equal patterns
+ * is reported).  Patterns of at most 64 bases (PFAC_E_ARG beyond, with
+ * *bad_index set).  Synchronous; uses temporary device memory.
+ */
+int pfac_build_table_device(const char* const* patterns, const uint32_t* lengths,
+                            const int32_t* ids, uint32_t num, pfac_table** out,
+                            int64_t* bad_index);
+
+/*
+ * A new table: the patterns of `base` (each keeps its ID) except those whose
+ * ID is in remove_ids, plus `add` (new IDs from one above the largest ID of
+ * base, in order; *first_new_id receives the first, may be NULL), built on
+ * the device as pfac_build_table_device.  `base` is unchanged and stays
+ * usable (a server swaps tables when the new one is ready).  IDs are not
+ * renumbered, so removed IDs leave gaps.  Tables from pfac_build_table and
+ * pfac_build_table_device keep their pattern sets for this; byte tables are
+ * not updated (PFAC_E_ARG).
+ */
+int pfac_table_update(const pfac_table* base, const char* const* add, const uint32_t* add_lens,
+                      uint32_t num_add, const int32_t* remove_ids, uint32_t num_remove,
+                      pfac_table** out, int32_t* first_new_id);
+
+/* Copy the table's whole device allocation (every array, at the offsets
+ * both builds share; gaps are zero) to host memory: *bytes receives its
+ * size, `host` (cap bytes) is written when large enough.  For tests. */
+int pfac_table_blob(const pfac_table* table, void* host, uint64_t cap, uint64_t* bytes);
+
 int pfac_table_info(const pfac_table* table, pfac_table_stats* out);
 
 /* Frees host and device memory (synchronises the device first).  NULL is a no-op. */

@@ -21,7 +21,8 @@ PFAC_WALKS_DEFERRED = 2
 PFAC_PREFIX_NONE = 0xFFFFFFFF
 
 EXPORTS = (
-    "pfac_build_table", "pfac_build_table_bytes", "pfac_table_info", "pfac_free_table", "pfac_match",
+    "pfac_build_table", "pfac_build_table_bytes", "pfac_build_table_device",
+    "pfac_table_update", "pfac_table_blob", "pfac_table_info", "pfac_free_table", "pfac_match",
     "pfac_match_all", "pfac_match_batch", "pfac_batch_create", "pfac_batch_launch", "pfac_batch_info",
     "pfac_batch_free",
     "pfac_default_plan", "pfac_build_host", "pfac_build_host_image", "pfac_build_host_hash",
@@ -85,6 +86,14 @@ def lib():
             L.pfac_build_table_bytes.argtypes = [P, P, u32, ctypes.POINTER(P),
                                                  ctypes.POINTER(i64)]
             L.pfac_build_table_bytes.restype = ctypes.c_int
+            L.pfac_build_table_device.argtypes = [P, P, P, u32, ctypes.POINTER(P),
+                                                  ctypes.POINTER(i64)]
+            L.pfac_build_table_device.restype = ctypes.c_int
+            L.pfac_table_update.argtypes = [P, P, P, u32, P, u32, ctypes.POINTER(P),
+                                            ctypes.POINTER(ctypes.c_int32)]
+            L.pfac_table_update.restype = ctypes.c_int
+            L.pfac_table_blob.argtypes = [P, P, u64, ctypes.POINTER(u64)]
+            L.pfac_table_blob.restype = ctypes.c_int
             L.pfac_table_info.argtypes = [P, ctypes.POINTER(PfacTableStats)]
             L.pfac_table_info.restype = ctypes.c_int
             L.pfac_free_table.argtypes = [P]

@@ -907,11 +907,141 @@ static uint32_t defer_per_tile(const HostTable& h, const pfac_plan& pl, uint32_t
   return (uint32_t)std::min(32.0, std::max(4.0, per));
 }
 
+// Byte offsets of every array of a table in its one device allocation:
+// next | out | chain | per depth: jump, jres, image, level descriptors |
+// second-filter bitmaps | prefix bitmap | duplicate IDs.  Computed from the
+// table's metadata (state count, depth starts, image layouts, filter K's),
+// so a table built on the host and one built on the device share it.
+void table_layout(const HostTable& h, uint64_t ndups, TableLayout* L) {
+  const uint64_t S = h.num_states;
+  uint64_t off = 0;
+  L->o_next = off; off = al256(off + S * 16);
+  L->o_out = off; off = al256(off + S * sizeof(OutEntry));
+  L->o_chain = off; off = al256(off + S * 8);
+  for (uint32_t D = kMinJump; D <= kMaxJump; ++D) {
+    const uint64_t E = 1ull << (2 * D);
+    const HostTable::Image& im = h.image[D];
+    L->image_words[D] = im.levels ? im.upto[im.levels - 1] : (uint32_t)(E / 32 + E / 128);
+    L->o_jump[D] = off; off = al256(off + E * 4);
+    L->o_jres[D] = off; off = al256(off + E * sizeof(OutEntry));
+    L->o_im[D] = off; off = al256(off + (uint64_t)L->image_words[D] * 4);
+    L->lvdesc[D].assign(4 * kImageLevels, 0);
+    for (uint32_t k = 0; k < kImageLevels; ++k) {
+      if (k < im.levels) {
+        L->lvdesc[D][4 * k] = im.byte_off[k];
+        L->lvdesc[D][4 * k + 1] = im.pre_off[k];
+      }
+      if (D + k < h.depth_start.size()) L->lvdesc[D][4 * k + 2] = (uint32_t)h.depth_start[D + k];
+    }
+    L->o_lv[D] = off; off = al256(off + L->lvdesc[D].size() * 4);
+  }
+  for (uint32_t b = kHashMinBits; b <= kHashMaxBits; ++b) {
+    L->hash_words[b] = h.hash_k ? (1u << b) / 32 : 0;
+    L->o_hash[b] = off; off = al256(off + (uint64_t)L->hash_words[b] * 4);
+  }
+  L->pfx_words = h.pfx_k ? (1ull << (2 * h.pfx_k)) / 32 : 0;
+  L->o_pfx = off; off = al256(off + L->pfx_words * 4);
+  L->ndups = ndups;
+  L->o_dups = off; off = al256(off + ndups * 4);
+  L->o_dupi = off; off = al256(off + ndups * 4);
+  L->bytes = off;
+}
+
+// Allocate (zeroed) and point t->dev at the arrays of t's layout; uploads
+// the level descriptors.
+int alloc_table(pfac_table* t, uint64_t ndups) {
+  TableLayout& L = t->layout;
+  table_layout(t->host, ndups, &L);
+  if (hipMalloc(&t->dmem, L.bytes) != hipSuccess) {
+    t->dmem = nullptr;
+    return PFAC_E_NOMEM;
+  }
+  t->dbytes = L.bytes;
+  char* base = static_cast<char*>(t->dmem);
+  if (hipMemset(base, 0, L.bytes) != hipSuccess) return PFAC_E_HIP;
+  DevTable& v = t->dev;
+  memset(&v, 0, sizeof(v));
+  v.next = reinterpret_cast<const uint32_t*>(base + L.o_next);
+  v.out = reinterpret_cast<const OutEntry*>(base + L.o_out);
+  v.chain = reinterpret_cast<const uint32_t*>(base + L.o_chain);
+  v.pfx = L.pfx_words ? reinterpret_cast<const uint32_t*>(base + L.o_pfx) : nullptr;
+  v.dup_state = reinterpret_cast<const uint32_t*>(base + L.o_dups);
+  v.dup_id = reinterpret_cast<const int32_t*>(base + L.o_dupi);
+  v.num_dups = (uint32_t)ndups;
+  v.num_states = (uint32_t)t->host.num_states;
+  v.max_len = t->host.max_len;
+  for (uint32_t D = kMinJump; D <= kMaxJump; ++D) {
+    v.levels[D] = reinterpret_cast<const uint32_t*>(base + L.o_lv[D]);
+    v.jump[D] = reinterpret_cast<const uint32_t*>(base + L.o_jump[D]);
+    v.jres[D] = reinterpret_cast<const OutEntry*>(base + L.o_jres[D]);
+    v.image[D] = reinterpret_cast<const uint32_t*>(base + L.o_im[D]);
+    if (hipMemcpy(base + L.o_lv[D], L.lvdesc[D].data(), L.lvdesc[D].size() * 4,
+                  hipMemcpyHostToDevice) != hipSuccess)
+      return PFAC_E_HIP;
+  }
+  for (uint32_t b = kHashMinBits; b <= kHashMaxBits; ++b)
+    v.hash[b] = reinterpret_cast<const uint32_t*>(base + L.o_hash[b]);
+  return PFAC_OK;
+}
+
+// Copy a host-built table's arrays into its device allocation.
+int upload_host_table(pfac_table* t) {
+  const HostTable& h = t->host;
+  const TableLayout& L = t->layout;
+  char* base = static_cast<char*>(t->dmem);
+  auto put = [&](uint64_t o, const void* src, size_t bytes) {
+    return bytes == 0 || hipMemcpy(base + o, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+  };
+  bool ok = put(L.o_next, h.next.data(), h.next.size() * 4) &&
+            put(L.o_out, h.out.data(), h.out.size() * sizeof(OutEntry)) &&
+            put(L.o_chain, h.chain.data(), h.chain.size() * 4) &&
+            put(L.o_pfx, h.pfx.data(), h.pfx.size() * 4) &&
+            put(L.o_dups, h.dup_state.data(), h.dup_state.size() * 4) &&
+            put(L.o_dupi, h.dup_id.data(), h.dup_id.size() * 4);
+  for (uint32_t D = kMinJump; D <= kMaxJump; ++D)
+    ok = ok && put(L.o_jump[D], h.jump[D].data(), h.jump[D].size() * 4) &&
+         put(L.o_jres[D], h.jres[D].data(), h.jres[D].size() * sizeof(OutEntry)) &&
+         put(L.o_im[D], h.image[D].words.data(), h.image[D].words.size() * 4);
+  for (uint32_t b = kHashMinBits; b <= kHashMaxBits; ++b)
+    ok = ok && put(L.o_hash[b], h.hash[b].data(), h.hash[b].size() * 4);
+  return ok ? PFAC_OK : PFAC_E_HIP;
+}
+
+// Keep the pattern set (bytes and IDs) with the table, for updates.
+int remember_patterns(pfac_table* t, const char* const* patterns, const uint32_t* lengths,
+                      uint32_t num, const int32_t* ids) {
+  try {
+    t->pats.resize(num);
+    t->ids.resize(num);
+    for (uint32_t k = 0; k < num; ++k) {
+      t->pats[k].assign(patterns[k], lengths[k]);
+      t->ids[k] = ids ? ids[k] : (int32_t)(k + 1);
+    }
+  } catch (const std::bad_alloc&) {
+    return PFAC_E_NOMEM;
+  }
+  return PFAC_OK;
+}
+
 }  // namespace pfac
 
 using namespace pfac;
 
 extern "C" {
+
+int pfac_table_blob(const pfac_table* t, void* host, uint64_t cap, uint64_t* bytes) {
+  if (!t || !bytes) return PFAC_E_ARG;
+  *bytes = t->dbytes;
+  if (host && cap >= t->dbytes) {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (hipSetDevice(t->device) != hipSuccess) return PFAC_E_HIP;
+    const hipError_t e = hipMemcpy(host, t->dmem, t->dbytes, hipMemcpyDeviceToHost);
+    (void)hipSetDevice(cur);
+    if (e != hipSuccess) return PFAC_E_HIP;
+  }
+  return PFAC_OK;
+}
 
 const char* pfac_strerror(int s) {
   switch (s) {
@@ -945,81 +1075,13 @@ int pfac_build_table(const char* const* patterns, const uint32_t* lengths, uint3
     return rc;
   }
   t->device = dev;
-  const HostTable& h = t->host;
-  // one device allocation: next | out | chain | per depth: jump, jres, image,
-  // level descriptors | second-filter bitmaps | prefix bitmap
-  uint64_t off = 0;
-  const uint64_t o_next = off; off = al256(off + h.next.size() * 4);
-  const uint64_t o_out = off; off = al256(off + h.out.size() * sizeof(OutEntry));
-  const uint64_t o_chain = off; off = al256(off + h.chain.size() * 4);
-  uint64_t o_jump[kMaxJump + 1] = {}, o_jres[kMaxJump + 1] = {}, o_im[kMaxJump + 1] = {};
-  uint64_t o_lv[kMaxJump + 1] = {};
-  std::vector<uint32_t> lvdesc[kMaxJump + 1];
-  for (uint32_t D = kMinJump; D <= kMaxJump; ++D) {
-    o_jump[D] = off; off = al256(off + h.jump[D].size() * 4);
-    o_jres[D] = off; off = al256(off + h.jres[D].size() * sizeof(OutEntry));
-    o_im[D] = off; off = al256(off + h.image[D].words.size() * 4);
-    lvdesc[D].assign(4 * kImageLevels, 0);
-    for (uint32_t k = 0; k < kImageLevels; ++k) {
-      if (k < h.image[D].levels) {
-        lvdesc[D][4 * k] = h.image[D].byte_off[k];
-        lvdesc[D][4 * k + 1] = h.image[D].pre_off[k];
-      }
-      if (D + k < h.depth_start.size()) lvdesc[D][4 * k + 2] = (uint32_t)h.depth_start[D + k];
-    }
-    o_lv[D] = off; off = al256(off + lvdesc[D].size() * 4);
-  }
-  uint64_t o_hash[kHashMaxBits + 1] = {};
-  for (uint32_t b = kHashMinBits; b <= kHashMaxBits; ++b) {
-    o_hash[b] = off; off = al256(off + h.hash[b].size() * 4);
-  }
-  const uint64_t o_pfx = off; off = al256(off + h.pfx.size() * 4);
-  const uint64_t o_dups = off; off = al256(off + h.dup_state.size() * 4);
-  const uint64_t o_dupi = off; off = al256(off + h.dup_id.size() * 4);
-  if (hipMalloc(&t->dmem, off) != hipSuccess) {
+  rc = remember_patterns(t, patterns, lengths, num, nullptr);
+  if (!rc) rc = alloc_table(t, t->host.dup_state.size());
+  if (!rc) rc = upload_host_table(t);
+  if (rc) {
+    if (t->dmem) (void)hipFree(t->dmem);
     delete t;
-    return PFAC_E_NOMEM;
-  }
-  t->dbytes = off;
-  char* base = static_cast<char*>(t->dmem);
-  auto put = [&](uint64_t o, const void* src, size_t bytes) {
-    return bytes == 0 || hipMemcpy(base + o, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
-  };
-  bool ok = put(o_next, h.next.data(), h.next.size() * 4) &&
-            put(o_out, h.out.data(), h.out.size() * sizeof(OutEntry)) &&
-            put(o_chain, h.chain.data(), h.chain.size() * 4) &&
-            put(o_pfx, h.pfx.data(), h.pfx.size() * 4) &&
-            put(o_dups, h.dup_state.data(), h.dup_state.size() * 4) &&
-            put(o_dupi, h.dup_id.data(), h.dup_id.size() * 4);
-  DevTable& v = t->dev;
-  memset(&v, 0, sizeof(v));
-  v.next = reinterpret_cast<const uint32_t*>(base + o_next);
-  v.out = reinterpret_cast<const OutEntry*>(base + o_out);
-  v.chain = reinterpret_cast<const uint32_t*>(base + o_chain);
-  v.pfx = h.pfx.empty() ? nullptr : reinterpret_cast<const uint32_t*>(base + o_pfx);
-  v.dup_state = reinterpret_cast<const uint32_t*>(base + o_dups);
-  v.dup_id = reinterpret_cast<const int32_t*>(base + o_dupi);
-  v.num_dups = (uint32_t)h.dup_state.size();
-  v.num_states = (uint32_t)h.num_states;
-  v.max_len = h.max_len;
-  for (uint32_t D = kMinJump; D <= kMaxJump; ++D) {
-    ok = ok && put(o_jump[D], h.jump[D].data(), h.jump[D].size() * 4) &&
-         put(o_jres[D], h.jres[D].data(), h.jres[D].size() * sizeof(OutEntry)) &&
-         put(o_im[D], h.image[D].words.data(), h.image[D].words.size() * 4) &&
-         put(o_lv[D], lvdesc[D].data(), lvdesc[D].size() * 4);
-    v.levels[D] = reinterpret_cast<const uint32_t*>(base + o_lv[D]);
-    v.jump[D] = reinterpret_cast<const uint32_t*>(base + o_jump[D]);
-    v.jres[D] = reinterpret_cast<const OutEntry*>(base + o_jres[D]);
-    v.image[D] = reinterpret_cast<const uint32_t*>(base + o_im[D]);
-  }
-  for (uint32_t b = kHashMinBits; b <= kHashMaxBits; ++b) {
-    ok = ok && put(o_hash[b], h.hash[b].data(), h.hash[b].size() * 4);
-    v.hash[b] = reinterpret_cast<const uint32_t*>(base + o_hash[b]);
-  }
-  if (!ok) {
-    (void)hipFree(t->dmem);
-    delete t;
-    return PFAC_E_HIP;
+    return rc;
   }
   *out = t;
   return PFAC_OK;

@@ -82,6 +82,14 @@ int launch_finish_single(const Scratch& sc, uint64_t tiles, uint32_t tile, uint6
 bool device_ok(int dev);
 uint32_t device_cus(int dev);
 
+// Device memory of a table: layout from its metadata, zeroed allocation,
+// pointers; the host-built arrays uploaded; the pattern set kept.
+void table_layout(const HostTable& h, uint64_t ndups, TableLayout* L);
+int alloc_table(pfac_table* t, uint64_t ndups);
+int upload_host_table(pfac_table* t);
+int remember_patterns(pfac_table* t, const char* const* patterns, const uint32_t* lengths,
+                      uint32_t num, const int32_t* ids);
+
 // pfac_match on a byte-alphabet table (bytes.hip).
 int match_bytes(const pfac_table* t, const void* d_text, uint64_t n, int32_t* d_match,
                 pfac_hit* d_hits, uint64_t hit_cap, unsigned long long* counters,

@@ -3,6 +3,7 @@
 
 #include <stdint.h>
 
+#include <string>
 #include <vector>
 
 #include "pfac.h"
@@ -149,6 +150,20 @@ struct DevTable {
   uint32_t max_len;
 };
 
+// Offsets of a table's arrays in its one device allocation (table_layout).
+struct TableLayout {
+  uint64_t o_next = 0, o_out = 0, o_chain = 0;
+  uint64_t o_jump[kMaxJump + 1] = {}, o_jres[kMaxJump + 1] = {}, o_im[kMaxJump + 1] = {};
+  uint64_t o_lv[kMaxJump + 1] = {};
+  uint32_t image_words[kMaxJump + 1] = {};
+  std::vector<uint32_t> lvdesc[kMaxJump + 1];
+  uint64_t o_hash[kHashMaxBits + 1] = {};
+  uint32_t hash_words[kHashMaxBits + 1] = {};
+  uint64_t o_pfx = 0, pfx_words = 0;
+  uint64_t o_dups = 0, o_dupi = 0, ndups = 0;
+  uint64_t bytes = 0;
+};
+
 }  // namespace pfac
 
 struct pfac_table {
@@ -165,6 +180,9 @@ struct pfac_table {
   void* dmem = nullptr;             // one device allocation for every array
   uint64_t dbytes = 0;
   pfac::DevTable dev{};             // device pointers into dmem
+  pfac::TableLayout layout;
+  std::vector<std::string> pats;    // the pattern set and its IDs (updates start from it)
+  std::vector<int32_t> ids;
   // the paper's two-array and merged-cell layouts, built on first use
   mutable void* cells_mem = nullptr;
   mutable const uint32_t* next2 = nullptr;

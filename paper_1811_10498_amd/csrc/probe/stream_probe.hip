@@ -11,10 +11,12 @@
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 
+// flags: bit 0 = plain (write-back) stores instead of non-temporal ones,
+// bit 1 = plain loads instead of non-temporal ones.
 template <uint32_t TILE>
 __global__ __launch_bounds__(1024) void stream_probe_kernel(const uint8_t* src, int32_t* dst,
                                                             uint64_t tiles, uint32_t mode,
-                                                            uint32_t* sink) {
+                                                            uint32_t flags, uint32_t* sink) {
   const uint32_t lane = threadIdx.x & 63;
   const uint64_t wave = (uint64_t)blockIdx.x * 16 + (threadIdx.x >> 6);
   const uint64_t nwaves = (uint64_t)gridDim.x * 16;
@@ -23,16 +25,18 @@ __global__ __launch_bounds__(1024) void stream_probe_kernel(const uint8_t* src, 
     if (mode != 2) {
       #pragma unroll
       for (uint32_t k = 0; k < TILE / 1024; ++k) {
-        const u32x4 v = __builtin_nontemporal_load(
-            reinterpret_cast<const u32x4*>(src + t * TILE + k * 1024) + lane);
+        const u32x4* a = reinterpret_cast<const u32x4*>(src + t * TILE + k * 1024) + lane;
+        const u32x4 v = (flags & 2u) ? *a : __builtin_nontemporal_load(a);
         acc ^= v.x ^ v.y ^ v.z ^ v.w;
       }
     }
     if (mode != 1) {
       const i32x4 z = {(int32_t)(acc & 1u), 0, 0, 0};
       #pragma unroll
-      for (uint32_t k = 0; k < TILE / 256; ++k)
-        __builtin_nontemporal_store(z, reinterpret_cast<i32x4*>(dst + t * TILE + k * 256) + lane);
+      for (uint32_t k = 0; k < TILE / 256; ++k) {
+        i32x4* d = reinterpret_cast<i32x4*>(dst + t * TILE + k * 256) + lane;
+        if (flags & 1u) *d = z; else __builtin_nontemporal_store(z, d);
+      }
     }
   }
   if (acc == 0x9E3779B1u) sink[0] = acc;   // keeps the loads; practically never taken
@@ -42,8 +46,9 @@ extern "C" {
 
 // Run the probe over `tiles` tiles of 2048 positions on `stream`: src holds
 // tiles*2048 bytes, dst tiles*2048 int32.  grid = 0: one workgroup per CU.
+// flags as the kernel's.
 int pfac_probe_stream(const void* src, int32_t* dst, uint64_t tiles, uint32_t mode,
-                      uint32_t grid, uint32_t* sink, void* stream) {
+                      uint32_t flags, uint32_t grid, uint32_t* sink, void* stream) {
   if (mode > 2 || (mode != 2 && !src) || (mode != 1 && !dst) || !sink) return -1;
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
@@ -52,7 +57,7 @@ int pfac_probe_stream(const void* src, int32_t* dst, uint64_t tiles, uint32_t mo
   const uint32_t g = grid ? grid : (uint32_t)cus;
   hipLaunchKernelGGL(stream_probe_kernel<2048>, dim3(g), dim3(1024), 0,
                      static_cast<hipStream_t>(stream), static_cast<const uint8_t*>(src), dst,
-                     tiles, mode, sink);
+                     tiles, mode, flags, sink);
   return hipGetLastError() == hipSuccess ? 0 : -5;
 }
 

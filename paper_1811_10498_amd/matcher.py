@@ -45,10 +45,16 @@ class Table:
     walk); "bytes": every byte value is a symbol (hash-compressed table,
     one-text ``match`` only)."""
 
-    def __init__(self, patterns: Sequence[bytes], alphabet: str = "dna"):
+    def __init__(self, patterns: Sequence[bytes], alphabet: str = "dna", on_device: bool = False,
+                 ids: Optional[Sequence[int]] = None, _handle=None):
         if alphabet not in ("dna", "bytes"):
             raise ValueError("alphabet is 'dna' or 'bytes'")
         self.alphabet = alphabet
+        if _handle is not None:
+            self._h = _handle
+            self._lib = L.lib()
+            self._read_info()
+            return
         pats = [bytes(p) for p in patterns]
         self.num_patterns = len(pats)
         bufs = [ctypes.create_string_buffer(p, max(1, len(p))) for p in pats]
@@ -58,17 +64,60 @@ class Table:
         lens = (ctypes.c_uint32 * max(1, len(pats)))(*[len(p) for p in pats])
         h = ctypes.c_void_p()
         bad = ctypes.c_int64(-1)
-        build = L.lib().pfac_build_table_bytes if alphabet == "bytes" else L.lib().pfac_build_table
-        rc = build(ctypes.cast(arr, ctypes.c_void_p), ctypes.cast(lens, ctypes.c_void_p),
-                   len(pats), ctypes.byref(h), ctypes.byref(bad))
+        if on_device:
+            idarr = None if ids is None else (ctypes.c_int32 * max(1, len(pats)))(*[int(x) for x in ids])
+            rc = L.lib().pfac_build_table_device(
+                ctypes.cast(arr, ctypes.c_void_p), ctypes.cast(lens, ctypes.c_void_p),
+                ctypes.cast(idarr, ctypes.c_void_p) if idarr is not None else None, len(pats),
+                ctypes.byref(h), ctypes.byref(bad))
+        else:
+            build = (L.lib().pfac_build_table_bytes if alphabet == "bytes"
+                     else L.lib().pfac_build_table)
+            rc = build(ctypes.cast(arr, ctypes.c_void_p), ctypes.cast(lens, ctypes.c_void_p),
+                       len(pats), ctypes.byref(h), ctypes.byref(bad))
         if rc != 0:
             e = L.PfacError(rc, "pfac_build_table")
             e.bad_index = bad.value
             raise e
         self._h = h
         self._lib = L.lib()
+        self._read_info()
+
+    def update(self, add: Sequence[bytes] = (), remove_ids: Sequence[int] = ()) -> "Table":
+        """A new table (built on the device): these patterns minus the IDs in
+        ``remove_ids``, plus ``add`` with new IDs from one above the largest.
+        The new table's ``first_new_id`` is the first of those."""
+        pats = [bytes(p) for p in add]
+        bufs = [ctypes.create_string_buffer(p, max(1, len(p))) for p in pats]
+        arr = (ctypes.c_void_p * max(1, len(pats)))()
+        for i, b in enumerate(bufs):
+            arr[i] = ctypes.addressof(b)
+        lens = (ctypes.c_uint32 * max(1, len(pats)))(*[len(p) for p in pats])
+        rem = (ctypes.c_int32 * max(1, len(remove_ids)))(*[int(x) for x in remove_ids])
+        h = ctypes.c_void_p()
+        first = ctypes.c_int32(0)
+        rc = self._lib.pfac_table_update(self._h, ctypes.cast(arr, ctypes.c_void_p),
+                                         ctypes.cast(lens, ctypes.c_void_p), len(pats),
+                                         ctypes.cast(rem, ctypes.c_void_p), len(remove_ids),
+                                         ctypes.byref(h), ctypes.byref(first))
+        L.check(rc, "pfac_table_update")
+        t = Table([], _handle=h)
+        t.first_new_id = int(first.value)
+        return t
+
+    def blob(self) -> np.ndarray:
+        """The table's device allocation as bytes (tests)."""
+        n = ctypes.c_uint64(0)
+        L.check(self._lib.pfac_table_blob(self._h, None, 0, ctypes.byref(n)), "pfac_table_blob")
+        out = np.zeros(int(n.value), dtype=np.uint8)
+        L.check(self._lib.pfac_table_blob(self._h, out.ctypes.data, out.size, ctypes.byref(n)),
+                "pfac_table_blob")
+        return out
+
+    def _read_info(self):
         st = L.PfacTableStats()
         L.check(self._lib.pfac_table_info(self._h, ctypes.byref(st)), "pfac_table_info")
+        self.num_patterns = int(st.num_patterns)
         self.num_states = int(st.num_states)
         self.max_len = int(st.max_len)
         self.min_len = int(st.min_len)
