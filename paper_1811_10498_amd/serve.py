@@ -400,10 +400,25 @@ class Server:
         for r in reqs:
             r.dispatched = t
         self.busy[si] = True
+        # the tables this dispatch reads stay alive until it completes (a
+        # table replaced meanwhile is freed after its last dispatch)
+        hold.append(list(self.tables))
         self.inflight.append(_Dispatch(reqs, si, ev, host_c, mt, hits, counters, first,
                                        match_offsets, lengths, (addrs, tids, stream), hold))
         self.max_seen_inflight = max(self.max_seen_inflight, len(self.inflight))
         self.dispatch_sizes.append(len(reqs))
+
+    def update_table(self, index: int, add: Sequence[bytes] = (),
+                     remove_ids: Sequence[int] = ()) -> Table:
+        """Replace table `index` by its update (patterns added and removed,
+        built on the device; IDs stay stable).  Requests dispatched from now on
+        use the new table; dispatches in flight finish on the old one."""
+        new = self.tables[index].update(add=add, remove_ids=remove_ids)
+        self.tables[index] = new
+        self._tabs = (ctypes.c_void_p * len(self.tables))(*[t.handle.value for t in self.tables])
+        for k in [k for k in self._prepared if k[0][0] == index]:
+            del self._prepared[k]                 # prepared batches name the old table
+        return new
 
     def _prepare(self, key, descs, ntext):
         """Keep a prepared batch for a one-request dispatch shape (offsets

@@ -138,3 +138,31 @@ def test_dispatches_overlap_on_the_device():
         torch.cuda.synchronize()
         assert torch.equal(r.result.text_match(0), alone.match)
         assert r.result.occurrences[0] == alone.total()
+
+
+def test_table_update_while_serving():
+    """A table replaced by its update between two waves of requests: the
+    requests dispatched before use the old table, those after the new one,
+    each equal to the plain call with its table."""
+    tries = W.served_tries(seed=8, sizes=[3000, 5000], pool_bases=1_000_000)
+    tables = [pf.Table(t) for t in tries]
+    g = W.rng(12)
+    pool = torch.from_numpy(W.uniform_ascii(16 << 20, g)).to(DEV)
+    first = [Request(i, i % 2, [pool[i * (1 << 20):(i + 1) * (1 << 20)]], 0.0) for i in range(6)]
+    srv = Server(tables, budget_bytes=4 << 30)
+    srv.run(first)
+    old = srv.tables[0]
+    add = W.cut_patterns(W.uniform_ascii(1 << 20, W.rng(13)), 500, 12, 30, W.rng(14))
+    add += [bytes(pool[6 << 20:(6 << 20) + 20].cpu().numpy())]    # occurs in the next wave
+    new = srv.update_table(0, add=add, remove_ids=list(range(1, 200)))
+    second = [Request(10 + i, 0, [pool[(6 + i) * (1 << 20):(7 + i) * (1 << 20)]], 0.0)
+              for i in range(4)]
+    srv.run(second)
+    for r in srv.done:
+        tab = old if r.rid < 10 else new
+        alone = pf.match(tab, r.text(0), hit_cap=hit_cap_of(r.lengths))
+        torch.cuda.synchronize()
+        assert torch.equal(r.result.text_match(0), alone.match), r.rid
+        assert r.result.occurrences[0] == alone.total()
+    r10 = next(r for r in srv.done if r.rid == 10)
+    assert int(r10.result.text_match(0)[0]) >= new.first_new_id
