@@ -887,21 +887,20 @@ static void fill_table(ScanParams& sp, const pfac_table* t, const pfac_plan& pl)
 }
 
 // Deferred walks a tile keeps room for: about twice the walks the filters
-// let through on random text (windows passing the depth-D bitmap, then the
-// two hash bits, then an exact K2-base prefix), at least 4, at most 32.
+// let through on random text, at least 4, at most 32.  With the exact prefix
+// filter that is the fraction of K2-base windows that start a pattern;
+// otherwise the windows passing the depth-D bitmap, times the square of the
+// hashed bitmap's fill (its false positives; the true matches are few).
 static uint32_t defer_per_tile(const HostTable& h, const pfac_plan& pl, uint32_t tile) {
-  double pass = (double)h.bitmap_set[pl.depth] / (double)(1ull << (2 * pl.depth));
-  if (pl.hash_bits != PFAC_HASH_NONE) {
-    const double f = (double)h.hash_set[pl.hash_bits] / (double)(1ull << pl.hash_bits);
-    pass *= f * f;
-  }
-  if (pl.prefix == 1 && h.pfx_k > pl.depth && h.bitmap_set[pl.depth]) {
-    // of the windows whose D-base prefix leads into the trie, those whose
-    // K2-base prefix starts a pattern
-    const double cond = (double)h.pfx_set /
-                        ((double)h.bitmap_set[pl.depth] *
-                         (double)(1ull << (2 * (h.pfx_k - pl.depth))));
-    pass *= std::min(1.0, cond);
+  double pass;
+  if (pl.prefix == 1 && h.pfx_k > pl.depth) {
+    pass = (double)h.pfx_set / (double)(1ull << (2 * h.pfx_k));
+  } else {
+    pass = (double)h.bitmap_set[pl.depth] / (double)(1ull << (2 * pl.depth));
+    if (pl.hash_bits != PFAC_HASH_NONE) {
+      const double f = (double)h.hash_set[pl.hash_bits] / (double)(1ull << pl.hash_bits);
+      pass *= f * f;
+    }
   }
   const double per = std::ceil(2.0 * pass * tile) + 4.0;
   return (uint32_t)std::min(32.0, std::max(4.0, per));

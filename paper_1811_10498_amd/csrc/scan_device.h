@@ -724,98 +724,160 @@ __device__ __forceinline__ void put_counts(const ScanParams& p, uint64_t tile, u
   __hip_atomic_store(&p.tile_occ[tile], occ, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// One deferred walk: the depth-D jump entry of the window, then the walk
-// with path compression over the 64 bases copied with the entry, continued
-// on the text in global memory past them.  A pattern found is written to
-// the dense output and appended to its tile's hit slots (the finish kernel
-// orders each tile's slots by position).
+// The deferred walks of a wave, four per lane at a time: the depth-D jump
+// entry of each window, then the walk with path compression over the 64
+// bases copied with the entry (continued on the text in global memory past
+// them).  The four walks of a lane issue their table reads together, so each
+// step waits for one round trip instead of four.  A pattern found is written
+// to the dense output and appended to its tile's hit slots (the finish
+// kernel orders each tile's slots by position).
 template <uint32_t D, bool SINGLE, uint32_t TILE>
-__device__ __forceinline__ void deferred_walk(const ScanParams& p, const WalkEntry& we) {
-  const u32x4 a = reinterpret_cast<const u32x4*>(&we)[0];
-  const u32x4 b = reinterpret_cast<const u32x4*>(&we)[1];
-  const uint32_t pos = a.x;
-  const uint32_t c0 = a.z, c1 = a.w, c2 = b.x, c3 = b.y;
-  const uint64_t ivall = ((uint64_t)b.w << 32) | b.z;
-  uint64_t n, gt;
-  uint32_t enc;
-  const uint8_t* text;
-  int32_t* match;
-  if (SINGLE) {
-    n = p.seg0.n;
-    enc = p.seg0.enc;
-    text = p.text;
-    match = p.match;
-    gt = pos / TILE;
-  } else {
-    const DevSeg sg = p.segs[a.y >> 1];
-    n = sg.n;
-    enc = sg.enc;
-    text = p.text + sg.text_off;
-    match = p.match ? p.match + sg.match_off : nullptr;
-    gt = (uint64_t)sg.first_tile + pos / TILE;
-  }
-  int32_t best = 0;
-  unsigned long long occ = 0;
-  uint32_t s = 0, q = 0;
-  bool live = true;
-  if (!(a.y & 1u)) {
-    const uint32_t x = c0 >> (32 - 2 * D);
-    const uint32_t jj = p.jump[x];
-    if (jj & kFinalBit) {
-      const OutEntry o = p.jres[x];
-      best = o.pid;
-      occ += o.mult;
-    }
-    s = jj & kStateMask;
-    q = D;
-    live = s != 0;
-  }
-  while (live) {
-    if (q >= kWindow) {
-      // past the copied bases: go on reading the text itself
-      walk<true>(s, (uint64_t)pos + q, nullptr, nullptr, p.next, p.out, text, n, enc, best, occ);
-      break;
-    }
-    const uint32_t wk = q >> 4, sh = 2 * (q & 15u);
-    const uint32_t hi = wk == 0 ? c0 : wk == 1 ? c1 : wk == 2 ? c2 : c3;
-    const uint32_t lo = wk == 0 ? c1 : wk == 1 ? c2 : wk == 2 ? c3 : 0u;
-    const uint32_t win = (uint32_t)(((((uint64_t)hi << 32) | lo) << sh) >> 32);
-    const uint32_t ivw = (uint32_t)(ivall >> q);
-    const u32x2 ch = *reinterpret_cast<const u32x2*>(p.chain + 2ull * s);
-    const uint32_t e = p.next[(uint64_t)s * 4 + (win >> 30)];
-    const uint32_t len = ch.x & 15u;
-    if (len >= 2) {
-      if (q + len > kWindow) {
-        // the run reaches past the copied bases
-        walk<true>(s, (uint64_t)pos + q, nullptr, nullptr, p.next, p.out, text, n, enc, best,
-                   occ);
-        break;
+__device__ __forceinline__ void deferred_walks(const ScanParams& p, const WalkEntry* wq,
+                                               uint32_t count) {
+  constexpr int M = 4;
+  const uint32_t lane = threadIdx.x & 63;
+  #pragma unroll 1
+  for (uint32_t j0 = 0; j0 < count; j0 += 64 * M) {
+    uint32_t pos[M], c[M][4], ivlo[M], ivhi[M], s[M], q[M], si[M];
+    int32_t best[M];
+    unsigned long long occ[M];
+    bool live[M], valid[M], slow[M];
+    uint32_t jj[M];
+    #pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const uint32_t j = j0 + 64 * m + lane;
+      valid[m] = j < count;
+      best[m] = 0;
+      occ[m] = 0;
+      s[m] = 0;
+      q[m] = 0;
+      jj[m] = 0;
+      if (valid[m]) {
+        const u32x4 a = reinterpret_cast<const u32x4*>(wq + j)[0];
+        const u32x4 b = reinterpret_cast<const u32x4*>(wq + j)[1];
+        pos[m] = a.x;
+        slow[m] = (a.y & 1u) != 0;
+        si[m] = a.y >> 1;
+        c[m][0] = a.z; c[m][1] = a.w; c[m][2] = b.x; c[m][3] = b.y;
+        ivlo[m] = b.z;
+        ivhi[m] = b.w;
+      } else {
+        pos[m] = 0; slow[m] = true; si[m] = 0;
+        c[m][0] = c[m][1] = c[m][2] = c[m][3] = 0;
+        ivlo[m] = ivhi[m] = 0;
       }
-      if ((ivw & ((1u << len) - 1u)) | ((win ^ ch.x) & (0xFFFFFFFFu << (32 - 2 * len)))) break;
-      s = ch.y & kStateMask;
-      q += len;
-      if (ch.y & kFinalBit) {
-        const OutEntry o = p.out[s];
-        best = o.pid;
-        occ += o.mult;
+    }
+    // the jump entries of the windows (walks from the root start at state 0)
+    #pragma unroll
+    for (int m = 0; m < M; ++m)
+      if (valid[m] && !slow[m]) jj[m] = p.jump[c[m][0] >> (32 - 2 * D)];
+    #pragma unroll
+    for (int m = 0; m < M; ++m) {
+      live[m] = valid[m];
+      if (valid[m] && !slow[m]) {
+        if (jj[m] & kFinalBit) {
+          const OutEntry o = p.jres[c[m][0] >> (32 - 2 * D)];
+          best[m] = o.pid;
+          occ[m] += o.mult;
+        }
+        s[m] = jj[m] & kStateMask;
+        q[m] = D;
+        live[m] = s[m] != 0;
       }
-      continue;
     }
-    if ((ivw & 1u) || e == 0) break;
-    s = e & kStateMask;
-    if (e & kFinalBit) {
-      const OutEntry o = p.out[s];
-      best = o.pid;
-      occ += o.mult;
+    for (;;) {
+      bool any = false;
+      u32x2 ch[M];
+      uint32_t e[M], win[M];
+      #pragma unroll
+      for (int m = 0; m < M; ++m) {
+        ch[m] = u32x2{0u, 0u};
+        e[m] = 0;
+        win[m] = 0;
+        if (live[m] && q[m] < kWindow) {
+          const uint32_t wk = q[m] >> 4, sh = 2 * (q[m] & 15u);
+          const uint32_t hi = wk == 0 ? c[m][0] : wk == 1 ? c[m][1] : wk == 2 ? c[m][2] : c[m][3];
+          const uint32_t lo = wk == 0 ? c[m][1] : wk == 1 ? c[m][2] : wk == 2 ? c[m][3] : 0u;
+          win[m] = (uint32_t)(((((uint64_t)hi << 32) | lo) << sh) >> 32);
+          ch[m] = *reinterpret_cast<const u32x2*>(p.chain + 2ull * s[m]);
+          e[m] = p.next[(uint64_t)s[m] * 4 + (win[m] >> 30)];
+        }
+      }
+      #pragma unroll
+      for (int m = 0; m < M; ++m) {
+        if (!live[m]) continue;
+        bool global = q[m] >= kWindow;
+        const uint32_t len = ch[m].x & 15u;
+        if (!global && len >= 2 && q[m] + len > kWindow) global = true;
+        if (global) {
+          // past the copied bases: go on reading the text itself
+          const uint8_t* text;
+          uint64_t n;
+          uint32_t enc;
+          if (SINGLE) {
+            text = p.text; n = p.seg0.n; enc = p.seg0.enc;
+          } else {
+            const DevSeg sg = p.segs[si[m]];
+            text = p.text + sg.text_off; n = sg.n; enc = sg.enc;
+          }
+          walk<true>(s[m], (uint64_t)pos[m] + q[m], nullptr, nullptr, p.next, p.out, text, n, enc,
+                     best[m], occ[m]);
+          live[m] = false;
+          continue;
+        }
+        const uint64_t ivall = ((uint64_t)ivhi[m] << 32) | ivlo[m];
+        const uint32_t ivw = (uint32_t)(ivall >> q[m]);
+        if (len >= 2) {
+          if ((ivw & ((1u << len) - 1u)) | ((win[m] ^ ch[m].x) & (0xFFFFFFFFu << (32 - 2 * len)))) {
+            live[m] = false;
+            continue;
+          }
+          s[m] = ch[m].y & kStateMask;
+          q[m] += len;
+          if (ch[m].y & kFinalBit) {
+            const OutEntry o = p.out[s[m]];
+            best[m] = o.pid;
+            occ[m] += o.mult;
+          }
+        } else {
+          if ((ivw & 1u) || e[m] == 0) {
+            live[m] = false;
+            continue;
+          }
+          s[m] = e[m] & kStateMask;
+          if (e[m] & kFinalBit) {
+            const OutEntry o = p.out[s[m]];
+            best[m] = o.pid;
+            occ[m] += o.mult;
+          }
+          ++q[m];
+        }
+        any = true;
+      }
+      if (!any) break;
     }
-    ++q;
+    // results: dense output, hit slot, tile counts
+    #pragma unroll
+    for (int m = 0; m < M; ++m) {
+      if (!valid[m] || (!best[m] && !occ[m])) continue;
+      int32_t* match;
+      uint64_t gt;
+      if (SINGLE) {
+        match = p.match;
+        gt = pos[m] / TILE;
+      } else {
+        const DevSeg sg = p.segs[si[m]];
+        match = p.match ? p.match + sg.match_off : nullptr;
+        gt = (uint64_t)sg.first_tile + pos[m] / TILE;
+      }
+      if (best[m]) {
+        if (match) match[pos[m]] = best[m];
+        const uint32_t slot = atomicAdd(&p.tile_hits[gt], 1u);
+        if (p.slots && slot < kSlot) p.slots[gt * kSlot + slot] = Slot{pos[m], best[m]};
+      }
+      if (occ[m]) atomicAdd(&p.tile_occ[gt], occ[m]);
+    }
   }
-  if (best) {
-    if (match) match[pos] = best;
-    const uint32_t slot = atomicAdd(&p.tile_hits[gt], 1u);
-    if (p.slots && slot < kSlot) p.slots[gt * kSlot + slot] = Slot{pos, best};
-  }
-  if (occ) atomicAdd(&p.tile_occ[gt], occ);
 }
 
 // Zero dense output of a whole tile of nt positions (mt 16-byte aligned or
@@ -1258,8 +1320,7 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
       // go over the zeros and counts stored above, so those stores complete
       // first
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-      #pragma unroll 1
-      for (uint32_t j = lane; j < wq_n; j += 64) deferred_walk<D, SINGLE, TILE>(p, wq[j]);
+      deferred_walks<D, SINGLE, TILE>(p, wq, wq_n);
     }
   }
 }
