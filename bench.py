@@ -553,19 +553,23 @@ def part_floor(pf, torch, args):
     del b
     lib = ctypes.CDLL(B.PROBE_LIB)
     lib.pfac_probe_stream.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64,
-                                      ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p,
-                                      ctypes.c_void_p]
+                                      ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32,
+                                      ctypes.c_void_p, ctypes.c_void_p]
     lib.pfac_probe_stream.restype = ctypes.c_int
     n = 256 << 20                              # the large-text scan's shape: 256 Mbase
     src = a[:n]
     dst = torch.empty(n, dtype=torch.int32, device=dev)
     sink = torch.zeros(4, dtype=torch.int32, device=dev)
     tiles = n // 2048
-    for mode, name, bytes_ in ((0, "scan_shape_read_256MB_write_1GiB", 5 * n),
-                               (1, "scan_shape_read_only_256MB", n),
-                               (2, "scan_shape_write_only_1GiB", 4 * n)):
-        fn = lambda: lib.pfac_probe_stream(src.data_ptr(), dst.data_ptr(), tiles, mode, 0,
-                                           sink.data_ptr(),
+    cases = [(0, 0, 0, "scan_shape_read_256MB_write_1GiB", 5 * n),
+             (1, 0, 0, "scan_shape_read_only_256MB", n),
+             (2, 0, 0, "scan_shape_write_only_1GiB", 4 * n),
+             (0, 1, 0, "scan_shape_plain_stores", 5 * n),
+             (0, 2, 0, "scan_shape_plain_loads", 5 * n),
+             (0, 0, 512, "scan_shape_2_workgroups_per_cu", 5 * n)]
+    for mode, flags, grid, name, bytes_ in cases:
+        fn = lambda: lib.pfac_probe_stream(src.data_ptr(), dst.data_ptr(), tiles, mode, flags,
+                                           grid, sink.data_ptr(),
                                            torch.cuda.current_stream().cuda_stream)
         assert fn() == 0
         warm_clock(torch, fn)
@@ -692,6 +696,9 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="let the autotuner pick the plans of the packed and batched workloads")
     ap.add_argument("--requests", type=int, default=600, help="served requests")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (the reference of the HBM "
+                         "traffic counters)")
     ap.add_argument("--paper-ladder", action="store_true",
                     help="instead: the paper's placement ladder on paper-shaped pattern and "
                          "read sets (prints one JSON line per case and a table)")
@@ -721,6 +728,13 @@ def main():
         return
 
     torch.cuda.set_device(torch.device("cuda:0"))
+    if args.calibrate_copy:
+        a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     plan = json.loads(args.plan) if args.plan else None
     parts = PARTS if args.only is None else (args.only,)
     extra = {}
