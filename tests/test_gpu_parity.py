@@ -182,7 +182,7 @@ def test_default_plan_uses_second_filter_when_patterns_are_long():
     short = pf.Table([b"ACG"] + W.random_patterns(100, 16, 40, W.rng(80)))
     assert short.default_plan(1 << 20)["hash_bits"] == pf.PFAC_HASH_NONE
     with pytest.raises(pf.PfacError):
-        pf.match(tab, torch.zeros(64, dtype=torch.uint8, device=DEV), plan=dict(hash_bits=19))
+        pf.match(tab, torch.zeros(64, dtype=torch.uint8, device=DEV), plan=dict(hash_bits=21))
 
 
 def test_edge_sizes_and_ragged_tails():
