@@ -44,7 +44,7 @@ def _mixed_texts(g, pool):
             + [int(x) for x in g.integers(5000, 400_000, size=12)] + [3_000_017, 0, 1, 15, 17])
     texts = []
     for L in lens:
-        if L and g.random() < 0.5:      # cut from the pattern pool: plenty of matches
+        if L and L < pool.size and g.random() < 0.5:   # cut from the pool: plenty of matches
             o = int(g.integers(0, pool.size - L))
             texts.append(pool[o:o + L].copy())
         else:
