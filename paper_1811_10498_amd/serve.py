@@ -501,6 +501,19 @@ class Server:
     def idle(self) -> bool:
         return not (self.gate.queue or self.admitted or self.inflight)
 
+    def device_intervals(self) -> List[tuple]:
+        """With ``trace``: per dispatch (stream index, start ms, end ms,
+        requests), times on the device clock from the earliest dispatch start,
+        sorted by start.  Call once the dispatches have completed."""
+        if not self.trace:
+            return []
+        torch.cuda.synchronize(self.device)
+        ref = self.trace[0][1]
+        rows = [(si, ref.elapsed_time(a), ref.elapsed_time(b), k) for si, a, b, k in self.trace]
+        lo = min(r[1] for r in rows)
+        out = [(si, a - lo, b - lo, k) for si, a, b, k in rows]
+        return sorted(out, key=lambda x: x[1])
+
     # ------------------------------------------------------------ driver
     def run(self, requests: Sequence[Request], poll_s: float = 20e-6) -> dict:
         """Feed requests at their arrival times (seconds from now) and serve
