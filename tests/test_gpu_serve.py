@@ -120,10 +120,13 @@ def test_dispatches_overlap_on_the_device():
     tries = W.served_tries(seed=5, sizes=[2000, 3000], pool_bases=500_000)
     tables = [pf.Table(t) for t in tries]
     pool = torch.from_numpy(W.uniform_ascii(64 << 20, W.rng(11))).to(DEV)
-    reqs = [Request(i, i % 2, [pool[(i % 4) * (16 << 20):(i % 4) * (16 << 20) + (12 << 20)]], 0.0)
+    # 48 Mbase per request, matched by the paper's global-memory kernel (about
+    # a millisecond each): longer on the device than a dispatch takes on the
+    # host, so later dispatches start while earlier ones run
+    reqs = [Request(i, i % 2, [pool[(i % 4) * (4 << 20):(i % 4) * (4 << 20) + (48 << 20)]], 0.0)
             for i in range(8)]
-    srv = Server(tables, budget_bytes=8 << 30, streams=4, max_dispatch_bases=12 << 20,
-                 trace=True)
+    srv = Server(tables, budget_bytes=8 << 30, streams=4, max_dispatch_bases=48 << 20,
+                 trace=True, plan=dict(variant=pf.PFAC_VARIANT_GLOBAL))
     srv.run(reqs)
     iv = srv.device_intervals()
     print("dispatch intervals (stream, ms, ms, requests):",
