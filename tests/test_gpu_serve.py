@@ -162,7 +162,10 @@ def test_table_update_while_serving():
               for i in range(4)]
     srv.run(second)
     for r in srv.done:
-        tab = old if r.rid < 10 else new
+        if r.table == 1:
+            tab = tables[1]
+        else:
+            tab = old if r.rid < 10 else new
         alone = pf.match(tab, r.text(0), hit_cap=hit_cap_of(r.lengths))
         torch.cuda.synchronize()
         assert torch.equal(r.result.text_match(0), alone.match), r.rid
