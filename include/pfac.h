@@ -257,6 +257,34 @@ int pfac_match(const pfac_table* table, const void* d_text, uint64_t n, int enc,
                const pfac_plan* plan, void* stream);
 
 /*
+ * pfac_match for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops that must not call hipMalloc, harnesses that
+ * forbid it).  Same arguments, kernels and results as pfac_match; the
+ * scratch (per-tile counts and hit slots, look-back words, deferred walks)
+ * lives in a fixed device array inside the library, pfac_noalloc_scratch_bytes()
+ * bytes (64 MiB) per GPU, held from the library's load until the process
+ * ends.  The call allocates nothing, copies nothing from the host and issues
+ * no memset: it enqueues a small fill kernel that clears the array's
+ * look-back words, then the scan and finish kernels.
+ *   Returns PFAC_E_SCRATCH, before anything is enqueued, when the text needs
+ *   more scratch than the array holds: 268 bytes per tile of 2048 positions
+ *   plus 32 bytes per deferred-walk entry, so between about 100 Mbase (plans
+ *   that defer many walks) and 500 Mbase (walks at once); pfac_match has no
+ *   such limit.  PFAC_E_ARG for
+ *   byte-alphabet tables and for the paper's two-array and merged-cell
+ *   layouts before pfac_match has built them.
+ * Every call on one GPU shares that GPU's array and overwrites it: calls that
+ * overlap on one GPU (two streams, two host threads) race and give wrong
+ * results; the caller serialises them.
+ */
+int pfac_match_noalloc(const pfac_table* table, const void* d_text, uint64_t n, int enc,
+                       int32_t* d_match, pfac_hit* d_hits, uint64_t hit_cap,
+                       uint64_t* d_counters, const pfac_plan* plan, void* stream);
+
+/* Size in bytes of the fixed scratch array of pfac_match_noalloc. */
+uint64_t pfac_noalloc_scratch_bytes(void);
+
+/*
  * Every occurrence of every pattern in one text: all pairs (start position,
  * pattern ID) with the pattern starting there, including the shorter
  * patterns PFAC's own report leaves out at a position where a longer one
