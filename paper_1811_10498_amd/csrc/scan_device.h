@@ -592,8 +592,8 @@ __device__ __forceinline__ uint32_t gather4(const TextRef& r, uint64_t g) {
 }
 
 // 2-bit chunk c (64 bases) -> four code words and 64 invalid bits.
-__device__ __forceinline__ void commit_2bit_chunk(const TextRef& r, uint32_t c, bool loaded,
-                                                  const u32x4& v, uint32_t* pk, uint32_t* iv) {
+__device__ __forceinline__ uint32_t commit_2bit_chunk(const TextRef& r, uint32_t c, bool loaded,
+                                                      const u32x4& v, uint32_t* pk, uint32_t* iv) {
   uint16_t* iv16 = reinterpret_cast<uint16_t*>(iv);
   uint32_t w[4] = {v.x, v.y, v.z, v.w};
   uint32_t inv[4] = {0, 0, 0, 0};
@@ -618,6 +618,7 @@ __device__ __forceinline__ void commit_2bit_chunk(const TextRef& r, uint32_t c, 
     pk[4 * c + k] = ((rv >> 1) & 0x55555555u) | ((rv & 0x55555555u) << 1);
     iv16[4 * c + k] = (uint16_t)inv[k];
   }
+  return inv[0] | inv[1] | inv[2] | inv[3];
 }
 
 // Convert the prefetched text of a tile into the wave's LDS area.  ASCII:
@@ -625,21 +626,24 @@ __device__ __forceinline__ void commit_2bit_chunk(const TextRef& r, uint32_t c, 
 // in 4-byte pieces, one per lane (one byte of codes and four invalid bits
 // each; two neighbouring lanes join their invalid bits into one byte).
 template <uint32_t TILE>
-__device__ __forceinline__ void commit(const TextRef& r, uint32_t halo, const Prefetch& f,
+__device__ __forceinline__ bool commit(const TextRef& r, uint32_t halo, const Prefetch& f,
                                        uint32_t* pk, uint32_t* iv) {
   const uint32_t lane = fresh_lane();
   const uint32_t span = TILE + halo;
+  uint32_t any_inv = 0;     // invalid bits this lane staged
   if (r.enc == PFAC_TEXT_ASCII) {
     uint32_t packed, inv;
     if (TILE >= 1024 || lane < TILE / 16) {
       ascii_chunk((f.fast & 1u) ? f.a : gather16(r, r.t0 + 16ull * lane), packed, inv);
       pk[lane] = packed;
       reinterpret_cast<uint16_t*>(iv)[lane] = (uint16_t)inv;
+      any_inv |= inv;
     }
     if (TILE == 2048) {
       ascii_chunk((f.fast & 2u) ? f.b : gather16(r, r.t0 + 1024 + 16ull * lane), packed, inv);
       pk[64 + lane] = packed;
       reinterpret_cast<uint16_t*>(iv)[64 + lane] = (uint16_t)inv;
+      any_inv |= inv;
     }
     uint8_t* pk8 = reinterpret_cast<uint8_t*>(pk);
     uint8_t* iv8 = reinterpret_cast<uint8_t*>(iv);
@@ -655,17 +659,19 @@ __device__ __forceinline__ void commit(const TextRef& r, uint32_t halo, const Pr
         // bases TILE+4pc .. +3: byte 3 - (pc & 3) of code word TILE/16 + pc/4
         pk8[4 * (TILE / 16 + (pc >> 2)) + 3 - (pc & 3)] = (uint8_t)code8;
         if (!(pc & 1u)) iv8[(TILE + 4 * pc) / 8] = (uint8_t)(inv4 | (other << 4));
+        any_inv |= inv4;
       }
     }
   } else {
     const uint32_t nch = span / 64;
-    if (lane < nch) commit_2bit_chunk(r, lane, f.fast & 1u, f.a, pk, iv);
-    if (lane + 64 < nch) commit_2bit_chunk(r, lane + 64, f.fast & 2u, f.b, pk, iv);
+    if (lane < nch) any_inv |= commit_2bit_chunk(r, lane, f.fast & 1u, f.a, pk, iv);
+    if (lane + 64 < nch) any_inv |= commit_2bit_chunk(r, lane + 64, f.fast & 2u, f.b, pk, iv);
   }
   if (lane < 2) {
     pk[span / 16 + lane] = 0;
     iv[span / 32 + lane] = 0xFFFFFFFFu;
   }
+  return any_inv != 0;
 }
 
 // LDS of one wave, in 32-bit words, each part a multiple of 4 words so the
@@ -991,6 +997,10 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
                                                     (hashed ? p.hash_words : 0u));
 
   const uint32_t dmask = (1u << D) - 1u;
+  // windows with a non-base among their first D bases: they walk from the
+  // root (keep_slow all ones) or, when every pattern is longer than D,
+  // report nothing (keep_slow 0)
+  const uint32_t keep_slow = (GLOBAL || p.longer) ? 0u : 0xFu;
   const uint32_t gmask = (1u << (D + 3)) - 1u;   // bases of the 4 windows of a group
   // byte selector of the 4 bases the lane's group starts at within a pair of
   // code words {first, second}: bytes 7-k .. 4-k of the pair, k = lane & 3
@@ -1040,8 +1050,9 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
     int32_t* mt = p.match ? seg_match(cur) + t0 : nullptr;
     const bool maligned = mt && ((reinterpret_cast<uintptr_t>(mt) & 15) == 0);
 
+    bool dirty = true;   // this lane staged a non-base (or a base past the text)
     if (!GLOBAL) {
-      commit<TILE>(TextRef{text, n, t0, enc}, p.halo, pf, pk, iv);
+      dirty = commit<TILE>(TextRef{text, n, t0, enc}, p.halo, pf, pk, iv);
       wave_sync();
     }
     // next tile: take it, locate it and start loading its text now.  Local
@@ -1067,54 +1078,90 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
       cpend = false;
     }
 
-    // ---- classify the lane's 4*NG positions: bit 4g+r of want / slow
+    // ---- classify the lane's 4*NG positions: bit 4g+r of want / slow.
+    //      A full tile whose staged bases are all A/C/G/T (the common case)
+    //      takes the short path: one bitmap bit per window, nothing else.
     uint32_t want = 0, slow = 0;
-    #pragma unroll
-    for (uint32_t g = 0; g < NG; ++g) {
-      const uint32_t q0 = g * 256 + 4 * lane;
-      const uint32_t vmask =
-          full ? 0xFu : (q0 >= nt ? 0u : (nt - q0 >= 4 ? 0xFu : (1u << (nt - q0)) - 1u));
-      uint32_t m4 = 0, s4 = 0;
-      if (GLOBAL) {
-        m4 = s4 = vmask;
-      } else {
-        const uint32_t wi = q0 >> 4, ii = q0 >> 5;
-        // 16 bases from q0, first base in the top bits
-        const uint32_t w = __builtin_amdgcn_perm(pk[wi], pk[wi + 1], bsel);
-        const uint32_t inv = __builtin_amdgcn_alignbit(iv[ii + 1], iv[ii], sh4);
-        // window key x_r = bits [o_r, o_r+2D) of w, o_r = 32-2r-2D: its
-        // bitmap word is bits [o_r+5, o_r+2D) (read at byte offset 4x that)
-        // and its bit within the word bits [o_r, o_r+5) (a bit-field offset
-        // uses the low 5 bits of its operand).  All four reads are issued
-        // before the first is used.
-        uint32_t word[4];
+    // bit-field offset of window r's bit within its bitmap word, and the word
+    // address: window key x_r = bits [o_r, o_r+2D) of w, o_r = 32-2r-2D; the
+    // word is bits [o_r+5, o_r+2D) (read at byte offset 4x that), the bit
+    // bits [o_r, o_r+5) (a bit-field offset uses the low 5 bits of its
+    // operand).  All four reads of a group are issued before the first is used.
+    constexpr uint32_t DL = GLOBAL ? kMinJump : D;      // (unused by the global variants)
+    auto lookup4 = [&](uint32_t w) -> uint32_t {
+      uint32_t word[4];
+      #pragma unroll
+      for (uint32_t r = 0; r < 4; ++r) {
+        const uint32_t o = 32 - 2 * r - 2 * DL;
+        word[r] = lds_word((w >> (o + 3)) & (((1u << (2 * DL - 5)) - 1u) << 2));
+      }
+      uint32_t m4 = 0;
+      #pragma unroll
+      for (uint32_t r = 0; r < 4; ++r)
+        m4 |= __builtin_amdgcn_ubfe(word[r], w >> (32 - 2 * r - 2 * DL), 1u) << r;
+      return m4;
+    };
+    if (!GLOBAL && __builtin_amdgcn_readfirstlane((uint32_t)(__ballot(dirty) != 0)) == 0) {
+      // every group's 16 bases (from q0, first base in the top bits) first,
+      // then the bitmap words of two groups at a time
+      uint32_t wv[NG];
+      #pragma unroll
+      for (uint32_t g = 0; g < NG; ++g) {
+        const uint32_t wi = (g * 256 + 4 * lane) >> 4;
+        wv[g] = __builtin_amdgcn_perm(pk[wi], pk[wi + 1], bsel);
+      }
+      constexpr uint32_t GS = NG >= 2 ? 2u : 1u;   // groups per batch of reads
+      #pragma unroll
+      for (uint32_t g = 0; g < NG; g += GS) {
+        uint32_t word[4 * GS];
         #pragma unroll
-        for (uint32_t r = 0; r < 4; ++r) {
-          const uint32_t o = 32 - 2 * r - 2 * D;
-          word[r] = lds_word((w >> (o + 3)) & (((1u << (2 * D - 5)) - 1u) << 2));
+        for (uint32_t k = 0; k < 4 * GS; ++k) {
+          const uint32_t o = 32 - 2 * (k & 3) - 2 * DL;
+          word[k] = lds_word((wv[g + (k >> 2)] >> (o + 3)) & (((1u << (2 * DL - 5)) - 1u) << 2));
         }
         #pragma unroll
-        for (uint32_t r = 0; r < 4; ++r)
-          m4 |= __builtin_amdgcn_ubfe(word[r], w >> (32 - 2 * r - 2 * D), 1u) << r;
-        if (inv & gmask) {
-          // a window holds a non-base (or runs past the text): such
-          // positions walk from the root -- or, when every pattern is longer
-          // than D, report nothing (no pattern fits before the non-base)
-          #pragma unroll
-          for (uint32_t r = 0; r < 4; ++r)
-            if ((inv >> r) & dmask) s4 |= 1u << r;
-          if (p.longer) {
-            m4 &= ~s4;
-            s4 = 0;
-          } else {
-            m4 |= s4;
+        for (uint32_t k = 0; k < 4 * GS; ++k)
+          want |= __builtin_amdgcn_ubfe(word[k], wv[g + (k >> 2)] >> (32 - 2 * (k & 3) - 2 * DL),
+                                        1u) << (4 * g + k);
+      }
+    } else {
+      // positions of the lane inside the text: all of them in a full tile
+      uint32_t valid = 0xFFFFFFFFu >> (32 - 4 * NG);
+      if (!full) {
+        valid = 0;
+        #pragma unroll
+        for (uint32_t g = 0; g < NG; ++g) {
+          const int32_t left = (int32_t)nt - (int32_t)(g * 256 + 4 * lane);
+          valid |= ((1u << (uint32_t)min(max(left, 0), 4)) - 1u) << (4 * g);
+        }
+      }
+      #pragma unroll
+      for (uint32_t g = 0; g < NG; ++g) {
+        const uint32_t q0 = g * 256 + 4 * lane;
+        uint32_t m4 = 0xFu, s4 = 0xFu;
+        if (!GLOBAL) {
+          const uint32_t wi = q0 >> 4, ii = q0 >> 5;
+          const uint32_t w = __builtin_amdgcn_perm(pk[wi], pk[wi + 1], bsel);
+          const uint32_t inv = __builtin_amdgcn_alignbit(iv[ii + 1], iv[ii], sh4);
+          m4 = lookup4(w);
+          s4 = 0;
+          if (inv & gmask) {
+            // a window holds a non-base (or runs past the text): such
+            // positions walk from the root -- or, when every pattern is
+            // longer than D, report nothing (no pattern fits before the
+            // non-base): keep_slow is 0 then, else all ones
+            #pragma unroll
+            for (uint32_t r = 0; r < 4; ++r)
+              if ((inv >> r) & dmask) s4 |= 1u << r;
+            m4 = (m4 & ~s4) | (s4 & keep_slow);
+            s4 &= keep_slow;
           }
         }
-        m4 &= vmask;
-        s4 &= vmask;
+        want |= m4 << (4 * g);
+        slow |= s4 << (4 * g);
       }
-      want |= m4 << (4 * g);
-      slow |= s4 << (4 * g);
+      want &= valid;
+      slow &= valid;
     }
 
     // ---- queue the surviving positions (lane order, then position order):
@@ -1144,7 +1191,26 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
       //      that must walk on, listed in queue2.  Up to four entries per
       //      lane at once, so their prefix-bitmap reads are in flight together
       uint32_t nwalk = ptotal;
-      if (hashed || pfxon) {
+      if (hashed && !pfxon) {
+        // second filter alone: one entry per lane at a time
+        nwalk = 0;
+        #pragma unroll 1
+        for (uint32_t i0 = 0; i0 < ptotal; i0 += 64) {
+          const uint32_t i = i0 + lane;
+          bool go = false;
+          if (i < ptotal) {
+            res[i] = 0;
+            go = hash_pass(queue[i], pk, iv, hl, p.hash_kmask, p.hash_imask, p.hash_shift);
+          }
+          const uint64_t m = __ballot(go);
+          if (go)
+            queue2[nwalk + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] =
+                (uint16_t)i;
+          nwalk += (uint32_t)__popcll(m);
+        }
+        wave_sync();
+      } else if (pfxon) {
         nwalk = 0;
         #pragma unroll 1
         for (uint32_t i0 = 0; i0 < ptotal; i0 += 256) {
