@@ -336,7 +336,8 @@ def part_c2(pf, torch, args, plan, tune=False):
                            "candidates": len(tr.tried)}
         del tab0, text0
     use = tuned if tuned is not None else plan
-    for dense in (True, False):
+    kinds = {"both": (True, False), "dense": (True,), "hits": (False,)}[args.c2_output]
+    for dense in kinds:
         st, table, _, _ = bench_one(pf, torch, w, use, args.steps, args.warmup, dense=dense)
         alg = alg_bytes_one(w.n, w.enc, st["hits"], table.num_states, dense=dense)
         key = "dense" if dense else "hits_only"
@@ -696,6 +697,8 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="let the autotuner pick the plans of the packed and batched workloads")
     ap.add_argument("--requests", type=int, default=600, help="served requests")
+    ap.add_argument("--c2-output", default="both", choices=("both", "dense", "hits"),
+                    help="outputs timed on the packed workload (profiling runs take one)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (the reference of the HBM "
                          "traffic counters)")

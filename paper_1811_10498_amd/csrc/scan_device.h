@@ -937,8 +937,37 @@ __device__ __forceinline__ bool pfx_locate(uint32_t e, const uint32_t* __restric
 // q = g*256 + 4*lane + r.  Positions whose walk goes on past the filters are
 // queued and walked by all lanes together (or kept for the end of the wave);
 // their results come back through a result slot per queue entry.
+// A uniform pointer copied into vector registers.  The scan keeps its
+// per-tile state in scalar registers; the table pointers the rare paths use
+// (walks, filters, hit slots) would otherwise hold scalar registers across
+// the tile loop and push that state out into spill lanes.
+template <typename T>
+__device__ __forceinline__ T* in_vgpr(T* ptr) {
+  const uint64_t x = reinterpret_cast<uint64_t>(ptr);
+  uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+  asm volatile("v_mov_b32 %0, %1" : "=v"(lo) : "s"(lo));
+  asm volatile("v_mov_b32 %0, %1" : "=v"(hi) : "s"(hi));
+  return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
+}
+
 template <int BLOCK, bool GLOBAL, int DT, bool SINGLE, bool DEFER, uint32_t TILE>
-__global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
+__global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p0) {
+  ScanParams p = p0;
+  p.next = in_vgpr(p0.next);
+  p.out = in_vgpr(p0.out);
+  p.chain = in_vgpr(p0.chain);
+  p.jump = in_vgpr(p0.jump);
+  p.jres = in_vgpr(p0.jres);
+  p.pfx = in_vgpr(p0.pfx);
+  p.slots = in_vgpr(p0.slots);
+  p.tile_hits = in_vgpr(p0.tile_hits);
+  p.tile_occ = in_vgpr(p0.tile_occ);
+  p.wq = in_vgpr(p0.wq);
+  if (GLOBAL) {
+    p.next2 = in_vgpr(p0.next2);
+    p.cell_pid = in_vgpr(p0.cell_pid);
+    p.cells = in_vgpr(p0.cells);
+  }
   extern __shared__ uint32_t lds[];
   // the wave index is uniform across the wave: keep it (and every tile
   // index and text offset derived from it) in scalar registers
@@ -1191,65 +1220,75 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p) {
       //      that must walk on, listed in queue2.  Up to four entries per
       //      lane at once, so their prefix-bitmap reads are in flight together
       uint32_t nwalk = ptotal;
-      if (hashed && !pfxon) {
-        // second filter alone: one entry per lane at a time
-        nwalk = 0;
-        #pragma unroll 1
-        for (uint32_t i0 = 0; i0 < ptotal; i0 += 64) {
-          const uint32_t i = i0 + lane;
-          bool go = false;
-          if (i < ptotal) {
-            res[i] = 0;
-            go = hash_pass(queue[i], pk, iv, hl, p.hash_kmask, p.hash_imask, p.hash_shift);
-          }
-          const uint64_t m = __ballot(go);
-          if (go)
-            queue2[nwalk + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] =
-                (uint16_t)i;
-          nwalk += (uint32_t)__popcll(m);
-        }
-        wave_sync();
-      } else if (pfxon) {
-        nwalk = 0;
-        #pragma unroll 1
-        for (uint32_t i0 = 0; i0 < ptotal; i0 += 256) {
-          bool go[4];
-          uint32_t pw[4], pb[4];
-          #pragma unroll
-          for (uint32_t r = 0; r < 4; ++r) {
-            const uint32_t i = i0 + 64 * r + lane;
-            go[r] = false;
-            pw[r] = 0;
-            pb[r] = 0;
+      if (hashed || pfxon) {
+        // second filter (LDS): one queue entry per lane at a time; the
+        // entries that pass are listed in queue2
+        uint32_t nh = ptotal;
+        if (hashed) {
+          nh = 0;
+          #pragma unroll 1
+          for (uint32_t i0 = 0; i0 < ptotal; i0 += 64) {
+            const uint32_t i = i0 + lane;
+            bool go = false;
             if (i < ptotal) {
               res[i] = 0;
-              const uint32_t e = queue[i];
-              go[r] = !hashed ||
-                      hash_pass(e, pk, iv, hl, p.hash_kmask, p.hash_imask, p.hash_shift);
-              if (pfxon && go[r]) {
+              go = hash_pass(queue[i], pk, iv, hl, p.hash_kmask, p.hash_imask, p.hash_shift);
+            }
+            const uint64_t m = __ballot(go);
+            if (go)
+              queue2[nh + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] =
+                  (uint16_t)i;
+            nh += (uint32_t)__popcll(m);
+          }
+          wave_sync();
+        }
+        nwalk = nh;
+        if (pfxon) {
+          // prefix filter (global): the candidates (queue2, or every queue
+          // entry without a second filter) read their prefix bit, up to four
+          // per lane in flight; those whose bit is set are listed in queue2
+          // again, in place (an iteration reads its entries before it writes
+          // the list, which never runs ahead of the reads)
+          nwalk = 0;
+          #pragma unroll 1
+          for (uint32_t i0 = 0; i0 < nh; i0 += 256) {
+            bool go[4];
+            uint32_t idx[4], pw[4], pb[4];
+            #pragma unroll
+            for (uint32_t r = 0; r < 4; ++r) {
+              const uint32_t j = i0 + 64 * r + lane;
+              go[r] = false;
+              idx[r] = j;
+              pw[r] = 0;
+              pb[r] = 0;
+              if (j < nh) {
+                if (hashed) {
+                  idx[r] = queue2[j];
+                } else {
+                  res[j] = 0;
+                }
                 uint32_t wd, bt;
-                go[r] = pfx_locate(e, pk, iv, p.pfx_shift, p.pfx_imask, &wd, &bt);
+                go[r] = pfx_locate(queue[idx[r]], pk, iv, p.pfx_shift, p.pfx_imask, &wd, &bt);
                 if (go[r]) {
                   pw[r] = p.pfx[wd];
                   pb[r] = bt;
                 }
               }
             }
+            #pragma unroll
+            for (uint32_t r = 0; r < 4; ++r) {
+              const bool g2 = go[r] && ((pw[r] >> pb[r]) & 1u);
+              const uint64_t m = __ballot(g2);
+              if (g2)
+                queue2[nwalk + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] =
+                    (uint16_t)idx[r];
+              nwalk += (uint32_t)__popcll(m);
+            }
           }
-          #pragma unroll
-          for (uint32_t r = 0; r < 4; ++r) {
-            const uint32_t i = i0 + 64 * r + lane;
-            const bool g2 = go[r] && (!pfxon || ((pw[r] >> pb[r]) & 1u));
-            const uint64_t m = __ballot(g2);
-            if (g2)
-              queue2[nwalk + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                       __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] =
-                  (uint16_t)i;
-            nwalk += (uint32_t)__popcll(m);
-          }
+          wave_sync();
         }
-        wave_sync();
       }
       const bool listed = hashed || pfxon;
       // ---- launches with deferred walks keep them for the end of the
