@@ -121,7 +121,7 @@ typedef struct {
   uint32_t tile;        /* start positions per wave tile: 1024 or 2048 (one-text and
                            batched calls), 256 (batched calls only).  0 = library
                            choice: 2048 for one text; in a batch 256 for texts of at
-                           most 512 bases and 1024 for longer ones (an explicit
+                           most 512 bases and 2048 for longer ones (an explicit
                            value applies to every text of the batch) */
   uint32_t prefix;      /* prefix filter, used when every pattern is longer than D:
                            windows that pass the LDS filters are looked up in an exact
@@ -130,10 +130,17 @@ typedef struct {
                            only those whose K2-base prefix starts some pattern walk on.
                            0 = library choice (on when the hashed second filter is
                            off and K2 > D), PFAC_PREFIX_NONE = off, 1 = on */
+  uint32_t pair;        /* the depth-D filter as a pair table (D <= 9, no LDS trie
+                           levels): one byte per string m of D-1 bases holds the filter
+                           bits of the windows that start one base before m and at m,
+                           so one LDS read tests two neighbouring positions; it takes
+                           twice the LDS of the bitmap.  0 = library choice (on when it
+                           fits), 1 = on, PFAC_PAIR_NONE = off */
 } pfac_plan;
 
 enum { PFAC_WALKS_INLINE = 1, PFAC_WALKS_DEFERRED = 2 };
 #define PFAC_PREFIX_NONE 0xFFFFFFFFu
+#define PFAC_PAIR_NONE 0xFFFFFFFFu
 
 /* Variants.  TILED: text tile in LDS, filters, deep walks (the library's).
  * GLOBAL: the paper's kernel (Sec. V.B): every position walks from the root,

@@ -19,6 +19,7 @@ PFAC_HASH_NONE = 0xFFFFFFFF
 PFAC_WALKS_INLINE = 1
 PFAC_WALKS_DEFERRED = 2
 PFAC_PREFIX_NONE = 0xFFFFFFFF
+PFAC_PAIR_NONE = 0xFFFFFFFF
 
 EXPORTS = (
     "pfac_build_table", "pfac_build_table_bytes", "pfac_build_table_device",
@@ -37,7 +38,7 @@ class PfacPlan(ctypes.Structure):
                 ("grid", ctypes.c_uint32), ("variant", ctypes.c_uint32),
                 ("levels", ctypes.c_uint32), ("hash_bits", ctypes.c_uint32),
                 ("walks", ctypes.c_uint32), ("tile", ctypes.c_uint32),
-                ("prefix", ctypes.c_uint32)]
+                ("prefix", ctypes.c_uint32), ("pair", ctypes.c_uint32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}

@@ -607,7 +607,7 @@ static int device_build(pfac_table* t, const char* const* patterns, const uint32
   for (uint32_t b = kHashMinBits; b <= kHashMaxBits; ++b)
     h.hash_set[b] = (uint32_t)hs[11 + (b - kHashMinBits)];
   h.pfx_set = L.pfx_words ? hs[30] : 0;
-  return PFAC_OK;
+  return build_pairs(t);
 }
 
 // Check, then build on the device; pattern k gets ID ids[k].

@@ -334,6 +334,26 @@ __global__ __launch_bounds__(256) void pfac_cells_kernel(const uint32_t* next, c
   }
 }
 
+// Pair table of depth D from the depth-D filter bitmap: four strings m per
+// thread (one 32-bit word of the table).
+__global__ __launch_bounds__(256) void pfac_pair_kernel(const uint32_t* bitmap, uint32_t D,
+                                                        uint32_t* pair) {
+  const uint32_t nm = 1u << (2 * (D - 1));
+  const uint32_t hi = 2 * (D - 1);
+  auto bit = [&](uint32_t x) { return (bitmap[x >> 5] >> (x & 31u)) & 1u; };
+  for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < nm / 4; i += gridDim.x * 256) {
+    uint32_t word = 0;
+    for (uint32_t k = 0; k < 4; ++k) {
+      const uint32_t m = 4 * i + k;
+      uint32_t e = 0;
+      for (uint32_t a = 0; a < 4; ++a) e |= bit((a << hi) | m) << a;
+      for (uint32_t b = 0; b < 4; ++b) e |= bit((m << 2) | b) << (4 + b);
+      word |= e << (8 * k);
+    }
+    pair[i] = word;
+  }
+}
+
 // Batch work items: one wave per text writes the items of its tiles,
 // {text index, tile index within the text}, from item_start[text] on.
 __global__ __launch_bounds__(256) void pfac_items_kernel(const DevSeg* segs,
@@ -617,7 +637,7 @@ constexpr int kNoFit = 1;
 // bare filter bitmap.  Sets p->levels on success; kNoFit when it does not fit.
 static int place_image(const HostTable& h, uint32_t D, uint32_t hw, uint32_t halo,
                        uint32_t budget, uint32_t tile, pfac_plan* p) {
-  if (h.min_len > D && p->levels != PFAC_LEVELS_NONE) {
+  if (h.min_len > D && p->levels != PFAC_LEVELS_NONE && p->pair != 1) {
     const uint32_t have = h.image[D].levels;
     const uint32_t want = p->levels == 0 ? have : std::min(p->levels, have);
     for (int32_t L = (int32_t)want; L >= 0; --L) {
@@ -625,14 +645,28 @@ static int place_image(const HostTable& h, uint32_t D, uint32_t hw, uint32_t hal
           budget) {
         if (p->levels != 0 && (uint32_t)L < want) return kNoFit;   // explicit, too big
         p->levels = (uint32_t)L;
+        p->pair = PFAC_PAIR_NONE;
         return PFAC_OK;
       }
     }
     if (p->levels != 0) return kNoFit;
   }
-  // filter bitmap only; survivors read the global depth-D jump table
-  if (scan_lds_bytes(p->block, image_words(h, D, false, 0) + hw, halo, tile) <= budget) {
+  if (p->levels != PFAC_LEVELS_NONE && p->levels != 0) return kNoFit;   // levels asked for
+  // filter bitmap only (or its pair table); survivors read the global
+  // depth-D jump table
+  const uint32_t bits = image_words(h, D, false, 0);
+  if (p->pair != PFAC_PAIR_NONE && D <= kPairMaxDepth) {
+    if (scan_lds_bytes(p->block, 2 * bits + hw, halo, tile) <= budget) {
+      p->levels = PFAC_LEVELS_NONE;
+      p->pair = 1;
+      return PFAC_OK;
+    }
+    if (p->pair == 1) return kNoFit;             // explicit, does not fit
+  }
+  if (p->pair == 1) return kNoFit;               // no pair table at this depth
+  if (scan_lds_bytes(p->block, bits + hw, halo, tile) <= budget) {
     p->levels = PFAC_LEVELS_NONE;
+    p->pair = PFAC_PAIR_NONE;
     return PFAC_OK;
   }
   return kNoFit;
@@ -645,7 +679,8 @@ static int resolve_plan(const pfac_plan* in, const HostTable& h, int dev, bool s
                         pfac_plan* out) {
   const DeviceInfo di = device_info(dev);
   if (!di.ok) return PFAC_E_NODEV;
-  pfac_plan p = in ? *in : pfac_plan{0, 0, 0, 0, 0, 0, 0, 0, 0};
+  pfac_plan p = in ? *in : pfac_plan{0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  if (p.pair != 0 && p.pair != 1 && p.pair != PFAC_PAIR_NONE) return PFAC_E_ARG;
   if (p.variant != PFAC_VARIANT_TILED && !global_variant(p.variant)) return PFAC_E_ARG;
   if (!single && p.variant != PFAC_VARIANT_TILED && p.variant != PFAC_VARIANT_GLOBAL)
     return PFAC_E_ARG;
@@ -687,6 +722,7 @@ static int resolve_plan(const pfac_plan* in, const HostTable& h, int dev, bool s
     p.hash_bits = PFAC_HASH_NONE;
     p.walks = PFAC_WALKS_INLINE;
     p.prefix = PFAC_PREFIX_NONE;
+    p.pair = PFAC_PAIR_NONE;
     p.tile = single ? kTileSingle : kTileBatch;
     *out = p;
     return PFAC_OK;
@@ -867,6 +903,11 @@ static void fill_table(ScanParams& sp, const pfac_table* t, const pfac_plan& pl)
     sp.lds_trie = (h.min_len > D && pl.levels != PFAC_LEVELS_NONE) ? 1u : 0u;
     sp.levels = sp.lds_trie ? pl.levels : 0u;
     sp.image_words = image_words(h, D, sp.lds_trie, sp.levels);
+    if (pl.pair == 1 && !sp.lds_trie) {
+      sp.pair = 1;
+      sp.image = reinterpret_cast<const uint32_t*>(t->dev.pair[D]);
+      sp.image_words = 2 * image_words(h, D, false, 0);
+    }
     sp.lvl = reinterpret_cast<const u32x4*>(t->dev.levels[D]);
     if (pl.hash_bits != PFAC_HASH_NONE) {
       const uint32_t b = pl.hash_bits, K = h.hash_k;
@@ -876,6 +917,12 @@ static void fill_table(ScanParams& sp, const pfac_table* t, const pfac_plan& pl)
       sp.hash_shift = 32 - b;
       sp.hash_kmask = K >= 16 ? 0xFFFFFFFFu : ~((1u << (32 - 2 * K)) - 1u);
       sp.hash_imask = (1u << K) - 1u;
+      // when most windows pass the depth-D bitmap (large pattern sets), every
+      // window of a tile takes the second filter while it is classified
+      // instead of through the queue (its K bases then fit the 16 bases a
+      // group of four positions holds)
+      const double fill = (double)h.bitmap_set[D] / (double)(1ull << (2 * D));
+      sp.hash_cls = (K <= 12 && fill > 0.3) ? 1u : 0u;
     }
     if (pl.prefix == 1 && h.pfx_k > D) {
       sp.pfx_on = 1;
@@ -933,6 +980,10 @@ void table_layout(const HostTable& h, uint64_t ndups, TableLayout* L) {
       if (D + k < h.depth_start.size()) L->lvdesc[D][4 * k + 2] = (uint32_t)h.depth_start[D + k];
     }
     L->o_lv[D] = off; off = al256(off + L->lvdesc[D].size() * 4);
+    if (D <= kPairMaxDepth) {
+      L->o_pair[D] = off;
+      off = al256(off + (E >> 2));
+    }
   }
   for (uint32_t b = kHashMinBits; b <= kHashMaxBits; ++b) {
     L->hash_words[b] = h.hash_k ? (1u << b) / 32 : 0;
@@ -974,6 +1025,8 @@ int alloc_table(pfac_table* t, uint64_t ndups) {
     v.jump[D] = reinterpret_cast<const uint32_t*>(base + L.o_jump[D]);
     v.jres[D] = reinterpret_cast<const OutEntry*>(base + L.o_jres[D]);
     v.image[D] = reinterpret_cast<const uint32_t*>(base + L.o_im[D]);
+    v.pair[D] = D <= kPairMaxDepth ? reinterpret_cast<const uint8_t*>(base + L.o_pair[D])
+                                   : nullptr;
     if (hipMemcpy(base + L.o_lv[D], L.lvdesc[D].data(), L.lvdesc[D].size() * 4,
                   hipMemcpyHostToDevice) != hipSuccess)
       return PFAC_E_HIP;
@@ -1004,6 +1057,19 @@ int upload_host_table(pfac_table* t) {
   for (uint32_t b = kHashMinBits; b <= kHashMaxBits; ++b)
     ok = ok && put(L.o_hash[b], h.hash[b].data(), h.hash[b].size() * 4);
   return ok ? PFAC_OK : PFAC_E_HIP;
+}
+
+// The pair tables of a table whose filter bitmaps are in its device
+// allocation (either build), derived on the device; synchronous.
+int build_pairs(pfac_table* t) {
+  for (uint32_t D = kMinJump; D <= kPairMaxDepth; ++D) {
+    const uint32_t words = (1u << (2 * (D - 1))) / 4;
+    hipLaunchKernelGGL(pfac_pair_kernel, dim3((words + 255) / 256), dim3(256), 0, nullptr,
+                       t->dev.image[D], D, const_cast<uint32_t*>(
+                           reinterpret_cast<const uint32_t*>(t->dev.pair[D])));
+    if (hipGetLastError() != hipSuccess) return PFAC_E_HIP;
+  }
+  return hipDeviceSynchronize() == hipSuccess ? PFAC_OK : PFAC_E_HIP;
 }
 
 // Keep the pattern set (bytes and IDs) with the table, for updates.
@@ -1077,6 +1143,7 @@ int pfac_build_table(const char* const* patterns, const uint32_t* lengths, uint3
   rc = remember_patterns(t, patterns, lengths, num, nullptr);
   if (!rc) rc = alloc_table(t, t->host.dup_state.size());
   if (!rc) rc = upload_host_table(t);
+  if (!rc) rc = build_pairs(t);
   if (rc) {
     if (t->dmem) (void)hipFree(t->dmem);
     delete t;
@@ -1121,7 +1188,7 @@ int pfac_default_plan(const pfac_table* t, uint64_t n, int enc, pfac_plan* out) 
   if (t->alphabet != 4) {
     // byte tables have one kernel: 1024-thread workgroups, the grid by size
     *out = pfac_plan{1024, 0, 0, PFAC_VARIANT_GLOBAL, PFAC_LEVELS_NONE, PFAC_HASH_NONE,
-                     PFAC_WALKS_INLINE, 2048, PFAC_PREFIX_NONE};
+                     PFAC_WALKS_INLINE, 2048, PFAC_PREFIX_NONE, PFAC_PAIR_NONE};
     return enc == PFAC_TEXT_ASCII ? PFAC_OK : PFAC_E_ARG;
   }
   return resolve_plan(nullptr, t->host, t->device, true, out);
@@ -1293,7 +1360,10 @@ struct BatchLayout {
 static uint32_t text_tile(const pfac_plan& pl, uint64_t n) {
   if (global_variant(pl.variant)) return kTileBatch;
   if (pl.tile) return pl.tile;
-  return n <= kShortText ? kTileShort : kTileBatch;
+  // short texts: 256-position tiles (a 150-base read fills 59 % of one);
+  // longer ones 2048 like a one-text call, the fixed cost of a tile spread
+  // over more positions (a text wastes half a tile at its end on average)
+  return n <= kShortText ? kTileShort : kTileSingle;
 }
 
 static int layout_batch(const pfac_table* const* tables, uint32_t num_tables,

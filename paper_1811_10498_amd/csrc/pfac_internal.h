@@ -15,6 +15,11 @@ constexpr uint32_t kMinJump = 6;
 constexpr uint32_t kMaxJump = 10;
 constexpr uint32_t kImageLevels = 8;      // trie levels an LDS image may hold
 constexpr uint32_t kImageMaxBytes = 160 * 1024;
+// Pair tables (filter depths kMinJump..kPairMaxDepth): one byte per
+// (D-1)-base string m; bits 0..3: the window a.m passes the depth-D filter
+// (a = the base before m), bits 4..7: the window m.b passes (b = the base
+// after m).  Two neighbouring positions share m, so one byte read tests both.
+constexpr uint32_t kPairMaxDepth = 9;
 
 // Second filter: the first K = min(shortest pattern, kHashK) bases of a
 // window, left-aligned in 32 bits (first base most significant), hashed
@@ -139,6 +144,7 @@ struct DevTable {
   const uint32_t* jump[kMaxJump + 1];
   const OutEntry* jres[kMaxJump + 1];
   const uint32_t* image[kMaxJump + 1];   // LDS image words (HostTable::Image)
+  const uint8_t* pair[kMaxJump + 1];     // pair tables (D <= kPairMaxDepth)
   const uint32_t* levels[kMaxJump + 1];  // per image level: {byte_off, pre_off, first state, 0}
   const uint32_t* hash[kHashMaxBits + 1]; // second-filter bitmaps
   const uint32_t* chain;                  // [2S] runs of single-child steps
@@ -155,6 +161,7 @@ struct TableLayout {
   uint64_t o_next = 0, o_out = 0, o_chain = 0;
   uint64_t o_jump[kMaxJump + 1] = {}, o_jres[kMaxJump + 1] = {}, o_im[kMaxJump + 1] = {};
   uint64_t o_lv[kMaxJump + 1] = {};
+  uint64_t o_pair[kMaxJump + 1] = {};
   uint32_t image_words[kMaxJump + 1] = {};
   std::vector<uint32_t> lvdesc[kMaxJump + 1];
   uint64_t o_hash[kHashMaxBits + 1] = {};

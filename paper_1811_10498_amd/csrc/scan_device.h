@@ -40,11 +40,11 @@
 
 namespace pfac {
 
-// Start positions per wave tile (a template parameter of the scan): one
-// text per launch takes 2048 by default (the fixed cost of a tile --
-// staging, locating, one round of deep walks -- spread over more
-// positions), a batch 1024, and short texts of a batch 256 (a 150-base read
-// then leaves less of its tile empty).
+// Start positions per wave tile (a template parameter of the scan): 2048 by
+// default (the fixed cost of a tile -- staging, locating, one round of deep
+// walks -- spread over more positions), 256 for the short texts of a batch
+// (a 150-base read then leaves less of its tile empty), 1024 on request and
+// for the global-memory variants of a batch.
 constexpr uint32_t kTileSingle = 2048;
 constexpr uint32_t kTileBatch = 1024;
 constexpr uint32_t kTileShort = 256;
@@ -118,6 +118,11 @@ struct ScanParams {
   uint32_t hash_shift;            // 32 - bits
   uint32_t hash_kmask;            // key bits of the K-base window (top 2K bits)
   uint32_t hash_imask;            // invalid bits of the K-base window ((1 << K) - 1)
+  uint32_t pair;                  // 1: the LDS image is the depth-D pair table
+  uint32_t hash_cls;              // 1 (K <= 12 only): tiles with only A/C/G/T staged
+                                  // test the second filter on every window while
+                                  // classifying (large pattern sets, whose depth-D
+                                  // bitmap lets most windows through)
   // the paper's layouts of the transition table (global-memory variants):
   // next state and matched pattern ID per cell as two arrays, or merged
   const uint32_t* next2;          // [S*4] child state, 0 = none
@@ -981,6 +986,7 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p0) {
   const uint32_t* bmpre = lds + (GLOBAL ? 0u : (1u << (2 * D)) / 32);
   // all LDS is dynamic (no static arrays), so its base is the constant 0
   const bool hashed = !GLOBAL && p.hash_on;
+  const bool pairm = !GLOBAL && p.pair;           // the image is the pair table
   const bool pfxon = !GLOBAL && p.pfx_on;
   const uint32_t* hl = lds + img_words;           // second-filter bitmap
   uint32_t* pk = nullptr;
@@ -1117,6 +1123,21 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p0) {
     // bits [o_r, o_r+5) (a bit-field offset uses the low 5 bits of its
     // operand).  All four reads of a group are issued before the first is used.
     constexpr uint32_t DL = GLOBAL ? kMinJump : D;      // (unused by the global variants)
+    // pair table: byte m = the filter bits of the windows a.m (bits 0..3, by
+    // the base a before m) and m.b (bits 4..7, by the base b after m).  The
+    // windows at r = 0, 1 share m = bases 1..D-1 of w, those at r = 2, 3
+    // m = bases 3..D+1 (base k of w is bits [30-2k, 32-2k)).
+    auto pair4 = [&](uint32_t w) -> uint32_t {
+      constexpr uint32_t M = (1u << (2 * (DL - 1))) - 1u;
+      const uint8_t* pt = reinterpret_cast<const uint8_t*>(lds);
+      const uint32_t e0 = pt[(w >> (32 - 2 * DL)) & M];
+      const uint32_t e1 = pt[(w >> (28 - 2 * DL)) & M];
+      const uint32_t r0 = __builtin_amdgcn_ubfe(e0, w >> 30, 1u);
+      const uint32_t r1 = __builtin_amdgcn_ubfe(e0, 4u + ((w >> (30 - 2 * DL)) & 3u), 1u);
+      const uint32_t r2 = __builtin_amdgcn_ubfe(e1, (w >> 26) & 3u, 1u);
+      const uint32_t r3 = __builtin_amdgcn_ubfe(e1, 4u + ((w >> (26 - 2 * DL)) & 3u), 1u);
+      return r0 | (r1 << 1) | (r2 << 2) | (r3 << 3);
+    };
     auto lookup4 = [&](uint32_t w) -> uint32_t {
       uint32_t word[4];
       #pragma unroll
@@ -1130,7 +1151,13 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p0) {
         m4 |= __builtin_amdgcn_ubfe(word[r], w >> (32 - 2 * r - 2 * DL), 1u) << r;
       return m4;
     };
-    if (!GLOBAL && __builtin_amdgcn_readfirstlane((uint32_t)(__ballot(dirty) != 0)) == 0) {
+    const bool clean =
+        !GLOBAL && __builtin_amdgcn_readfirstlane((uint32_t)(__ballot(dirty) != 0)) == 0;
+    // windows of a clean tile of a large pattern set have passed the second
+    // filter here already
+    const bool hash_cls = clean && hashed && p.hash_cls;
+    const bool hash_q = hashed && !hash_cls;     // queue entries still to test
+    if (clean) {
       // every group's 16 bases (from q0, first base in the top bits) first,
       // then the bitmap words of two groups at a time
       uint32_t wv[NG];
@@ -1140,6 +1167,10 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p0) {
         wv[g] = __builtin_amdgcn_perm(pk[wi], pk[wi + 1], bsel);
       }
       constexpr uint32_t GS = NG >= 2 ? 2u : 1u;   // groups per batch of reads
+      if (pairm) {
+        #pragma unroll
+        for (uint32_t g = 0; g < NG; ++g) want |= pair4(wv[g]) << (4 * g);
+      } else {
       #pragma unroll
       for (uint32_t g = 0; g < NG; g += GS) {
         uint32_t word[4 * GS];
@@ -1152,6 +1183,31 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p0) {
         for (uint32_t k = 0; k < 4 * GS; ++k)
           want |= __builtin_amdgcn_ubfe(word[k], wv[g + (k >> 2)] >> (32 - 2 * (k & 3) - 2 * DL),
                                         1u) << (4 * g + k);
+      }
+      }
+      if (hash_cls) {
+        // the second filter on every window: its K <= 12 bases from position
+        // r of the group are the top 2K bits of the group's 16 bases shifted
+        // by 2r; both bits must be set
+        uint32_t hbits = 0;
+        #pragma unroll
+        for (uint32_t g = 0; g < NG; ++g) {
+          uint32_t hw[8];
+          uint32_t hh[8];
+          #pragma unroll
+          for (uint32_t r = 0; r < 4; ++r) {
+            const uint32_t key = (wv[g] << (2 * r)) & p.hash_kmask;
+            hh[2 * r] = (key * kHashMul) >> p.hash_shift;
+            hh[2 * r + 1] = (key * kHashMul2) >> p.hash_shift;
+            hw[2 * r] = hl[hh[2 * r] >> 5];
+            hw[2 * r + 1] = hl[hh[2 * r + 1] >> 5];
+          }
+          #pragma unroll
+          for (uint32_t r = 0; r < 4; ++r)
+            hbits |= ((hw[2 * r] >> (hh[2 * r] & 31u)) & (hw[2 * r + 1] >> (hh[2 * r + 1] & 31u)) &
+                      1u) << (4 * g + r);
+        }
+        want &= hbits;
       }
     } else {
       // positions of the lane inside the text: all of them in a full tile
@@ -1172,7 +1228,7 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p0) {
           const uint32_t wi = q0 >> 4, ii = q0 >> 5;
           const uint32_t w = __builtin_amdgcn_perm(pk[wi], pk[wi + 1], bsel);
           const uint32_t inv = __builtin_amdgcn_alignbit(iv[ii + 1], iv[ii], sh4);
-          m4 = lookup4(w);
+          m4 = pairm ? pair4(w) : lookup4(w);
           s4 = 0;
           if (inv & gmask) {
             // a window holds a non-base (or runs past the text): such
@@ -1200,9 +1256,24 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p0) {
     uint32_t tile_hits = 0;
     uint32_t total;
     const uint32_t base = wave_excl_dpp(__builtin_popcount(want), &total);
-    const uint32_t passes = total <= kQueue ? 1u : NG;
+    // passes over the tile: one when the queue holds every survivor, else
+    // one per half of the groups when each half fits, else one per group
+    uint32_t passes = 1, gpp = NG;               // groups per pass
+    if (total > kQueue) {
+      passes = NG;
+      gpp = 1;
+      if (NG >= 2) {
+        const uint32_t lo = __builtin_popcount(want & ((1u << (2 * NG)) - 1u));
+        const uint32_t both = wave_sum(lo | ((__builtin_popcount(want) - lo) << 16));
+        if ((both & 0xFFFFu) <= kQueue && (both >> 16) <= kQueue) {
+          passes = 2;
+          gpp = NG / 2;
+        }
+      }
+    }
     for (uint32_t pass = 0; pass < passes; ++pass) {
-      const uint32_t sel = passes == 1 ? (0xFFFFFFFFu >> (32 - 4 * NG)) : (0xFu << (4 * pass));
+      const uint32_t sel = passes == 1 ? (0xFFFFFFFFu >> (32 - 4 * NG))
+                                       : ((0xFFFFFFFFu >> (32 - 4 * gpp)) << (4 * gpp * pass));
       const uint32_t wsel = want & sel;
       uint32_t pbase = base, ptotal = total;
       if (passes != 1) pbase = wave_excl_dpp(__builtin_popcount(wsel), &ptotal);
@@ -1220,11 +1291,11 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p0) {
       //      that must walk on, listed in queue2.  Up to four entries per
       //      lane at once, so their prefix-bitmap reads are in flight together
       uint32_t nwalk = ptotal;
-      if (hashed || pfxon) {
+      if (hash_q || pfxon) {
         // second filter (LDS): one queue entry per lane at a time; the
         // entries that pass are listed in queue2
         uint32_t nh = ptotal;
-        if (hashed) {
+        if (hash_q) {
           nh = 0;
           #pragma unroll 1
           for (uint32_t i0 = 0; i0 < ptotal; i0 += 64) {
@@ -1263,7 +1334,7 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p0) {
               pw[r] = 0;
               pb[r] = 0;
               if (j < nh) {
-                if (hashed) {
+                if (hash_q) {
                   idx[r] = queue2[j];
                 } else {
                   res[j] = 0;
@@ -1290,7 +1361,7 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p0) {
           wave_sync();
         }
       }
-      const bool listed = hashed || pfxon;
+      const bool listed = hash_q || pfxon;
       // ---- launches with deferred walks keep them for the end of the
       //      wave: each lane copies an entry into the wave's own part of the
       //      buffer; the entries that do not fit there are walked here

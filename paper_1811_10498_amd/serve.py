@@ -142,6 +142,11 @@ class RequestResult:
     @property
     def hits(self) -> torch.Tensor:
         """(k, 3) hits of the request: text index within the request, pos, pid."""
+        if self.hits_all.shape[1] == 2:
+            # a one-text launch: (pos, pid) rows of text 0
+            z = torch.zeros((self.hits_all.shape[0], 1), dtype=self.hits_all.dtype,
+                            device=self.hits_all.device)
+            return torch.cat([z, self.hits_all], dim=1)
         h = self.hits_all.clone()
         h[:, 0] -= self.first_text
         return h
@@ -220,11 +225,18 @@ class Server:
     by default), one dispatch in flight per stream."""
 
     def __init__(self, tables: Sequence[Table], budget_bytes: int = 32 << 30,
-                 streams: int = MAX_STREAMS, max_dispatch_bases: int = 256 << 20,
+                 streams: int = MAX_STREAMS, max_dispatch_bases: int = 64 << 20,
                  plan=None, device=None, keep_results: bool = True,
                  on_complete: Optional[Callable[[Request], None]] = None,
-                 prepared_cache: int = 64, trace: bool = False):
+                 prepared_cache: int = 64, trace: bool = False,
+                 single_min_bases: int = 4 << 20, alone_min_texts: int = 1000):
         self.tables = list(tables)
+        # a request of one text at least this long gets a launch of its own
+        # (pfac_match: 2048-position tiles, its totals from the finish kernel)
+        # instead of joining a batched launch, where the per-text reduction
+        # of such a text is one wave's serial loop
+        self.single_min_bases = int(single_min_bases)
+        self.alone_min_texts = int(alone_min_texts)
         self._lib = L.lib()
         self._tabs = (ctypes.c_void_p * len(self.tables))(*[t.handle.value for t in self.tables])
         self.budget = int(budget_bytes)
@@ -323,18 +335,35 @@ class Server:
         L_ = r.lengths
         return (r.table, int(L_.size), hash(L_.tobytes()), hash(rel.tobytes())), base, rel
 
+    def _single(self, r: Request) -> bool:
+        return r.num_texts == 1 and r.bases >= self.single_min_bases
+
+    def _alone(self, r: Request) -> bool:
+        """Many texts: dispatched on its own, so a request of a shape seen
+        before reuses a prepared batch (launch = kernels only, no per-text
+        host layout), which coalescing would forgo."""
+        return r.num_texts >= self.alone_min_texts
+
     def _dispatch(self):
         if not self.admitted or all(self.busy):
             return
         si = self.busy.index(False)
         stream = self.streams[si]
-        reqs = []
-        bases = 0
-        while self.admitted and (not reqs or
-                                 bases + self.admitted[0].bases <= self.max_dispatch_bases):
-            r = self.admitted.popleft()
-            reqs.append(r)
-            bases += r.bases
+        if self._single(self.admitted[0]):
+            self._dispatch_single(self.admitted.popleft(), si)
+            return
+        r = self.admitted.popleft()
+        reqs = [r]
+        bases = r.bases
+        if not self._alone(r):
+            # coalesce the short requests waiting behind it
+            while self.admitted:
+                h = self.admitted[0]
+                if (self._single(h) or self._alone(h)
+                        or bases + h.bases > self.max_dispatch_bases):
+                    break
+                reqs.append(self.admitted.popleft())
+                bases += h.bases
         for r in reqs:
             if r.ready is not None:
                 stream.wait_event(r.ready)
@@ -408,6 +437,47 @@ class Server:
         self.max_seen_inflight = max(self.max_seen_inflight, len(self.inflight))
         self.dispatch_sizes.append(len(reqs))
 
+    def _dispatch_single(self, r: Request, si: int):
+        """One long text: pfac_match on stream `si`, hits as (pos, pid) rows."""
+        stream = self.streams[si]
+        if r.ready is not None:
+            stream.wait_event(r.ready)
+        addrs, hold = self._texts([r], stream)
+        n = int(r.lengths[0])
+        cap = hit_cap_of(r.lengths)
+        dev = self.device
+        mt = torch.empty(max(1, n), dtype=torch.int32, device=dev)
+        hits = torch.empty((cap, 2), dtype=torch.int32, device=dev)
+        counters = torch.empty(2, dtype=torch.int64, device=dev)
+        if self.trace is not None:
+            ev_start = torch.cuda.Event(enable_timing=True)
+            ev_start.record(stream)
+        pl = ctypes.byref(self._plan) if self._plan is not None else None
+        addr = int(addrs[0])
+        tab = self.tables[r.table]
+        with torch.cuda.stream(stream):
+            rc = self._lib.pfac_match(tab.handle, addr, n, ENCODINGS["ascii"], mt.data_ptr(),
+                                      hits.data_ptr(), cap, counters.data_ptr(), pl,
+                                      stream.cuda_stream)
+        L.check(rc, "pfac_match")
+        if self.trace is not None:
+            ev_end = torch.cuda.Event(enable_timing=True)
+            ev_end.record(stream)
+            self.trace.append((si, ev_start, ev_end, 1))
+        host_c = torch.empty(2, dtype=torch.int64, pin_memory=True)
+        with torch.cuda.stream(stream):
+            host_c.copy_(counters, non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(stream)
+        r.dispatched = self.now()
+        self.busy[si] = True
+        hold.append(tab)
+        self.inflight.append(_Dispatch([r], si, ev, host_c, mt, hits, counters, [0],
+                                       np.zeros(1, dtype=np.int64), r.lengths.copy(),
+                                       ("single", addr, stream, tab), hold))
+        self.max_seen_inflight = max(self.max_seen_inflight, len(self.inflight))
+        self.dispatch_sizes.append(1)
+
     def update_table(self, index: int, add: Sequence[bytes] = (),
                      remove_ids: Sequence[int] = ()) -> Table:
         """Replace table `index` by its update (patterns added and removed,
@@ -437,6 +507,9 @@ class Server:
     # ------------------------------------------------------------ completion
     def _finish(self, d: _Dispatch):
         c = d.counters_host.numpy()
+        if isinstance(d.args[0], str):
+            self._finish_single(d, c)
+            return
         if c[0] > d.hits.shape[0]:
             # the hit buffer was too small: redo the dispatch with room for all
             addrs, tids, stream = d.args
@@ -481,6 +554,39 @@ class Server:
             r.result = res if self.keep_results else None
             del res
             self.done.append(r)
+        self.busy[d.stream_idx] = False
+
+    def _finish_single(self, d: _Dispatch, c: np.ndarray):
+        _, addr, stream, tab = d.args
+        extra = 0
+        if c[0] > d.hits.shape[0]:
+            # the hit buffer was too small: again with room for every hit
+            extra = 8 * (int(c[0]) + 64 - d.hits.shape[0])
+            self.gate.reserve(extra)
+            d.hits = torch.empty((int(c[0]) + 64, 2), dtype=torch.int32, device=self.device)
+            pl = ctypes.byref(self._plan) if self._plan is not None else None
+            n = int(d.lengths[0])
+            with torch.cuda.stream(stream):
+                L.check(self._lib.pfac_match(tab.handle, addr, n, ENCODINGS["ascii"],
+                                             d.match.data_ptr(), d.hits.data_ptr(),
+                                             d.hits.shape[0], d.counters.data_ptr(), pl,
+                                             stream.cuda_stream), "pfac_match")
+            stream.synchronize()
+            c = d.counters.cpu().numpy()
+        r = d.reqs[0]
+        lease = _Lease(self.gate, r.device_bytes() + extra, 1)
+        n = int(d.lengths[0])
+        res = RequestResult(d.match[:n], np.zeros(1, dtype=np.int64), d.lengths.copy(),
+                            d.hits[:int(c[0])], 0, np.array([c[0]]), np.array([c[1]]))
+        weakref.finalize(res, lease.drop)
+        r.completed = self.now()
+        r.ready = None
+        if self.on_complete is not None:
+            r.result = res
+            self.on_complete(r)
+        r.result = res if self.keep_results else None
+        del res
+        self.done.append(r)
         self.busy[d.stream_idx] = False
 
     def _complete(self):

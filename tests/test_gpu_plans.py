@@ -50,6 +50,13 @@ SINGLE_PLANS = [
     dict(tile=1024),
     dict(tile=1024, walks=pf.PFAC_WALKS_INLINE, prefix=1),
     dict(prefix=1, levels=0, depth=8, hash_bits=NONE_H),
+    # the filter as a pair table (one LDS byte per two neighbouring windows)
+    # and as the plain bitmap
+    dict(pair=1, depth=9, hash_bits=NONE_H, prefix=NONE_P),
+    dict(pair=1, depth=8, hash_bits=18),
+    dict(pair=pf.PFAC_PAIR_NONE, depth=9, hash_bits=18),
+    dict(pair=1, depth=7, tile=1024, prefix=1),
+    dict(pair=1, depth=6, block=512),
     None,
 ]
 
@@ -122,6 +129,9 @@ BATCH_PLANS = [
     dict(prefix=1, walks=pf.PFAC_WALKS_DEFERRED, tile=256),
     dict(prefix=1, hash_bits=NONE_H, depth=10, block=512),
     dict(walks=pf.PFAC_WALKS_INLINE, hash_bits=19),
+    dict(pair=1, depth=9, hash_bits=18),
+    dict(pair=1, depth=8, tile=256, walks=pf.PFAC_WALKS_DEFERRED),
+    dict(pair=pf.PFAC_PAIR_NONE, depth=9),
     dict(variant=pf.PFAC_VARIANT_GLOBAL),
 ]
 
