@@ -481,9 +481,10 @@ def part_c4(pf, torch, args, plan, num_requests=600, load=0.7, plain_requests=60
         return out
 
     kw = dict(budget_bytes=32 << 30, keep_results=False, plan=plan)
-    srv = Server(tables, **kw)
-    srv.run(make([0.0] * num_requests)[:60])          # warm-up (and prepared batches)
     srv = Server(tables, trace=True, **kw)
+    srv.run(make([0.0] * num_requests)[:60])          # warm-up (and prepared batches)
+    srv.done.clear()
+    srv.trace.clear()
     closed = srv.run(make([0.0] * num_requests))
     iv = srv.device_intervals()
     busy = 0.0
@@ -514,8 +515,11 @@ def part_c4(pf, torch, args, plan, num_requests=600, load=0.7, plain_requests=60
         if not ks:
             continue
         reqs = lambda: make([0.0] * len(ks), ks)
-        Server(tables, **kw).run(reqs()[:8])                     # warm-up
-        sk = Server(tables, **kw).run(reqs())
+        sv = Server(tables, **kw)
+        sv.run(reqs())                                  # warm-up: scratch, prepared batches
+        sv.done.clear()
+        sk = sv.run(reqs())
+        plain_per_request(tables, reqs()[:4], plan=plan)   # warm-up
         pk = plain_per_request(tables, reqs(), plan=plan)
         per_kind[kind] = {"requests": len(ks),
                           "served_gbases_per_s": round(sk["gbases_per_s"], 2),

@@ -249,7 +249,12 @@ class Server:
         self.device = torch.device(device or "cuda")
         n = max(1, min(int(streams), MAX_STREAMS))
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n)]
-        self.busy = [False] * n
+        # dispatches in flight per stream: a long one-text launch fills the
+        # device by itself, so those go to stream 0 only, up to three queued
+        # there (the next starts as the previous ends, no host round trip);
+        # the other dispatches take the other streams, one each
+        self.busy = [0] * n
+        self.depth = [3] + [1] * (n - 1)
         self.gate = Admission(budget_bytes)                      # arrived, not admitted
         self.admitted: collections.deque = collections.deque()  # admitted, not dispatched
         self.inflight: List[_Dispatch] = []
@@ -344,15 +349,38 @@ class Server:
         host layout), which coalescing would forgo."""
         return r.num_texts >= self.alone_min_texts
 
+    def _free(self, long_text: bool):
+        """A stream that can take a dispatch of this kind, or None."""
+        n = len(self.streams)
+        lanes = [0] if (long_text or n == 1) else range(1, n)
+        for si in lanes:
+            if self.busy[si] < self.depth[si]:
+                return si
+        return None
+
     def _dispatch(self):
-        if not self.admitted or all(self.busy):
-            return
-        si = self.busy.index(False)
+        """Start one dispatch from the head of the admitted queue; False when
+        no stream can take it now."""
+        if not self.admitted:
+            return False
+        big = self._single(self.admitted[0])
+        si = self._free(big)
+        pick = 0
+        if si is None:
+            if not big:
+                return False
+            # the long-text stream is full: a short request behind may go
+            pick = next((i for i, q in enumerate(self.admitted) if not self._single(q)), None)
+            si = None if pick is None else self._free(False)
+            if si is None:
+                return False
+            big = False
         stream = self.streams[si]
-        if self._single(self.admitted[0]):
+        if big:
             self._dispatch_single(self.admitted.popleft(), si)
-            return
-        r = self.admitted.popleft()
+            return True
+        r = self.admitted[pick]
+        del self.admitted[pick]
         reqs = [r]
         bases = r.bases
         if not self._alone(r):
@@ -428,7 +456,7 @@ class Server:
         t = self.now()
         for r in reqs:
             r.dispatched = t
-        self.busy[si] = True
+        self.busy[si] += 1
         # the tables this dispatch reads stay alive until it completes (a
         # table replaced meanwhile is freed after its last dispatch)
         hold.append(list(self.tables))
@@ -436,6 +464,7 @@ class Server:
                                        match_offsets, lengths, (addrs, tids, stream), hold))
         self.max_seen_inflight = max(self.max_seen_inflight, len(self.inflight))
         self.dispatch_sizes.append(len(reqs))
+        return True
 
     def _dispatch_single(self, r: Request, si: int):
         """One long text: pfac_match on stream `si`, hits as (pos, pid) rows."""
@@ -470,7 +499,7 @@ class Server:
             ev = torch.cuda.Event()
             ev.record(stream)
         r.dispatched = self.now()
-        self.busy[si] = True
+        self.busy[si] += 1
         hold.append(tab)
         self.inflight.append(_Dispatch([r], si, ev, host_c, mt, hits, counters, [0],
                                        np.zeros(1, dtype=np.int64), r.lengths.copy(),
@@ -554,7 +583,7 @@ class Server:
             r.result = res if self.keep_results else None
             del res
             self.done.append(r)
-        self.busy[d.stream_idx] = False
+        self.busy[d.stream_idx] -= 1
 
     def _finish_single(self, d: _Dispatch, c: np.ndarray):
         _, addr, stream, tab = d.args
@@ -587,7 +616,7 @@ class Server:
         r.result = res if self.keep_results else None
         del res
         self.done.append(r)
-        self.busy[d.stream_idx] = False
+        self.busy[d.stream_idx] -= 1
 
     def _complete(self):
         still = []
@@ -601,8 +630,8 @@ class Server:
     def step(self):
         self._complete()
         self._admit()
-        while self.admitted and not all(self.busy):
-            self._dispatch()
+        while self._dispatch():
+            pass
 
     def idle(self) -> bool:
         return not (self.gate.queue or self.admitted or self.inflight)

@@ -114,33 +114,39 @@ def test_kept_results_hold_their_reservation():
 
 
 def test_dispatches_overlap_on_the_device():
-    """Requests admitted while others run go out on other streams: the
-    device intervals of dispatches on different streams overlap, and every
-    result is the same as the request's plain call."""
+    """Requests admitted while others run go out on other streams: long
+    one-text requests on the long-text stream (two queued there), requests
+    of several shorter texts on the others; the device intervals of
+    dispatches on different streams overlap, and every result is the same as
+    the request's plain call."""
     tries = W.served_tries(seed=5, sizes=[2000, 3000], pool_bases=500_000)
     tables = [pf.Table(t) for t in tries]
     pool = torch.from_numpy(W.uniform_ascii(64 << 20, W.rng(11))).to(DEV)
-    # 48 Mbase per request, matched by the paper's global-memory kernel (about
-    # a millisecond each): longer on the device than a dispatch takes on the
-    # host, so later dispatches start while earlier ones run
+    # matched by the paper's global-memory kernel (about a millisecond per
+    # 48 Mbase): longer on the device than a dispatch takes on the host
     reqs = [Request(i, i % 2, [pool[(i % 4) * (4 << 20):(i % 4) * (4 << 20) + (48 << 20)]], 0.0)
-            for i in range(8)]
-    srv = Server(tables, budget_bytes=8 << 30, streams=4, max_dispatch_bases=48 << 20,
+            for i in range(4)]
+    for i in range(4, 10):
+        o = (i % 4) * (4 << 20)
+        texts = TextBatch(pool, o + (3 << 20) * np.arange(16), np.full(16, 3 << 20))
+        reqs.append(Request(i, i % 2, texts, 0.0))
+    srv = Server(tables, budget_bytes=16 << 30, streams=4, max_dispatch_bases=48 << 20,
                  trace=True, plan=dict(variant=pf.PFAC_VARIANT_GLOBAL))
     srv.run(reqs)
     iv = srv.device_intervals()
     print("dispatch intervals (stream, ms, ms, requests):",
           [(si, round(a, 3), round(b, 3), k) for si, a, b, k in iv], flush=True)
-    assert len(iv) == 8 and srv.max_seen_inflight >= 2
-    assert len({si for si, _, _, _ in iv}) >= 2
+    assert len(iv) == 10 and srv.max_seen_inflight >= 2
+    assert {si for si, _, _, _ in iv if True} >= {0, 1}
     overlap = any(a2 < b1 and s1 != s2
                   for (s1, a1, b1, _) in iv for (s2, a2, b2, _) in iv if a1 <= a2)
     assert overlap
     for r in srv.done:
-        alone = pf.match(tables[r.table], r.text(0), hit_cap=hit_cap_of(r.lengths))
-        torch.cuda.synchronize()
-        assert torch.equal(r.result.text_match(0), alone.match)
-        assert r.result.occurrences[0] == alone.total()
+        for t in range(r.num_texts):
+            alone = pf.match(tables[r.table], r.text(t), hit_cap=hit_cap_of(r.lengths))
+            torch.cuda.synchronize()
+            assert torch.equal(r.result.text_match(t), alone.match), (r.rid, t)
+            assert r.result.occurrences[t] == alone.total()
 
 
 def test_table_update_while_serving():
