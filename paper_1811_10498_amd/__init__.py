@@ -10,11 +10,11 @@ from ._lib import (PFAC_HASH_NONE, PFAC_LEVELS_NONE, PFAC_VARIANT_GLOBAL,
                    PFAC_VARIANT_GLOBAL_MERGED, PFAC_VARIANT_GLOBAL_TWO_ARRAYS, PFAC_VARIANT_TILED,
                    PFAC_PREFIX_NONE, PFAC_PAIR_NONE, PFAC_WALKS_DEFERRED, PFAC_WALKS_INLINE, PfacError, lib)
 from .matcher import (AllResult, Batch, BatchResult, MatchResult, Table, match, match_all,
-                      match_batch, n_bases)
+                      match_batch, match_layout, n_bases)
 
 __all__ = [
     "Table", "match", "match_all", "AllResult", "match_batch", "Batch", "MatchResult",
-    "BatchResult", "PfacError", "lib", "n_bases", "PFAC_VARIANT_TILED", "PFAC_VARIANT_GLOBAL",
+    "BatchResult", "PfacError", "lib", "n_bases", "match_layout", "PFAC_VARIANT_TILED", "PFAC_VARIANT_GLOBAL",
     "PFAC_VARIANT_GLOBAL_TWO_ARRAYS", "PFAC_VARIANT_GLOBAL_MERGED", "PFAC_LEVELS_NONE", "PFAC_HASH_NONE",
     "PFAC_WALKS_INLINE", "PFAC_WALKS_DEFERRED", "PFAC_PREFIX_NONE", "PFAC_PAIR_NONE",
 ]

@@ -316,6 +316,17 @@ class BatchResult:
         return c[2::2], c[3::2]
 
 
+def match_layout(lengths) -> np.ndarray:
+    """Default element offsets of per-text dense outputs in one int32 array:
+    back to back, each run starting at a multiple of 4 elements, so that every
+    tile of a text writes its output with 16-byte stores."""
+    lengths = np.asarray(lengths, dtype=np.int64)
+    if lengths.size == 0:
+        return np.zeros(0, dtype=np.uint64)
+    padded = (lengths + 3) // 4 * 4
+    return np.concatenate([[0], np.cumsum(padded)[:-1]]).astype(np.uint64)
+
+
 def _descriptors(offsets, lengths, table_index, enc, match_offsets):
     offsets = np.asarray(offsets, dtype=np.uint64)
     lengths = np.asarray(lengths, dtype=np.uint64)
@@ -326,8 +337,7 @@ def _descriptors(offsets, lengths, table_index, enc, match_offsets):
     encs = (np.full(T, ENCODINGS[enc], dtype=np.uint32) if isinstance(enc, str)
             else np.array([ENCODINGS[e] for e in enc], dtype=np.uint32))
     if match_offsets is None:
-        match_offsets = np.concatenate([[0], np.cumsum(lengths)[:-1]]).astype(np.uint64) \
-            if T else np.zeros(0, dtype=np.uint64)
+        match_offsets = match_layout(lengths)
     descs = np.zeros(max(1, T), dtype=DESC_DTYPE)
     if T:
         descs["text_offset"][:T] = offsets

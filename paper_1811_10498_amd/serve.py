@@ -35,7 +35,7 @@ import numpy as np
 import torch
 
 from . import _lib as L
-from .matcher import DESC_DTYPE, ENCODINGS, Batch, Table, match, match_batch
+from .matcher import DESC_DTYPE, ENCODINGS, Batch, Table, match, match_batch, match_layout
 
 ALIGN = 16
 MAX_STREAMS = 4          # hardware queues per process on the target (HIP's default)
@@ -121,13 +121,13 @@ class Request:
         """What a dispatch allocates for the request: its copied host texts,
         its dense match arrays, its hit slots (12 bytes each) and counters."""
         L_ = self.lengths
-        return (self.host_text_bytes() + 4 * int(L_.sum()) + 12 * hit_cap_of(L_)
-                + 16 * (int(L_.size) + 1))
+        return (self.host_text_bytes() + 4 * int(((L_ + 3) // 4 * 4).sum())
+                + 12 * hit_cap_of(L_) + 16 * (int(L_.size) + 1))
 
 
 @dataclass
 class RequestResult:
-    match: torch.Tensor              # int32, the texts' dense outputs back to back
+    match: torch.Tensor              # int32, the texts' dense outputs, each at its offset
     offsets: np.ndarray              # start of each text's run in `match`
     lengths: np.ndarray
     hits_all: torch.Tensor           # int32 (k, 3) rows of the dispatch: text, pos, pid
@@ -406,10 +406,11 @@ class Server:
         tids = np.concatenate(tids)
         addrs, hold = self._texts(reqs, stream)
         cap = sum(hit_cap_of(r.lengths) for r in reqs)
-        total = int(lengths.sum())
-        match_offsets = np.concatenate([[0], np.cumsum(lengths)[:-1]]).astype(np.int64)
+        # each text's output starts at a multiple of 4 elements (16-byte stores)
+        match_offsets = match_layout(lengths).astype(np.int64)
+        extent = int(match_offsets[-1] + lengths[-1]) if ntext else 0
         dev = self.device
-        mt = torch.empty(max(1, total), dtype=torch.int32, device=dev)
+        mt = torch.empty(max(1, extent), dtype=torch.int32, device=dev)
         hits = torch.empty((cap, 3), dtype=torch.int32, device=dev)
         counters = torch.empty(2 + 2 * ntext, dtype=torch.int64, device=dev)
         if self.trace is not None:
@@ -570,7 +571,8 @@ class Server:
             k = r.num_texts
             Lr = d.lengths[f:f + k]
             m0 = int(d.match_offsets[f]) if k else 0
-            mats = d.match[m0:m0 + int(Lr.sum())]
+            m1 = int(d.match_offsets[f + k - 1]) + int(Lr[-1]) if k else 0
+            mats = d.match[m0:m1]
             res = RequestResult(mats, d.match_offsets[f:f + k] - m0, Lr,
                                 d.hits[int(hit_start[f]):int(hit_start[f + k])], f,
                                 per_hits[f:f + k].copy(), per_occ[f:f + k].copy())

@@ -53,3 +53,16 @@ def check_batch(res, refs, lengths, hits_only=False):
     assert c[0] == tot_h and c[1] == tot_o
 
 
+
+
+def runs_equal(a, b, offsets, lengths):
+    """Two dense batch outputs agree on every text's run (the up to three
+    elements between runs, left by the 16-byte alignment of each run, are
+    not written)."""
+    a = a.cpu().numpy() if hasattr(a, "cpu") else np.asarray(a)
+    b = b.cpu().numpy() if hasattr(b, "cpu") else np.asarray(b)
+    for o, n in zip(offsets, lengths):
+        o, n = int(o), int(n)
+        if not np.array_equal(a[o:o + n], b[o:o + n]):
+            return False
+    return True

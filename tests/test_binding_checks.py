@@ -42,11 +42,11 @@ def _descs(offsets, lengths, enc="ascii", match_offsets=None):
 
 def test_batch_extent_checks():
     d, T = _descs([0, 160, 320], [150, 150, 150])
-    M.check_batch_extents(d, T, 470, 450)
+    M.check_batch_extents(d, T, 470, 454)
     with pytest.raises(ValueError):
-        M.check_batch_extents(d, T, 469, 450)          # last text runs past the base
+        M.check_batch_extents(d, T, 469, 454)          # last text runs past the base
     with pytest.raises(ValueError):
-        M.check_batch_extents(d, T, 470, 449)          # outputs run past match_out
+        M.check_batch_extents(d, T, 470, 453)          # outputs run past match_out
     M.check_batch_extents(d, T, 470, None)             # no dense output
     d2, T2 = _descs([0, 64], [100, 100], enc="2bit")
     M.check_batch_extents(d2, T2, 89, 200)
@@ -55,9 +55,22 @@ def test_batch_extent_checks():
     d3, T3 = _descs([0, 1000], [10, 0])                # empty texts reach nothing
     M.check_batch_extents(d3, T3, 10, 10)
     with pytest.raises(ValueError):
-        M.check_batch_extents(d, T, 470, 450, hits_shape=(16, 2))
+        M.check_batch_extents(d, T, 470, 454, hits_shape=(16, 2))
     with pytest.raises(ValueError):
-        M.check_batch_extents(d, T, 470, 450, counters_numel=7)
-    assert M._extents(d, T) == (470, 450)
+        M.check_batch_extents(d, T, 470, 454, counters_numel=7)
+    assert M._extents(d, T) == (470, 454)
     d4, T4 = _descs([0, 16], [5, 5], match_offsets=np.array([100, 0]))
     assert M._extents(d4, T4) == (21, 105)
+
+
+def test_default_match_layout_is_aligned_and_disjoint():
+    L = np.array([150, 1, 0, 7, 4, 2049, 3], dtype=np.int64)
+    o = M.match_layout(L).astype(np.int64)
+    assert o.dtype == np.int64 and o.size == L.size
+    assert (o % 4 == 0).all()
+    assert (o[1:] >= o[:-1] + L[:-1]).all()             # runs do not overlap
+    assert (o[1:] - (o[:-1] + L[:-1]) <= 3).all()       # at most 3 elements of padding
+    d, T = _descs(np.arange(L.size) * 4096, L)
+    assert (d["match_offset"][:T] == o).all()
+    assert M._extents(d, T)[1] == int(o[-1] + L[-1])
+    assert M.match_layout([]).size == 0

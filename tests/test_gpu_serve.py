@@ -64,7 +64,8 @@ def test_served_results_match_alone_and_oracle(device_reads):
     assert max(srv.dispatch_sizes) > 1          # requests were coalesced
     for r in srv.done:
         res = r.result
-        assert res.match.numel() == r.bases
+        assert res.match.numel() == int(res.offsets[-1]) + int(res.lengths[-1])
+        assert int(res.lengths.sum()) == r.bases
         step = max(1, r.num_texts // 25)         # reads requests: every 25th read
         for i in range(0, r.num_texts, step):
             t = r.text(i)
