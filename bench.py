@@ -210,9 +210,19 @@ def filter_rates(pf, table_patterns, plan, codes_sample):
                                  ctypes.byref(bad))
         hb = np.unpackbits(hw.view(np.uint8), bitorder="little").astype(bool)
         key = (key16 & np.uint64(((1 << (2 * K.value)) - 1) << (32 - 2 * K.value)))
-        h1 = ((key * np.uint64(0x9E3779B1)) & np.uint64(0xFFFFFFFF)) >> np.uint64(32 - b)
-        h2 = ((key * np.uint64(0x85EBCA77)) & np.uint64(0xFFFFFFFF)) >> np.uint64(32 - b)
-        passH = passD & hb[h1.astype(np.int64)] & hb[h2.astype(np.int64)]
+        if K.value <= 12 and bits.mean() > 0.3:
+            # large sets: the one-hash form (first K bases right-aligned, 24-bit multiplier)
+            lib.pfac_build_host_hash1(arr, lens, len(pats), b, hw.ctypes.data, ctypes.byref(K),
+                                      ctypes.byref(bad))
+            hb = np.unpackbits(hw.view(np.uint8), bitorder="little").astype(bool)
+            k24 = key >> np.uint64(32 - 2 * K.value)
+            h1 = ((k24 * np.uint64(0xC6A4A7)) & np.uint64(0xFFFFFFFF)) >> np.uint64(32 - b)
+            passH = passD & hb[h1.astype(np.int64)]
+            out["hash_form"] = "one 24-bit multiplicative hash"
+        else:
+            h1 = ((key * np.uint64(0x9E3779B1)) & np.uint64(0xFFFFFFFF)) >> np.uint64(32 - b)
+            h2 = ((key * np.uint64(0x85EBCA77)) & np.uint64(0xFFFFFFFF)) >> np.uint64(32 - b)
+            passH = passD & hb[h1.astype(np.int64)] & hb[h2.astype(np.int64)]
         out["hash_filter"] = float(passH.mean())
     passP = passH
     if plan.get("prefix", 0xFFFFFFFF) == 1:

@@ -121,8 +121,10 @@ typedef struct {
   uint32_t tile;        /* start positions per wave tile: 1024 or 2048 (one-text and
                            batched calls), 256 (batched calls only).  0 = library
                            choice: 2048 for one text; in a batch 256 for texts of at
-                           most 512 bases and 2048 for longer ones (an explicit
-                           value applies to every text of the batch) */
+                           most 512 bases and 2048 for longer ones, except that
+                           fewer than 4096 short texts of a table that also has
+                           longer ones get 2048 with them (an explicit value
+                           applies to every text of the batch) */
   uint32_t prefix;      /* prefix filter, used when every pattern is longer than D:
                            windows that pass the LDS filters are looked up in an exact
                            bitmap of the patterns' first K2 bases held in global
@@ -275,7 +277,7 @@ int pfac_match(const pfac_table* table, const void* d_text, uint64_t n, int enc,
  * look-back words, then the scan and finish kernels.
  *   Returns PFAC_E_SCRATCH, before anything is enqueued, when the text needs
  *   more scratch than the array holds: 268 bytes per tile of 2048 positions
- *   plus 32 bytes per deferred-walk entry, so between about 100 Mbase (plans
+ *   plus 32 bytes per deferred-walk entry plus 8 KB, so between about 100 Mbase (plans
  *   that defer many walks) and 500 Mbase (walks at once); pfac_match has no
  *   such limit.  PFAC_E_ARG for
  *   byte-alphabet tables and for the paper's two-array and merged-cell
@@ -316,7 +318,8 @@ int pfac_match_all(const pfac_table* table, const void* d_text, uint64_t n, int 
  * Match many texts in one persistent launch per (table, tile size): the
  * waves of each workgroup take (text, tile) work items one at a time from a
  * counter in LDS, in text-then-position order; texts of at most 512 bases get
- * 256-position tiles unless the plan fixes the tile size.
+ * 256-position tiles (unless the plan fixes the tile size, or fewer than 4096
+ * of them share their table with longer texts: those go with the longer ones).
  *   tables/num_tables  host array of tables (all on the current device)
  *   descs/num_texts    host array of descriptors (copied by the call)
  *   d_text_base        device base of all texts
@@ -421,6 +424,21 @@ int pfac_build_host_image(const char* const* patterns, const uint32_t* lengths, 
  */
 int pfac_build_host_hash(const char* const* patterns, const uint32_t* lengths, uint32_t num,
                          uint32_t bits, uint32_t* words, uint32_t* k, int64_t* bad_index);
+
+/*
+ * Host-only: the one-hash form of the second filter (2^bits bits, bits =
+ * 12..20), which the scan uses instead of the two-hash one for pattern sets
+ * with K <= 12 that most windows pass at the filter depth (they also have
+ * the exact prefix filter behind it).  The key of a K-base window is
+ * sum of base_k * 4^(K-1-k) for k < K (first base most significant,
+ * right-aligned); its bit is h = (key * 0xC6A4A7 mod 2^32) >> (32 - bits),
+ * set for the first K bases of every pattern; a window passes when its bit
+ * is set.  *k receives K and `words` (uint32[2^bits / 32], caller-owned)
+ * the bitmap when non-NULL.  PFAC_E_ARG when K > 12 (no such bitmap; words
+ * are zeroed).
+ */
+int pfac_build_host_hash1(const char* const* patterns, const uint32_t* lengths, uint32_t num,
+                          uint32_t bits, uint32_t* words, uint32_t* k, int64_t* bad_index);
 
 /*
  * Host-only: the path-compression records the walk uses, for inspection and

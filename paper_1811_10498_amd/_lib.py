@@ -27,7 +27,7 @@ EXPORTS = (
     "pfac_match_all", "pfac_match_batch", "pfac_batch_create", "pfac_batch_launch", "pfac_batch_info",
     "pfac_batch_free",
     "pfac_default_plan", "pfac_build_host", "pfac_build_host_image", "pfac_build_host_hash",
-    "pfac_build_host_chain", "pfac_build_host_prefix",
+    "pfac_build_host_hash1", "pfac_build_host_chain", "pfac_build_host_prefix",
     "pfac_strerror",
     "pfac_version",
 )
@@ -129,6 +129,9 @@ def lib():
             L.pfac_build_host_hash.argtypes = [P, P, u32, u32, P, ctypes.POINTER(u32),
                                                ctypes.POINTER(i64)]
             L.pfac_build_host_hash.restype = ctypes.c_int
+            L.pfac_build_host_hash1.argtypes = [P, P, u32, u32, P, ctypes.POINTER(u32),
+                                                ctypes.POINTER(i64)]
+            L.pfac_build_host_hash1.restype = ctypes.c_int
             L.pfac_build_host_chain.argtypes = [P, P, u32, P, u64, ctypes.POINTER(u64),
                                                 ctypes.POINTER(i64)]
             L.pfac_build_host_chain.restype = ctypes.c_int

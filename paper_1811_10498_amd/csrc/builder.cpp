@@ -266,6 +266,31 @@ int build_host_table(const char* const* patterns, const uint32_t* lengths, uint3
       for (uint32_t b = kHashMinBits; b <= kHashMaxBits; ++b)
         for (uint32_t w : out->hash[b]) out->hash_set[b] += (uint32_t)__builtin_popcount(w);
     }
+    //    the one-hash form (K <= 12), folded the same way
+    if (out->hash_k && out->hash_k <= kHash1MaxK) {
+      const uint32_t K = out->hash_k;
+      std::vector<uint32_t>& big = out->hash1[kHashMaxBits];
+      big.assign((1u << kHashMaxBits) / 32, 0);
+      for (uint32_t i = 0; i < num; ++i) {
+        uint32_t key = 0;
+        for (uint32_t k = 0; k < K; ++k)
+          key = (key << 2) | (uint32_t)base_code((uint8_t)patterns[i][k]);
+        const uint32_t h = (key * kHash1Mul) >> (32 - kHashMaxBits);
+        big[h >> 5] |= 1u << (h & 31);
+      }
+      for (uint32_t b = kHashMinBits; b < kHashMaxBits; ++b) {
+        std::vector<uint32_t>& v = out->hash1[b];
+        v.assign((1u << b) / 32, 0);
+        const uint32_t fold = kHashMaxBits - b;
+        for (uint32_t h = 0; h < (1u << kHashMaxBits); ++h)
+          if ((big[h >> 5] >> (h & 31)) & 1u) {
+            const uint32_t g = h >> fold;
+            v[g >> 5] |= 1u << (g & 31);
+          }
+      }
+      for (uint32_t b = kHashMinBits; b <= kHashMaxBits; ++b)
+        for (uint32_t w : out->hash1[b]) out->hash1_set[b] += (uint32_t)__builtin_popcount(w);
+    }
     // 7. prefix filter: the first K2 bases of every pattern, exactly, one bit
     //    per K2-base key (first base most significant)
     out->pfx_k = (num && minl >= kPfxMinK) ? std::min(minl, kPfxMaxK) : 0;
@@ -453,6 +478,24 @@ extern "C" int pfac_build_host_hash(const char* const* patterns, const uint32_t*
     else memset(words, 0, ((size_t)1 << bits) / 8);
   }
   return PFAC_OK;
+}
+
+extern "C" int pfac_build_host_hash1(const char* const* patterns, const uint32_t* lengths,
+                                     uint32_t num, uint32_t bits, uint32_t* words, uint32_t* k,
+                                     int64_t* bad_index) {
+  using namespace pfac;
+  if (bits < kHashMinBits || bits > kHashMaxBits) return PFAC_E_ARG;
+  HostTable h;
+  int rc = build_host_table(patterns, lengths, num, &h, bad_index);
+  if (rc != PFAC_OK) return rc;
+  if (k) *k = h.hash_k;
+  if (words) {
+    if (!h.hash1[bits].empty())
+      memcpy(words, h.hash1[bits].data(), h.hash1[bits].size() * sizeof(uint32_t));
+    else
+      memset(words, 0, ((size_t)1 << bits) / 8);
+  }
+  return h.hash_k && h.hash_k <= kHash1MaxK ? PFAC_OK : PFAC_E_ARG;
 }
 
 extern "C" int pfac_build_host_chain(const char* const* patterns, const uint32_t* lengths,

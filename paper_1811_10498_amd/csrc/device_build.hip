@@ -254,9 +254,10 @@ __global__ __launch_bounds__(1024) void db_level_rank(const uint32_t* bytes, uin
 }
 
 // Second filter at its largest size (two hashes of the first K bases of
-// every pattern) and the prefix filter (the first K2 bases, exactly).
+// every pattern; the one-hash form too when `hash1` is set) and the prefix
+// filter (the first K2 bases, exactly).
 __global__ void db_filters(const uint64_t* w0, uint64_t n, uint32_t K, uint32_t* hash,
-                           uint32_t K2, uint32_t* pfx) {
+                           uint32_t* hash1, uint32_t K2, uint32_t* pfx) {
   DB_FOR(i, n) {
     const uint32_t top = (uint32_t)(w0[i] >> 32);     // first 16 bases, first on top
     const uint32_t key = K >= 16 ? top : top & ~((1u << (32 - 2 * K)) - 1u);
@@ -264,6 +265,10 @@ __global__ void db_filters(const uint64_t* w0, uint64_t n, uint32_t K, uint32_t*
     const uint32_t h2 = (key * kHashMul2) >> (32 - kHashMaxBits);
     atomicOr(&hash[h >> 5], 1u << (h & 31));
     atomicOr(&hash[h2 >> 5], 1u << (h2 & 31));
+    if (hash1) {
+      const uint32_t x = (key >> (32 - 2 * K)) * kHash1Mul >> (32 - kHashMaxBits);
+      atomicOr(&hash1[x >> 5], 1u << (x & 31));
+    }
     if (K2) {
       const uint32_t x = (uint32_t)(w0[i] >> (64 - 2 * K2));
       atomicOr(&pfx[x >> 5], 1u << (x & 31));
@@ -530,10 +535,10 @@ static int device_build(pfac_table* t, const char* const* patterns, const uint32
   uint32_t* chain = reinterpret_cast<uint32_t*>(base + L.o_chain);
   uint8_t* fin = sc.get<uint8_t>(S);
   uint8_t* node = sc.get<uint8_t>(S);
-  unsigned long long* sets = sc.get<unsigned long long>(32);
+  unsigned long long* sets = sc.get<unsigned long long>(48);
   DB_CHECK(fin && node && sets);
   DB_HIP(hipMemset(fin, 0, S));
-  DB_HIP(hipMemset(sets, 0, 32 * 8));
+  DB_HIP(hipMemset(sets, 0, 48 * 8));
   hipLaunchKernelGGL(db_out_init, dim3(db_grid(S)), dim3(kDbBlock), 0, nullptr, out, S);
   hipLaunchKernelGGL(db_finals, dim3(db_grid(n)), dim3(kDbBlock), 0, nullptr, st, len, id, n, out,
                      fin);
@@ -567,9 +572,11 @@ static int device_build(pfac_table* t, const char* const* patterns, const uint32
     }
   }
   uint32_t* big = reinterpret_cast<uint32_t*>(base + L.o_hash[kHashMaxBits]);
+  uint32_t* big1 = L.hash1_words[kHashMaxBits]
+                       ? reinterpret_cast<uint32_t*>(base + L.o_hash1[kHashMaxBits]) : nullptr;
   uint32_t* pfx = reinterpret_cast<uint32_t*>(base + L.o_pfx);
   hipLaunchKernelGGL(db_filters, dim3(db_grid(n)), dim3(kDbBlock), 0, nullptr, w0, n, h.hash_k, big,
-                     h.pfx_k, pfx);
+                     big1, h.pfx_k, pfx);
   DB_LAUNCH();
   for (uint32_t b = kHashMinBits; b <= kHashMaxBits; ++b) {
     uint32_t* hb = reinterpret_cast<uint32_t*>(base + L.o_hash[b]);
@@ -579,6 +586,15 @@ static int device_build(pfac_table* t, const char* const* patterns, const uint32
     hipLaunchKernelGGL(db_popcount, dim3(db_grid(L.hash_words[b])), dim3(kDbBlock), 0, nullptr, hb,
                        (uint64_t)L.hash_words[b], sets + 11 + (b - kHashMinBits));
     DB_LAUNCH();
+    if (big1) {
+      uint32_t* h1 = reinterpret_cast<uint32_t*>(base + L.o_hash1[b]);
+      if (b < kHashMaxBits)
+        hipLaunchKernelGGL(db_fold, dim3(db_grid(L.hash1_words[b])), dim3(kDbBlock), 0, nullptr,
+                           big1, kHashMaxBits - b, (uint64_t)L.hash1_words[b], h1);
+      hipLaunchKernelGGL(db_popcount, dim3(db_grid(L.hash1_words[b])), dim3(kDbBlock), 0, nullptr,
+                         h1, (uint64_t)L.hash1_words[b], sets + 31 + (b - kHashMinBits));
+      DB_LAUNCH();
+    }
   }
   if (L.pfx_words) {
     hipLaunchKernelGGL(db_popcount, dim3(db_grid(L.pfx_words)), dim3(kDbBlock), 0, nullptr, pfx,
@@ -601,11 +617,13 @@ static int device_build(pfac_table* t, const char* const* patterns, const uint32
                        reinterpret_cast<int32_t*>(base + L.o_dupi));
     DB_LAUNCH();
   }
-  unsigned long long hs[32];
+  unsigned long long hs[48];
   DB_HIP(hipMemcpy(hs, sets, sizeof(hs), hipMemcpyDeviceToHost));   // waits for every kernel
   for (uint32_t D = kMinJump; D <= kMaxJump; ++D) h.bitmap_set[D] = hs[D];
-  for (uint32_t b = kHashMinBits; b <= kHashMaxBits; ++b)
+  for (uint32_t b = kHashMinBits; b <= kHashMaxBits; ++b) {
     h.hash_set[b] = (uint32_t)hs[11 + (b - kHashMinBits)];
+    h.hash1_set[b] = big1 ? (uint32_t)hs[31 + (b - kHashMinBits)] : 0u;
+  }
   h.pfx_set = L.pfx_words ? hs[30] : 0;
   return build_pairs(t);
 }

@@ -419,7 +419,8 @@ ScratchLayout scratch_layout(uint64_t tiles, bool items, uint64_t walks) {
   L.zero_bytes = al256(L.o_sync + 256) - L.o_st;   // look-back words .. counters
   L.o_items = al256(L.o_sync + 256);
   L.o_walk = al256(L.o_items + (items ? tiles * sizeof(TileItem) : 0));
-  L.bytes = al256(L.o_walk + walks * sizeof(WalkEntry));
+  L.o_dummy = al256(L.o_walk + walks * sizeof(WalkEntry));
+  L.bytes = al256(L.o_dummy + kTileSingle * 4);
   return L;
 }
 
@@ -433,6 +434,7 @@ Scratch carve(uint8_t* mem, const ScratchLayout& L, uint64_t tiles, uint64_t wal
   s.sync = reinterpret_cast<uint32_t*>(mem + L.o_sync);
   s.items = reinterpret_cast<TileItem*>(mem + L.o_items);
   s.walk = reinterpret_cast<WalkEntry*>(mem + L.o_walk);
+  s.dummy = reinterpret_cast<int32_t*>(mem + L.o_dummy);
   s.tiles = tiles;
   s.walk_cap = walks;
   return s;
@@ -585,16 +587,16 @@ static uint32_t scan_lds_bytes(uint32_t block, uint32_t img_words, uint32_t halo
 }
 
 static ScanFn pick_scan(uint32_t block, bool global, uint32_t D, bool single, bool defer,
-                        uint32_t tile) {
+                        uint32_t tile, bool pz = false) {
   switch (block) {
-    case 256: return single ? pick_scan_single_256(global, D, defer, tile)
-                            : pick_scan_batch_256(global, D, defer, tile);
-    case 512: return single ? pick_scan_single_512(global, D, defer, tile)
-                            : pick_scan_batch_512(global, D, defer, tile);
-    case 768: return single ? pick_scan_single_768(global, D, defer, tile)
-                            : pick_scan_batch_768(global, D, defer, tile);
-    case 1024: return single ? pick_scan_single_1024(global, D, defer, tile)
-                             : pick_scan_batch_1024(global, D, defer, tile);
+    case 256: return single ? pick_scan_single_256(global, D, defer, tile, pz)
+                            : pick_scan_batch_256(global, D, defer, tile, pz);
+    case 512: return single ? pick_scan_single_512(global, D, defer, tile, pz)
+                            : pick_scan_batch_512(global, D, defer, tile, pz);
+    case 768: return single ? pick_scan_single_768(global, D, defer, tile, pz)
+                            : pick_scan_batch_768(global, D, defer, tile, pz);
+    case 1024: return single ? pick_scan_single_1024(global, D, defer, tile, pz)
+                             : pick_scan_batch_1024(global, D, defer, tile, pz);
     default: return nullptr;
   }
 }
@@ -834,6 +836,13 @@ static int launch_scan(const ScanParams& sp, const pfac_plan& plan, bool single,
   const int rc = scan_shape(sp, plan, single, tile, dev, &fn, &lds, &grid);
   if (rc) return rc;
   if (sp.defer && grid * (plan.block / 64) > sp.wq_waves) return PFAC_E_ARG;
+  // one-text deferred scans with a 16-byte aligned dense output: the
+  // pre-zeroing kernel, when it has the same occupancy (hence grid)
+  if (single && sp.defer && sp.match && sp.pz_dummy &&
+      (reinterpret_cast<uintptr_t>(sp.match) & 15) == 0 && !global_variant(plan.variant)) {
+    const ScanFn pz = pick_scan(plan.block, false, sp.D, true, true, tile, true);
+    if (pz && blocks_per_cu(pz, plan.block, lds) == blocks_per_cu(fn, plan.block, lds)) fn = pz;
+  }
   hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(plan.block), lds, stream, sp);
   return hipGetLastError() == hipSuccess ? PFAC_OK : PFAC_E_HIP;
 }
@@ -881,6 +890,14 @@ static int ensure_cells(const pfac_table* t) {
   return PFAC_OK;
 }
 
+// The second filter takes its one-hash form (and is tested while
+// classifying) when most windows pass the depth-D bitmap (large pattern
+// sets) and the K-base key fits in 24 bits.
+static bool hash_one(const HostTable& h, uint32_t D) {
+  if (h.hash_k == 0 || h.hash_k > kHash1MaxK || D < kMinJump || D > kMaxJump) return false;
+  return (double)h.bitmap_set[D] / (double)(1ull << (2 * D)) > 0.3;
+}
+
 static void fill_table(ScanParams& sp, const pfac_table* t, const pfac_plan& pl) {
   sp.next = t->dev.next;
   sp.out = t->dev.out;
@@ -921,8 +938,11 @@ static void fill_table(ScanParams& sp, const pfac_table* t, const pfac_plan& pl)
       // window of a tile takes the second filter while it is classified
       // instead of through the queue (its K bases then fit the 16 bases a
       // group of four positions holds)
-      const double fill = (double)h.bitmap_set[D] / (double)(1ull << (2 * D));
-      sp.hash_cls = (K <= 12 && fill > 0.3) ? 1u : 0u;
+      if (hash_one(h, D) && t->dev.hash1[b]) {
+        sp.hash_cls = 1;
+        sp.hash = t->dev.hash1[b];
+        sp.hash_kshift = 32 - 2 * K;
+      }
     }
     if (pl.prefix == 1 && h.pfx_k > D) {
       sp.pfx_on = 1;
@@ -944,7 +964,9 @@ static uint32_t defer_per_tile(const HostTable& h, const pfac_plan& pl, uint32_t
     pass = (double)h.pfx_set / (double)(1ull << (2 * h.pfx_k));
   } else {
     pass = (double)h.bitmap_set[pl.depth] / (double)(1ull << (2 * pl.depth));
-    if (pl.hash_bits != PFAC_HASH_NONE) {
+    if (pl.hash_bits != PFAC_HASH_NONE && hash_one(h, pl.depth)) {
+      pass *= (double)h.hash1_set[pl.hash_bits] / (double)(1ull << pl.hash_bits);
+    } else if (pl.hash_bits != PFAC_HASH_NONE) {
       const double f = (double)h.hash_set[pl.hash_bits] / (double)(1ull << pl.hash_bits);
       pass *= f * f;
     }
@@ -989,6 +1011,10 @@ void table_layout(const HostTable& h, uint64_t ndups, TableLayout* L) {
     L->hash_words[b] = h.hash_k ? (1u << b) / 32 : 0;
     L->o_hash[b] = off; off = al256(off + (uint64_t)L->hash_words[b] * 4);
   }
+  for (uint32_t b = kHashMinBits; b <= kHashMaxBits; ++b) {
+    L->hash1_words[b] = (h.hash_k && h.hash_k <= kHash1MaxK) ? (1u << b) / 32 : 0;
+    L->o_hash1[b] = off; off = al256(off + (uint64_t)L->hash1_words[b] * 4);
+  }
   L->pfx_words = h.pfx_k ? (1ull << (2 * h.pfx_k)) / 32 : 0;
   L->o_pfx = off; off = al256(off + L->pfx_words * 4);
   L->ndups = ndups;
@@ -1031,8 +1057,11 @@ int alloc_table(pfac_table* t, uint64_t ndups) {
                   hipMemcpyHostToDevice) != hipSuccess)
       return PFAC_E_HIP;
   }
-  for (uint32_t b = kHashMinBits; b <= kHashMaxBits; ++b)
+  for (uint32_t b = kHashMinBits; b <= kHashMaxBits; ++b) {
     v.hash[b] = reinterpret_cast<const uint32_t*>(base + L.o_hash[b]);
+    v.hash1[b] = L.hash1_words[b] ? reinterpret_cast<const uint32_t*>(base + L.o_hash1[b])
+                                  : nullptr;
+  }
   return PFAC_OK;
 }
 
@@ -1055,7 +1084,8 @@ int upload_host_table(pfac_table* t) {
          put(L.o_jres[D], h.jres[D].data(), h.jres[D].size() * sizeof(OutEntry)) &&
          put(L.o_im[D], h.image[D].words.data(), h.image[D].words.size() * 4);
   for (uint32_t b = kHashMinBits; b <= kHashMaxBits; ++b)
-    ok = ok && put(L.o_hash[b], h.hash[b].data(), h.hash[b].size() * 4);
+    ok = ok && put(L.o_hash[b], h.hash[b].data(), h.hash[b].size() * 4) &&
+         put(L.o_hash1[b], h.hash1[b].data(), h.hash1[b].size() * 4);
   return ok ? PFAC_OK : PFAC_E_HIP;
 }
 
@@ -1249,6 +1279,7 @@ int enqueue_single(const pfac_table* t, SinglePrep& P, const Scratch& sc, const 
   sp.tile_occ = sc.tile_occ;
   sp.slots = (d_hits || keep_slots) ? sc.slots : nullptr;
   sp.wq = sc.walk;
+  sp.pz_dummy = sc.dummy;
   int rc = launch_scan(sp, P.pl, true, P.pl.tile, dev, stream);
   if (rc) return rc;
   FinishParams fp;
@@ -1357,14 +1388,21 @@ struct BatchLayout {
   uint64_t match_extent = 0;     // int32 elements of d_match_base they reach
 };
 
-static uint32_t text_tile(const pfac_plan& pl, uint64_t n) {
+static uint32_t text_tile(const pfac_plan& pl, uint64_t n, bool fold_short) {
   if (global_variant(pl.variant)) return kTileBatch;
   if (pl.tile) return pl.tile;
   // short texts: 256-position tiles (a 150-base read fills 59 % of one);
   // longer ones 2048 like a one-text call, the fixed cost of a tile spread
-  // over more positions (a text wastes half a tile at its end on average)
-  return n <= kShortText ? kTileShort : kTileSingle;
+  // over more positions (a text wastes half a tile at its end on average).
+  // A few short texts among long ones of the same table go with the long
+  // ones: their own launch (about 15 us) costs more than a few thousand
+  // mostly empty 2048-position tiles
+  return (n <= kShortText && !fold_short) ? kTileShort : kTileSingle;
 }
+
+// Short texts of a table are folded into its long texts' tiles when they
+// would need fewer 256-position tiles than this.
+constexpr uint64_t kFoldShort = 4096;
 
 static int layout_batch(const pfac_table* const* tables, uint32_t num_tables,
                         const pfac_text_desc* descs, uint32_t num_texts, const pfac_plan* plan,
@@ -1384,6 +1422,13 @@ static int layout_batch(const pfac_table* const* tables, uint32_t num_tables,
     const int rc = resolve_plan(plan, tables[i]->host, dev, false, &L->plans[i]);
     if (rc) return rc;
   }
+  // per table: short and long texts, for folding a few short ones in
+  std::vector<uint64_t> nshort(num_tables, 0), nlong(num_tables, 0);
+  for (uint32_t s = 0; s < num_texts; ++s) {
+    if (descs[s].n == 0) continue;
+    if (descs[s].n <= kShortText) ++nshort[descs[s].table];
+    else ++nlong[descs[s].table];
+  }
   L->num_texts = num_texts;
   L->segs.resize(num_texts);
   L->tile_prefix.assign(num_texts + 1, 0);
@@ -1391,7 +1436,8 @@ static int layout_batch(const pfac_table* const* tables, uint32_t num_tables,
   L->match_extent = 0;
   for (uint32_t s = 0; s < num_texts; ++s) {
     const pfac_text_desc& d = descs[s];
-    const uint32_t tile = text_tile(L->plans[d.table], d.n);
+    const uint32_t tile = text_tile(L->plans[d.table], d.n,
+                                    nlong[d.table] > 0 && nshort[d.table] < kFoldShort);
     const uint64_t nt = (d.n + tile - 1) / tile;
     L->tile_prefix[s + 1] = L->tile_prefix[s] + nt;
     if (L->tile_prefix[s + 1] >= (1ull << 32)) return PFAC_E_ARG;

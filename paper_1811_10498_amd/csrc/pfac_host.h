@@ -16,7 +16,8 @@ uint64_t al256(uint64_t x);
 // Scratch of the scan and finish kernels, carved out of one device block:
 // per-tile hit counts, occurrence counts and hit slots; the finish kernel's
 // look-back word and occurrence sum per workgroup and its two counters
-// (zero between launches); batch work items; deferred walks.
+// (zero between launches); batch work items; deferred walks; the area a
+// pre-zeroing scan writes in place of a tile that is not full.
 struct Scratch {
   uint32_t* tile_hits = nullptr;
   unsigned long long* tile_occ = nullptr;
@@ -26,6 +27,7 @@ struct Scratch {
   uint32_t* sync = nullptr;
   TileItem* items = nullptr;
   WalkEntry* walk = nullptr;
+  int32_t* dummy = nullptr;
   uint64_t tiles = 0, walk_cap = 0;
 };
 
@@ -33,7 +35,8 @@ struct Scratch {
 // many batch work items when `items`) and `walks` deferred walks; bytes =
 // the total, [o_st, o_st + zero_bytes) = the part that must start at zero.
 struct ScratchLayout {
-  uint64_t o_hits, o_occ, o_slots, o_st, o_bo, o_sync, o_items, o_walk, bytes, zero_bytes;
+  uint64_t o_hits, o_occ, o_slots, o_st, o_bo, o_sync, o_items, o_walk, o_dummy, bytes,
+      zero_bytes;
 };
 ScratchLayout scratch_layout(uint64_t tiles, bool items, uint64_t walks);
 Scratch carve(uint8_t* mem, const ScratchLayout& L, uint64_t tiles, uint64_t walks);

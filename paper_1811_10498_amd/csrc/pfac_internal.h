@@ -32,6 +32,16 @@ constexpr uint32_t kHashMaxBits = 20;
 constexpr uint32_t kHashMul = 0x9E3779B1u;
 constexpr uint32_t kHashMul2 = 0x85EBCA77u;
 
+// One-hash form of the second filter, for K <= 12: the K-base key
+// right-aligned in 2K bits (at most 24) times a 24-bit multiplier, whose
+// product's low 32 bits the GPU forms in one full-rate 24-bit multiply; its
+// top `bits` bits are the window's one bit.  Used for pattern sets that most
+// windows pass at depth D, where the exact prefix filter follows it and the
+// second hash would only halve the few prefix-bitmap reads.  (0xC6A4A7 maps
+// every 24-bit key range evenly: each 2^19-bit slot gets 30..33 keys.)
+constexpr uint32_t kHash1Mul = 0xC6A4A7u;
+constexpr uint32_t kHash1MaxK = 12;
+
 // Prefix filter: an exact bitmap of the first K2 = min(shortest pattern,
 // kPfxMaxK) bases of every pattern (4^K2 bits, 2 MB at K2 = 12), kept in
 // global memory (L2-resident) for pattern sets too large for the hashed one.
@@ -98,6 +108,8 @@ struct HostTable {
   uint32_t hash_k = 0;                      // K of the second filter
   std::vector<uint32_t> hash[kHashMaxBits + 1];   // 2^bits-bit bitmaps
   uint32_t hash_set[kHashMaxBits + 1] = {};       // set bits of each
+  std::vector<uint32_t> hash1[kHashMaxBits + 1];  // one-hash bitmaps (hash_k <= 12)
+  uint32_t hash1_set[kHashMaxBits + 1] = {};
   uint32_t pfx_k = 0;                       // K2 of the prefix filter (0 = none)
   std::vector<uint32_t> pfx;                // 4^K2-bit bitmap
   uint64_t pfx_set = 0;                     // distinct K2-base pattern prefixes
@@ -147,6 +159,7 @@ struct DevTable {
   const uint8_t* pair[kMaxJump + 1];     // pair tables (D <= kPairMaxDepth)
   const uint32_t* levels[kMaxJump + 1];  // per image level: {byte_off, pre_off, first state, 0}
   const uint32_t* hash[kHashMaxBits + 1]; // second-filter bitmaps
+  const uint32_t* hash1[kHashMaxBits + 1]; // one-hash second-filter bitmaps (or null)
   const uint32_t* chain;                  // [2S] runs of single-child steps
   const uint32_t* pfx;                    // prefix-filter bitmap (or null)
   const uint32_t* dup_state;              // further IDs of final states (HostTable)
@@ -166,6 +179,8 @@ struct TableLayout {
   std::vector<uint32_t> lvdesc[kMaxJump + 1];
   uint64_t o_hash[kHashMaxBits + 1] = {};
   uint32_t hash_words[kHashMaxBits + 1] = {};
+  uint64_t o_hash1[kHashMaxBits + 1] = {};
+  uint32_t hash1_words[kHashMaxBits + 1] = {};
   uint64_t o_pfx = 0, pfx_words = 0;
   uint64_t o_dups = 0, o_dupi = 0, ndups = 0;
   uint64_t bytes = 0;

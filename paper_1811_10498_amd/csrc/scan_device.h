@@ -119,10 +119,12 @@ struct ScanParams {
   uint32_t hash_kmask;            // key bits of the K-base window (top 2K bits)
   uint32_t hash_imask;            // invalid bits of the K-base window ((1 << K) - 1)
   uint32_t pair;                  // 1: the LDS image is the depth-D pair table
-  uint32_t hash_cls;              // 1 (K <= 12 only): tiles with only A/C/G/T staged
-                                  // test the second filter on every window while
+  uint32_t hash_cls;              // 1 (K <= 12 only): the second filter is the one-hash
+                                  // form (`hash` its bitmap), and tiles with only
+                                  // A/C/G/T staged test it on every window while
                                   // classifying (large pattern sets, whose depth-D
                                   // bitmap lets most windows through)
+  uint32_t hash_kshift;           // hash_cls: 32 - 2K (the key's shift to the right)
   // the paper's layouts of the transition table (global-memory variants):
   // next state and matched pattern ID per cell as two arrays, or merged
   const uint32_t* next2;          // [S*4] child state, 0 = none
@@ -148,6 +150,8 @@ struct ScanParams {
   uint32_t wq_cap;
   WalkEntry* wq;
   uint64_t wq_waves;              // waves wq has room for
+  int32_t* pz_dummy;              // pre-zeroing kernels: kTileSingle int32 written in
+                                  // place of a tile that is not full
 };
 
 // ---------------------------------------------------------------- device helpers
@@ -460,7 +464,8 @@ __device__ __forceinline__ int32_t deep_walk(uint32_t e, uint32_t D, uint32_t ld
 __device__ __forceinline__ bool hash_pass(uint32_t e, const uint32_t* __restrict__ pk,
                                           const uint32_t* __restrict__ iv,
                                           const uint32_t* __restrict__ hl, uint32_t kmask,
-                                          uint32_t imask, uint32_t shift) {
+                                          uint32_t imask, uint32_t shift, bool one,
+                                          uint32_t kshift) {
   if (e & 0x8000u) return true;
   const uint32_t qt = e & 0x7FFFu;
   // a non-base among the first K bases: every pattern has at least K bases,
@@ -469,6 +474,11 @@ __device__ __forceinline__ bool hash_pass(uint32_t e, const uint32_t* __restrict
   const uint32_t wi = qt >> 4;
   const uint32_t key =
       (uint32_t)(((((uint64_t)pk[wi] << 32) | pk[wi + 1]) << (2 * (qt & 15u))) >> 32) & kmask;
+  if (one) {
+    // the one-hash form: the key right-aligned (at most 24 bits), one 24-bit multiply
+    const uint32_t h = (((key >> kshift) & 0xFFFFFFu) * kHash1Mul) >> shift;
+    return (hl[h >> 5] >> (h & 31u)) & 1u;
+  }
   const uint32_t h = (key * kHashMul) >> shift;
   const uint32_t h2 = (key * kHashMul2) >> shift;
   return (hl[h >> 5] >> (h & 31u)) & (hl[h2 >> 5] >> (h2 & 31u)) & 1u;
@@ -952,11 +962,16 @@ __device__ __forceinline__ T* in_vgpr(T* ptr) {
   uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
   asm volatile("v_mov_b32 %0, %1" : "=v"(lo) : "s"(lo));
   asm volatile("v_mov_b32 %0, %1" : "=v"(hi) : "s"(hi));
-  return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
+  // rebuilt as a global-memory pointer: accesses through it stay global
+  // (not flat) instructions, whose waits count vector memory only
+  typedef __attribute__((address_space(1))) T GT;
+  GT* g = reinterpret_cast<GT*>(((uint64_t)hi << 32) | lo);
+  return (T*)g;
 }
 
-template <int BLOCK, bool GLOBAL, int DT, bool SINGLE, bool DEFER, uint32_t TILE>
+template <int BLOCK, bool GLOBAL, int DT, bool SINGLE, bool DEFER, uint32_t TILE, bool PZ>
 __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p0) {
+  static_assert(!PZ || (SINGLE && DEFER && !GLOBAL), "pre-zeroing: one-text deferred scans");
   ScanParams p = p0;
   p.next = in_vgpr(p0.next);
   p.out = in_vgpr(p0.out);
@@ -1070,8 +1085,28 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p0) {
   auto seg_match = [&](const TileLoc& L) -> int32_t* {
     return SINGLE ? p.match : p.match + L.seg.match_off;
   };
-  if (!GLOBAL)
+  // pre-zeroing (one-text deferred scans with a 16-byte aligned dense
+  // output): a tile's output is zeroed right after its text loads are
+  // issued, and its few non-zero positions are written over it later (by
+  // the lanes that wrote the zeros, or after the wave's fence).  The eight
+  // stores sit in the same block as the loads, so they follow them on every
+  // path to the wait for the text, and that wait leaves them in flight
+  // (measured on the scan's traffic shape: 0.266 -> 0.239 ms).  Issued at the
+  // end of the iteration instead they measured slower (0.311 against 0.294 ms
+  // on the large-text scan).  A tile that is not full writes them to a
+  // scratch area instead.
+  auto prezero = [&](const TileLoc& L) {
+    const uint64_t s0 = L.ts * TILE;
+    int32_t* zt = s0 + TILE <= p.seg0.n ? p.match + s0 : p.pz_dummy;
+    const i32x4 z = {0, 0, 0, 0};
+    #pragma unroll
+    for (uint32_t g = 0; g < NG; ++g)
+      __builtin_nontemporal_store(z, reinterpret_cast<i32x4*>(zt + g * 256) + lane);
+  };
+  if (!GLOBAL) {
     pf = fetch<TILE>(TextRef{seg_text(cur), seg_n(cur), cur.ts * TILE, seg_enc(cur)}, p.halo);
+    if constexpr (PZ) prezero(cur);
+  }
 
   for (;;) {
     const uint64_t t0 = cur.ts * TILE;
@@ -1103,11 +1138,13 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p0) {
     TileLoc nxt = cur;
     if (more) {
       nxt = locate<SINGLE>(p, lt_next);
-      if (!GLOBAL)
+      if (!GLOBAL) {
         pf = fetch<TILE>(TextRef{seg_text(nxt), seg_n(nxt), nxt.ts * TILE, seg_enc(nxt)},
                          p.halo);
+        if constexpr (PZ) prezero(nxt);
+      }
     }
-    if (DEFER && zmt) {
+    if (!PZ && DEFER && zmt) {
       zero_tile<NG>(zmt, znt, zal);
       zmt = nullptr;
     }
@@ -1189,26 +1226,25 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p0) {
       }
       }
       if (hash_cls) {
-        // the second filter on every window: its K <= 12 bases from position
-        // r of the group are the top 2K bits of the group's 16 bases shifted
-        // by 2r; both bits must be set
+        // the one-hash second filter on every window: its K <= 12 bases from
+        // position r of the group are bits [32-2K-2r, 32-2r) of the group's
+        // 16 bases, right-aligned into at most 24 bits for one 24-bit multiply
         uint32_t hbits = 0;
+        const uint32_t kw = 32u - p.hash_kshift;             // 2K
         #pragma unroll
         for (uint32_t g = 0; g < NG; ++g) {
-          uint32_t hw[8];
-          uint32_t hh[8];
+          uint32_t hw[4];
+          uint32_t hh[4];
           #pragma unroll
           for (uint32_t r = 0; r < 4; ++r) {
-            const uint32_t key = (wv[g] << (2 * r)) & p.hash_kmask;
-            hh[2 * r] = (key * kHashMul) >> p.hash_shift;
-            hh[2 * r + 1] = (key * kHashMul2) >> p.hash_shift;
-            hw[2 * r] = hl[hh[2 * r] >> 5];
-            hw[2 * r + 1] = hl[hh[2 * r + 1] >> 5];
+            const uint32_t key =
+                __builtin_amdgcn_ubfe(wv[g], p.hash_kshift - 2 * r, kw) & 0xFFFFFFu;
+            hh[r] = (key * kHash1Mul) >> p.hash_shift;
+            hw[r] = hl[hh[r] >> 5];
           }
           #pragma unroll
           for (uint32_t r = 0; r < 4; ++r)
-            hbits |= ((hw[2 * r] >> (hh[2 * r] & 31u)) & (hw[2 * r + 1] >> (hh[2 * r + 1] & 31u)) &
-                      1u) << (4 * g + r);
+            hbits |= ((hw[r] >> (hh[r] & 31u)) & 1u) << (4 * g + r);
         }
         want &= hbits;
       }
@@ -1306,7 +1342,8 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p0) {
             bool go = false;
             if (i < ptotal) {
               res[i] = 0;
-              go = hash_pass(queue[i], pk, iv, hl, p.hash_kmask, p.hash_imask, p.hash_shift);
+              go = hash_pass(queue[i], pk, iv, hl, p.hash_kmask, p.hash_imask, p.hash_shift,
+                             p.hash_cls != 0, p.hash_kshift);
             }
             const uint64_t m = __ballot(go);
             if (go)
@@ -1425,6 +1462,7 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p0) {
         if (!((sel >> (4 * g)) & 1u)) continue;
         const uint32_t q0 = g * 256 + 4 * lane;
         if (!any) {
+          if (PZ && full) break;          // zeroed when its text was fetched
           if (DEFER && mt && passes == 1) {
             // the whole tile is zero: written with the next tile
             zmt = mt;
@@ -1507,13 +1545,13 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p0) {
 }  // namespace pfac
 
 // Kernel selection, one function per instantiation unit (workgroup size x
-// launch kind): the scan kernel for a variant, filter depth, walk placement
-// and tile size, or nullptr when that combination is not built.
+// launch kind): the scan kernel for a variant, filter depth, walk placement,
+// tile size and pre-zeroing, or nullptr when that combination is not built.
 namespace pfac {
 using ScanFn = void (*)(ScanParams);
 #define PFAC_DECLARE_PICK(B)                                                          \
-  ScanFn pick_scan_single_##B(bool global, uint32_t D, bool defer, uint32_t tile);    \
-  ScanFn pick_scan_batch_##B(bool global, uint32_t D, bool defer, uint32_t tile);
+  ScanFn pick_scan_single_##B(bool global, uint32_t D, bool defer, uint32_t tile, bool pz); \
+  ScanFn pick_scan_batch_##B(bool global, uint32_t D, bool defer, uint32_t tile, bool pz);
 PFAC_DECLARE_PICK(256)
 PFAC_DECLARE_PICK(512)
 PFAC_DECLARE_PICK(768)

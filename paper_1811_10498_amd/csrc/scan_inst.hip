@@ -17,15 +17,15 @@
 
 namespace pfac {
 
-template <bool DEFER, uint32_t TILE>
+template <bool DEFER, uint32_t TILE, bool PZ = false>
 static ScanFn by_depth(uint32_t D) {
   constexpr bool S = PFAC_SINGLE != 0;
   switch (D) {
-    case 6: return pfac_scan_kernel<PFAC_BLOCK, false, 6, S, DEFER, TILE>;
-    case 7: return pfac_scan_kernel<PFAC_BLOCK, false, 7, S, DEFER, TILE>;
-    case 8: return pfac_scan_kernel<PFAC_BLOCK, false, 8, S, DEFER, TILE>;
-    case 9: return pfac_scan_kernel<PFAC_BLOCK, false, 9, S, DEFER, TILE>;
-    case 10: return pfac_scan_kernel<PFAC_BLOCK, false, 10, S, DEFER, TILE>;
+    case 6: return pfac_scan_kernel<PFAC_BLOCK, false, 6, S, DEFER, TILE, PZ>;
+    case 7: return pfac_scan_kernel<PFAC_BLOCK, false, 7, S, DEFER, TILE, PZ>;
+    case 8: return pfac_scan_kernel<PFAC_BLOCK, false, 8, S, DEFER, TILE, PZ>;
+    case 9: return pfac_scan_kernel<PFAC_BLOCK, false, 9, S, DEFER, TILE, PZ>;
+    case 10: return pfac_scan_kernel<PFAC_BLOCK, false, 10, S, DEFER, TILE, PZ>;
     default: return nullptr;
   }
 }
@@ -35,15 +35,17 @@ static ScanFn by_walks(uint32_t D, bool defer) {
   return defer ? by_depth<true, TILE>(D) : by_depth<false, TILE>(D);
 }
 
-ScanFn PFAC_PICK(bool global, uint32_t D, bool defer, uint32_t tile) {
+ScanFn PFAC_PICK(bool global, uint32_t D, bool defer, uint32_t tile, bool pz) {
 #if PFAC_SINGLE
+  // pre-zeroing variants: deferred walks, 2048-position tiles
+  if (pz) return (!global && defer && tile == 2048) ? by_depth<true, 2048, true>(D) : nullptr;
   // global-memory variants: D names the transition table layout
   if (global) {
     if (tile != kTileSingle) return nullptr;
     switch (D) {
-      case 0: return pfac_scan_kernel<PFAC_BLOCK, true, 0, true, false, kTileSingle>;
-      case 1: return pfac_scan_kernel<PFAC_BLOCK, true, 1, true, false, kTileSingle>;
-      case 2: return pfac_scan_kernel<PFAC_BLOCK, true, 2, true, false, kTileSingle>;
+      case 0: return pfac_scan_kernel<PFAC_BLOCK, true, 0, true, false, kTileSingle, false>;
+      case 1: return pfac_scan_kernel<PFAC_BLOCK, true, 1, true, false, kTileSingle, false>;
+      case 2: return pfac_scan_kernel<PFAC_BLOCK, true, 2, true, false, kTileSingle, false>;
       default: return nullptr;
     }
   }
@@ -53,8 +55,9 @@ ScanFn PFAC_PICK(bool global, uint32_t D, bool defer, uint32_t tile) {
     default: return nullptr;
   }
 #else
+  if (pz) return nullptr;
   if (global) return (tile == kTileBatch && D == 0)
-                        ? pfac_scan_kernel<PFAC_BLOCK, true, 0, false, false, kTileBatch>
+                        ? pfac_scan_kernel<PFAC_BLOCK, true, 0, false, false, kTileBatch, false>
                         : nullptr;
   switch (tile) {
     case 2048: return by_walks<2048>(D, defer);

@@ -331,6 +331,47 @@ def test_second_filter_bitmap_holds_every_pattern_prefix(bits):
     assert abs(rate - mine.mean() ** 2) < 0.03
 
 
+def test_one_hash_second_filter_bits_and_folds():
+    """The one-hash form (K <= 12): every pattern's bit is set, smaller sizes
+    are the OR-fold of the largest, random keys pass at about its fill, and a
+    set whose shortest pattern is longer than 12 bases has no such bitmap."""
+    import ctypes
+    from paper_1811_10498_amd import _lib as L
+    lib = L.lib()
+    g = W.rng(83)
+    pats = W.random_patterns(5000, 12, 30, g)
+    arr, lens, keep = _pattern_arrays(pats)
+    def get(b, ps=None):
+        a, l, kp = (arr, lens, keep) if ps is None else _pattern_arrays(ps)
+        n = len(pats) if ps is None else len(ps)
+        words = np.zeros((1 << b) // 32, dtype=np.uint32)
+        k = ctypes.c_uint32(0)
+        bad = ctypes.c_int64(-1)
+        rc = lib.pfac_build_host_hash1(a, l, n, b, words.ctypes.data, ctypes.byref(k),
+                                       ctypes.byref(bad))
+        del kp
+        return rc, words, k.value
+    rc, words, K = get(16)
+    assert rc == 0 and K == 12
+    code = {ord("A"): 0, ord("C"): 1, ord("G"): 2, ord("T"): 3}
+    for p in pats:
+        key = 0
+        for i in range(K):
+            key = (key << 2) | code[p[i]]
+        x = ((key * 0xC6A4A7) & 0xFFFFFFFF) >> (32 - 16)
+        assert (words[x >> 5] >> (x & 31)) & 1
+    _, big, _ = get(20)
+    bigbits = np.unpackbits(big.view(np.uint8), bitorder="little").astype(bool)
+    folded = bigbits.reshape(1 << 16, 1 << 4).any(axis=1)
+    mine = np.unpackbits(words.view(np.uint8), bitorder="little").astype(bool)
+    assert np.array_equal(folded, mine)
+    keys = g.integers(0, 1 << 24, size=20000, dtype=np.uint64)
+    x = ((keys * np.uint64(0xC6A4A7)) & np.uint64(0xFFFFFFFF)) >> np.uint64(16)
+    assert abs(mine[x.astype(np.int64)].mean() - mine.mean()) < 0.03
+    rc, w13, K13 = get(16, [b"ACGTACGTACGTA", b"CCCCCCCCCCCCCCCCCC"])
+    assert K13 == 13 and rc != 0 and not w13.any()
+
+
 def test_second_filter_k_is_shortest_pattern_capped_at_16():
     import ctypes
     from paper_1811_10498_amd import _lib as L
