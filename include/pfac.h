@@ -277,7 +277,7 @@ int pfac_match(const pfac_table* table, const void* d_text, uint64_t n, int enc,
  * look-back words, then the scan and finish kernels.
  *   Returns PFAC_E_SCRATCH, before anything is enqueued, when the text needs
  *   more scratch than the array holds: 268 bytes per tile of 2048 positions
- *   plus 32 bytes per deferred-walk entry plus 8 KB, so between about 100 Mbase (plans
+ *   plus 32 bytes per deferred-walk entry plus 2 MiB, so between about 100 Mbase (plans
  *   that defer many walks) and 500 Mbase (walks at once); pfac_match has no
  *   such limit.  PFAC_E_ARG for
  *   byte-alphabet tables and for the paper's two-array and merged-cell

@@ -420,7 +420,7 @@ ScratchLayout scratch_layout(uint64_t tiles, bool items, uint64_t walks) {
   L.o_items = al256(L.o_sync + 256);
   L.o_walk = al256(L.o_items + (items ? tiles * sizeof(TileItem) : 0));
   L.o_dummy = al256(L.o_walk + walks * sizeof(WalkEntry));
-  L.bytes = al256(L.o_dummy + kTileSingle * 4);
+  L.bytes = al256(L.o_dummy + (uint64_t)kPzSlots * kTileSingle * 4);
   return L;
 }
 
@@ -836,11 +836,12 @@ static int launch_scan(const ScanParams& sp, const pfac_plan& plan, bool single,
   const int rc = scan_shape(sp, plan, single, tile, dev, &fn, &lds, &grid);
   if (rc) return rc;
   if (sp.defer && grid * (plan.block / 64) > sp.wq_waves) return PFAC_E_ARG;
-  // one-text deferred scans with a 16-byte aligned dense output: the
-  // pre-zeroing kernel, when it has the same occupancy (hence grid)
-  if (single && sp.defer && sp.match && sp.pz_dummy &&
-      (reinterpret_cast<uintptr_t>(sp.match) & 15) == 0 && !global_variant(plan.variant)) {
-    const ScanFn pz = pick_scan(plan.block, false, sp.D, true, true, tile, true);
+  // deferred-walk scans with a dense output (16-byte aligned for one text;
+  // a batch checks each text's): the pre-zeroing kernel, when it has the same
+  // occupancy (hence grid)
+  if (sp.defer && sp.match && sp.pz_dummy && !global_variant(plan.variant) &&
+      (!single || (reinterpret_cast<uintptr_t>(sp.match) & 15) == 0)) {
+    const ScanFn pz = pick_scan(plan.block, false, sp.D, single, true, tile, true);
     if (pz && blocks_per_cu(pz, plan.block, lds) == blocks_per_cu(fn, plan.block, lds)) fn = pz;
   }
   hipLaunchKernelGGL(fn, dim3((uint32_t)grid), dim3(plan.block), lds, stream, sp);
@@ -1558,6 +1559,7 @@ static int enqueue_batch(const BatchLayout& L, const Scratch& sc, const uint8_t*
       sp.wq_cap = G.wq_cap;
       sp.wq_waves = G.wq_waves;
     }
+    sp.pz_dummy = sc.dummy;
     const int rc = launch_scan(sp, L.plans[G.table], false, G.tile, dev, stream);
     if (rc) return rc;
   }

@@ -48,6 +48,9 @@ namespace pfac {
 constexpr uint32_t kTileSingle = 2048;
 constexpr uint32_t kTileBatch = 1024;
 constexpr uint32_t kTileShort = 256;
+// Scratch areas of pre-zeroing scans: one per workgroup slot (workgroup
+// index mod kPzSlots), kTileSingle int32 each.
+constexpr uint32_t kPzSlots = 256;
 constexpr uint32_t kQueue = 256;       // deep-walk queue entries per wave
 constexpr uint32_t kSlot = 32;         // hits parked per tile
 constexpr uint32_t kMaxHalo = 4096;    // longest halo staged in LDS (bases)
@@ -150,8 +153,8 @@ struct ScanParams {
   uint32_t wq_cap;
   WalkEntry* wq;
   uint64_t wq_waves;              // waves wq has room for
-  int32_t* pz_dummy;              // pre-zeroing kernels: kTileSingle int32 written in
-                                  // place of a tile that is not full
+  int32_t* pz_dummy;              // pre-zeroing kernels: kPzSlots areas of kTileSingle
+                                  // int32, written in place of a tile that is not full
 };
 
 // ---------------------------------------------------------------- device helpers
@@ -971,7 +974,7 @@ __device__ __forceinline__ T* in_vgpr(T* ptr) {
 
 template <int BLOCK, bool GLOBAL, int DT, bool SINGLE, bool DEFER, uint32_t TILE, bool PZ>
 __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p0) {
-  static_assert(!PZ || (SINGLE && DEFER && !GLOBAL), "pre-zeroing: one-text deferred scans");
+  static_assert(!PZ || (DEFER && !GLOBAL), "pre-zeroing: deferred-walk scans");
   ScanParams p = p0;
   p.next = in_vgpr(p0.next);
   p.out = in_vgpr(p0.out);
@@ -1085,19 +1088,25 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p0) {
   auto seg_match = [&](const TileLoc& L) -> int32_t* {
     return SINGLE ? p.match : p.match + L.seg.match_off;
   };
-  // pre-zeroing (one-text deferred scans with a 16-byte aligned dense
-  // output): a tile's output is zeroed right after its text loads are
-  // issued, and its few non-zero positions are written over it later (by
-  // the lanes that wrote the zeros, or after the wave's fence).  The eight
-  // stores sit in the same block as the loads, so they follow them on every
-  // path to the wait for the text, and that wait leaves them in flight
-  // (measured on the scan's traffic shape: 0.266 -> 0.239 ms).  Issued at the
-  // end of the iteration instead they measured slower (0.311 against 0.294 ms
-  // on the large-text scan).  A tile that is not full writes them to a
-  // scratch area instead.
+  // pre-zeroing (deferred-walk scans with a dense output): a tile's output
+  // is zeroed right after its text loads are issued, and its few non-zero
+  // positions are written over it later (by the lanes that wrote the zeros,
+  // or after the wave's fence).  The eight stores sit in the same block as
+  // the loads, so they follow them on every path to the wait for the text,
+  // and that wait leaves them in flight (measured on the scan's traffic
+  // shape: 0.266 -> 0.239 ms).  Issued at the end of the iteration instead
+  // they measured slower (0.311 against 0.294 ms on the large-text scan).  A
+  // tile that is not full, or whose output is not 16-byte aligned, writes
+  // them to the workgroup's scratch area instead (kTileSingle int32 per
+  // workgroup slot) and is written at its end as without pre-zeroing.
+  int32_t* const pz_own =
+      PZ ? p.pz_dummy + (uint64_t)(blockIdx.x & (kPzSlots - 1)) * kTileSingle : nullptr;
   auto prezero = [&](const TileLoc& L) {
     const uint64_t s0 = L.ts * TILE;
-    int32_t* zt = s0 + TILE <= p.seg0.n ? p.match + s0 : p.pz_dummy;
+    int32_t* const mb = SINGLE ? p.match : p.match + L.seg.match_off;
+    const bool ok = s0 + TILE <= seg_n(L) &&
+                    (SINGLE || (reinterpret_cast<uintptr_t>(mb) & 15) == 0);
+    int32_t* zt = ok ? mb + s0 : pz_own;
     const i32x4 z = {0, 0, 0, 0};
     #pragma unroll
     for (uint32_t g = 0; g < NG; ++g)
@@ -1462,7 +1471,7 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p0) {
         if (!((sel >> (4 * g)) & 1u)) continue;
         const uint32_t q0 = g * 256 + 4 * lane;
         if (!any) {
-          if (PZ && full) break;          // zeroed when its text was fetched
+          if (PZ && full && maligned) break;   // zeroed when its text was fetched
           if (DEFER && mt && passes == 1) {
             // the whole tile is zero: written with the next tile
             zmt = mt;

@@ -55,7 +55,8 @@ ScanFn PFAC_PICK(bool global, uint32_t D, bool defer, uint32_t tile, bool pz) {
     default: return nullptr;
   }
 #else
-  if (pz) return nullptr;
+  // pre-zeroing variants: deferred walks, 2048-position tiles
+  if (pz) return (!global && defer && tile == 2048) ? by_depth<true, 2048, true>(D) : nullptr;
   if (global) return (tile == kTileBatch && D == 0)
                         ? pfac_scan_kernel<PFAC_BLOCK, true, 0, false, false, kTileBatch, false>
                         : nullptr;
