@@ -572,7 +572,9 @@ def part_floor(pf, torch, args):
     """What the memory system gives for this traffic: plain fills and copies
     of 1 GiB by the runtime, and the probe kernel with the scan's exact
     access shape (a wave per 2048-position tile, 2 KB read, 8 KB written,
-    16-byte non-temporal accesses, 1024-thread workgroups, one per CU)."""
+    16-byte non-temporal accesses, 1024-thread workgroups, one per CU); the
+    last case issues each tile's loads before the previous tile's stores, so
+    the wait for them does not drain those stores."""
     from paper_1811_10498_amd import build as B
     dev = torch.device("cuda:0")
     a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
@@ -600,7 +602,8 @@ def part_floor(pf, torch, args):
              (2, 0, 0, "scan_shape_write_only_1GiB", 4 * n),
              (0, 1, 0, "scan_shape_plain_stores", 5 * n),
              (0, 2, 0, "scan_shape_plain_loads", 5 * n),
-             (0, 0, 512, "scan_shape_2_workgroups_per_cu", 5 * n)]
+             (0, 0, 512, "scan_shape_2_workgroups_per_cu", 5 * n),
+             (3, 0, 0, "scan_shape_stores_left_in_flight", 5 * n)]
     for mode, flags, grid, name, bytes_ in cases:
         fn = lambda: lib.pfac_probe_stream(src.data_ptr(), dst.data_ptr(), tiles, mode, flags,
                                            grid, sink.data_ptr(),

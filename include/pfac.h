@@ -308,7 +308,7 @@ uint64_t pfac_noalloc_scratch_bytes(void);
  *               [1] = total occurrences (the full list length, may exceed
  *               occ_cap: the caller can retry with a larger buffer)
  *   plan        NULL for the library's choice (as pfac_match)
- * Asynchronous on `stream`; scratch as in pfac_match, plus 8 bytes per tile.
+ * Asynchronous on `stream`; scratch as in pfac_match, plus 32 bytes per tile.
  */
 int pfac_match_all(const pfac_table* table, const void* d_text, uint64_t n, int enc,
                    pfac_hit* d_occ, uint64_t occ_cap, uint64_t* d_counters,

@@ -354,8 +354,9 @@ __global__ __launch_bounds__(256) void pfac_pair_kernel(const uint32_t* bitmap, 
   }
 }
 
-// Batch work items: one wave per text writes the items of its tiles,
-// {text index, tile index within the text}, from item_start[text] on.
+// Batch work items: one wave per text writes the items of its tiles (text
+// offsets, length and encoding, tile index in the call and in the text, text
+// index) from item_start[text] on.
 __global__ __launch_bounds__(256) void pfac_items_kernel(const DevSeg* segs,
                                                          const uint64_t* item_start,
                                                          uint32_t ntexts, TileItem* items) {
@@ -364,7 +365,9 @@ __global__ __launch_bounds__(256) void pfac_items_kernel(const DevSeg* segs,
   const DevSeg s = segs[t];
   const uint64_t tiles = ((uint64_t)s.n + (1u << s.tile_shift) - 1) >> s.tile_shift;
   TileItem* dst = items + item_start[t];
-  for (uint64_t j = threadIdx.x & 63; j < tiles; j += 64) dst[j] = TileItem{(uint32_t)t, (uint32_t)j};
+  for (uint64_t j = threadIdx.x & 63; j < tiles; j += 64)
+    dst[j] = TileItem{s.text_off, s.match_off, s.n, s.first_tile + (uint32_t)j, (uint32_t)j,
+                      (uint32_t)t | ((uint32_t)s.enc << 31)};
 }
 
 // ---------------------------------------------------------------- host side
@@ -1408,7 +1411,8 @@ constexpr uint64_t kFoldShort = 4096;
 static int layout_batch(const pfac_table* const* tables, uint32_t num_tables,
                         const pfac_text_desc* descs, uint32_t num_texts, const pfac_plan* plan,
                         int dev, BatchLayout* L) {
-  if (!tables || num_tables == 0 || (num_texts && !descs)) return PFAC_E_ARG;
+  if (!tables || num_tables == 0 || (num_texts && !descs) || num_texts >= (1u << 31))
+    return PFAC_E_ARG;
   for (uint32_t i = 0; i < num_tables; ++i)
     if (!tables[i] || tables[i]->device != dev || tables[i]->alphabet != 4) return PFAC_E_ARG;
   for (uint32_t s = 0; s < num_texts; ++s) {

@@ -75,8 +75,20 @@ struct DevSeg {
 };
 static_assert(sizeof(DevSeg) == 32, "descriptor layout");
 
-// One work item of a batched launch: text index, tile index within the text.
-typedef u32x2 TileItem;
+// One work item of a batched launch: everything a wave needs to start its
+// tile (the text's offsets, length and encoding, the tile's index within the
+// text and within the call, the text's index), so that locating the next
+// tile is one 32-byte load instead of an item load and a dependent
+// descriptor load.
+struct TileItem {
+  uint64_t text_off;
+  uint64_t match_off;
+  uint32_t n;
+  uint32_t gtile;       // tile index in the call
+  uint32_t ts;          // tile index within the text
+  uint32_t si_enc;      // text index in bits 0..30, encoding in bit 31
+};
+static_assert(sizeof(TileItem) == 32, "work item layout");
 
 struct Slot {
   uint32_t pos;
@@ -732,10 +744,10 @@ __device__ __forceinline__ TileLoc locate(const ScanParams& p, uint64_t lt) {
     L.gtile = lt;
   } else {
     const TileItem it = p.items[lt];
-    L.si = it.x;
-    L.seg = p.segs[it.x];
-    L.ts = it.y;
-    L.gtile = (uint64_t)L.seg.first_tile + it.y;
+    L.si = it.si_enc & 0x7FFFFFFFu;
+    L.seg = DevSeg{it.text_off, it.match_off, it.n, 0u, 0u, (uint16_t)(it.si_enc >> 31), 0};
+    L.ts = it.ts;
+    L.gtile = it.gtile;
   }
   return L;
 }
