@@ -625,7 +625,7 @@ static int device_build(pfac_table* t, const char* const* patterns, const uint32
     h.hash1_set[b] = big1 ? (uint32_t)hs[31 + (b - kHashMinBits)] : 0u;
   }
   h.pfx_set = L.pfx_words ? hs[30] : 0;
-  return build_pairs(t);
+  return build_derived(t);
 }
 
 // Check, then build on the device; pattern k gets ID ids[k].

@@ -354,6 +354,23 @@ __global__ __launch_bounds__(256) void pfac_pair_kernel(const uint32_t* bitmap, 
   }
 }
 
+// Node records of the deferred walks: per state its four edge words, its run
+// record and its output, 32 bytes, so that a walk step reads one record
+// (one cache line) instead of an edge word, a run record and an output in
+// three arrays.
+__global__ __launch_bounds__(256) void pfac_node_kernel(const uint32_t* next, const uint32_t* chain,
+                                                        const OutEntry* out, uint64_t S,
+                                                        uint32_t* node) {
+  for (uint64_t s = (uint64_t)blockIdx.x * 256 + threadIdx.x; s < S;
+       s += (uint64_t)gridDim.x * 256) {
+    const u32x4 a = reinterpret_cast<const u32x4*>(next)[s];
+    const OutEntry o = out[s];
+    const u32x4 b = {chain[2 * s], chain[2 * s + 1], (uint32_t)o.pid, o.mult};
+    reinterpret_cast<u32x4*>(node)[2 * s] = a;
+    reinterpret_cast<u32x4*>(node)[2 * s + 1] = b;
+  }
+}
+
 // Batch work items: one wave per text writes the items of its tiles (text
 // offsets, length and encoding, tile index in the call and in the text, text
 // index) from item_start[text] on.
@@ -906,6 +923,7 @@ static void fill_table(ScanParams& sp, const pfac_table* t, const pfac_plan& pl)
   sp.next = t->dev.next;
   sp.out = t->dev.out;
   sp.chain = t->dev.chain;
+  sp.node = reinterpret_cast<const u32x4*>(t->dev.node);
   if (pl.variant == PFAC_VARIANT_GLOBAL_TWO_ARRAYS || pl.variant == PFAC_VARIANT_GLOBAL_MERGED) {
     // the kernel's depth parameter names the layout for global variants
     sp.D = pl.variant == PFAC_VARIANT_GLOBAL_TWO_ARRAYS ? 1u : 2u;
@@ -990,6 +1008,7 @@ void table_layout(const HostTable& h, uint64_t ndups, TableLayout* L) {
   L->o_next = off; off = al256(off + S * 16);
   L->o_out = off; off = al256(off + S * sizeof(OutEntry));
   L->o_chain = off; off = al256(off + S * 8);
+  L->o_node = off; off = al256(off + S * 32);
   for (uint32_t D = kMinJump; D <= kMaxJump; ++D) {
     const uint64_t E = 1ull << (2 * D);
     const HostTable::Image& im = h.image[D];
@@ -1044,6 +1063,7 @@ int alloc_table(pfac_table* t, uint64_t ndups) {
   v.next = reinterpret_cast<const uint32_t*>(base + L.o_next);
   v.out = reinterpret_cast<const OutEntry*>(base + L.o_out);
   v.chain = reinterpret_cast<const uint32_t*>(base + L.o_chain);
+  v.node = reinterpret_cast<const uint32_t*>(base + L.o_node);
   v.pfx = L.pfx_words ? reinterpret_cast<const uint32_t*>(base + L.o_pfx) : nullptr;
   v.dup_state = reinterpret_cast<const uint32_t*>(base + L.o_dups);
   v.dup_id = reinterpret_cast<const int32_t*>(base + L.o_dupi);
@@ -1093,9 +1113,17 @@ int upload_host_table(pfac_table* t) {
   return ok ? PFAC_OK : PFAC_E_HIP;
 }
 
-// The pair tables of a table whose filter bitmaps are in its device
-// allocation (either build), derived on the device; synchronous.
-int build_pairs(pfac_table* t) {
+// The arrays derived from others in a table's device allocation (either
+// build): the node records and the pair tables; synchronous.
+int build_derived(pfac_table* t) {
+  const uint64_t S = t->host.num_states;
+  if (S) {
+    const uint64_t blocks = std::min<uint64_t>((S + 255) / 256, 65535);
+    hipLaunchKernelGGL(pfac_node_kernel, dim3((uint32_t)blocks), dim3(256), 0, nullptr,
+                       t->dev.next, t->dev.chain, t->dev.out, S,
+                       const_cast<uint32_t*>(t->dev.node));
+    if (hipGetLastError() != hipSuccess) return PFAC_E_HIP;
+  }
   for (uint32_t D = kMinJump; D <= kPairMaxDepth; ++D) {
     const uint32_t words = (1u << (2 * (D - 1))) / 4;
     hipLaunchKernelGGL(pfac_pair_kernel, dim3((words + 255) / 256), dim3(256), 0, nullptr,
@@ -1177,7 +1205,7 @@ int pfac_build_table(const char* const* patterns, const uint32_t* lengths, uint3
   rc = remember_patterns(t, patterns, lengths, num, nullptr);
   if (!rc) rc = alloc_table(t, t->host.dup_state.size());
   if (!rc) rc = upload_host_table(t);
-  if (!rc) rc = build_pairs(t);
+  if (!rc) rc = build_derived(t);
   if (rc) {
     if (t->dmem) (void)hipFree(t->dmem);
     delete t;

@@ -90,7 +90,7 @@ uint32_t device_cus(int dev);
 void table_layout(const HostTable& h, uint64_t ndups, TableLayout* L);
 int alloc_table(pfac_table* t, uint64_t ndups);
 int upload_host_table(pfac_table* t);
-int build_pairs(pfac_table* t);
+int build_derived(pfac_table* t);      // node records, pair tables
 int remember_patterns(pfac_table* t, const char* const* patterns, const uint32_t* lengths,
                       uint32_t num, const int32_t* ids);
 

@@ -161,6 +161,7 @@ struct DevTable {
   const uint32_t* hash[kHashMaxBits + 1]; // second-filter bitmaps
   const uint32_t* hash1[kHashMaxBits + 1]; // one-hash second-filter bitmaps (or null)
   const uint32_t* chain;                  // [2S] runs of single-child steps
+  const uint32_t* node;                   // [8S] per state: next[4], chain[2], out (pid, mult)
   const uint32_t* pfx;                    // prefix-filter bitmap (or null)
   const uint32_t* dup_state;              // further IDs of final states (HostTable)
   const int32_t* dup_id;
@@ -171,7 +172,7 @@ struct DevTable {
 
 // Offsets of a table's arrays in its one device allocation (table_layout).
 struct TableLayout {
-  uint64_t o_next = 0, o_out = 0, o_chain = 0;
+  uint64_t o_next = 0, o_out = 0, o_chain = 0, o_node = 0;
   uint64_t o_jump[kMaxJump + 1] = {}, o_jres[kMaxJump + 1] = {}, o_im[kMaxJump + 1] = {};
   uint64_t o_lv[kMaxJump + 1] = {};
   uint64_t o_pair[kMaxJump + 1] = {};

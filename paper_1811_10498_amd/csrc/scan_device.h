@@ -115,6 +115,7 @@ struct ScanParams {
   const uint32_t* next;
   const OutEntry* out;
   const uint32_t* chain;          // runs of single-child steps (TILED)
+  const u32x4* node;              // per state {next[4]}, {run record, output} (TILED)
   const uint32_t* jump;           // depth-D jump table (TILED)
   const OutEntry* jres;
   const uint32_t* image;          // LDS image of depth D (TILED): filter bitmap, its
@@ -763,8 +764,10 @@ __device__ __forceinline__ void put_counts(const ScanParams& p, uint64_t tile, u
 // The deferred walks of a wave, four per lane at a time: the depth-D jump
 // entry of each window, then the walk with path compression over the 64
 // bases copied with the entry (continued on the text in global memory past
-// them).  The four walks of a lane issue their table reads together, so each
-// step waits for one round trip instead of four.  A pattern found is written
+// them).  Each step reads the state's 32-byte node record (edge words, run
+// record, output: one cache line).  The four walks of a lane issue their
+// table reads together, so each step waits for one round trip instead of
+// four.  A pattern found is written
 // to the dense output and appended to its tile's hit slots (the finish
 // kernel orders each tile's slots by position).
 template <uint32_t D, bool SINGLE, uint32_t TILE>
@@ -803,31 +806,30 @@ __device__ __forceinline__ void deferred_walks(const ScanParams& p, const WalkEn
         ivlo[m] = ivhi[m] = 0;
       }
     }
-    // the jump entries of the windows (walks from the root start at state 0)
+    // the jump entries of the windows (walks from the root start at state 0);
+    // a state's output is read from its node record with its next step
+    bool fin[M];
     #pragma unroll
     for (int m = 0; m < M; ++m)
       if (valid[m] && !slow[m]) jj[m] = p.jump[c[m][0] >> (32 - 2 * D)];
     #pragma unroll
     for (int m = 0; m < M; ++m) {
       live[m] = valid[m];
+      fin[m] = false;
       if (valid[m] && !slow[m]) {
-        if (jj[m] & kFinalBit) {
-          const OutEntry o = p.jres[c[m][0] >> (32 - 2 * D)];
-          best[m] = o.pid;
-          occ[m] += o.mult;
-        }
         s[m] = jj[m] & kStateMask;
+        fin[m] = (jj[m] & kFinalBit) != 0;
         q[m] = D;
         live[m] = s[m] != 0;
       }
     }
     for (;;) {
       bool any = false;
-      u32x2 ch[M];
-      uint32_t e[M], win[M];
+      u32x4 nb[M];
+      uint32_t win[M], e[M];
       #pragma unroll
       for (int m = 0; m < M; ++m) {
-        ch[m] = u32x2{0u, 0u};
+        nb[m] = u32x4{0u, 0u, 0u, 0u};
         e[m] = 0;
         win[m] = 0;
         if (live[m] && q[m] < kWindow) {
@@ -835,18 +837,31 @@ __device__ __forceinline__ void deferred_walks(const ScanParams& p, const WalkEn
           const uint32_t hi = wk == 0 ? c[m][0] : wk == 1 ? c[m][1] : wk == 2 ? c[m][2] : c[m][3];
           const uint32_t lo = wk == 0 ? c[m][1] : wk == 1 ? c[m][2] : wk == 2 ? c[m][3] : 0u;
           win[m] = (uint32_t)(((((uint64_t)hi << 32) | lo) << sh) >> 32);
-          ch[m] = *reinterpret_cast<const u32x2*>(p.chain + 2ull * s[m]);
-          e[m] = p.next[(uint64_t)s[m] * 4 + (win[m] >> 30)];
+          // the state's node record: the edge word of the next base, the run
+          // record and the output (one cache line)
+          e[m] = reinterpret_cast<const uint32_t*>(p.node)[8ull * s[m] + (win[m] >> 30)];
+          nb[m] = p.node[2ull * s[m] + 1];
         }
       }
       #pragma unroll
       for (int m = 0; m < M; ++m) {
         if (!live[m]) continue;
         bool global = q[m] >= kWindow;
-        const uint32_t len = ch[m].x & 15u;
+        if (!global && fin[m]) {
+          best[m] = (int32_t)nb[m].z;
+          occ[m] += nb[m].w;
+          fin[m] = false;
+        }
+        const uint32_t len = nb[m].x & 15u;
         if (!global && len >= 2 && q[m] + len > kWindow) global = true;
         if (global) {
           // past the copied bases: go on reading the text itself
+          if (fin[m]) {
+            const OutEntry o = p.out[s[m]];
+            best[m] = o.pid;
+            occ[m] += o.mult;
+            fin[m] = false;
+          }
           const uint8_t* text;
           uint64_t n;
           uint32_t enc;
@@ -864,28 +879,20 @@ __device__ __forceinline__ void deferred_walks(const ScanParams& p, const WalkEn
         const uint64_t ivall = ((uint64_t)ivhi[m] << 32) | ivlo[m];
         const uint32_t ivw = (uint32_t)(ivall >> q[m]);
         if (len >= 2) {
-          if ((ivw & ((1u << len) - 1u)) | ((win[m] ^ ch[m].x) & (0xFFFFFFFFu << (32 - 2 * len)))) {
+          if ((ivw & ((1u << len) - 1u)) | ((win[m] ^ nb[m].x) & (0xFFFFFFFFu << (32 - 2 * len)))) {
             live[m] = false;
             continue;
           }
-          s[m] = ch[m].y & kStateMask;
+          s[m] = nb[m].y & kStateMask;
+          fin[m] = (nb[m].y & kFinalBit) != 0;
           q[m] += len;
-          if (ch[m].y & kFinalBit) {
-            const OutEntry o = p.out[s[m]];
-            best[m] = o.pid;
-            occ[m] += o.mult;
-          }
         } else {
           if ((ivw & 1u) || e[m] == 0) {
             live[m] = false;
             continue;
           }
           s[m] = e[m] & kStateMask;
-          if (e[m] & kFinalBit) {
-            const OutEntry o = p.out[s[m]];
-            best[m] = o.pid;
-            occ[m] += o.mult;
-          }
+          fin[m] = (e[m] & kFinalBit) != 0;
           ++q[m];
         }
         any = true;
@@ -991,6 +998,7 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p0) {
   p.next = in_vgpr(p0.next);
   p.out = in_vgpr(p0.out);
   p.chain = in_vgpr(p0.chain);
+  if (SINGLE) p.node = in_vgpr(p0.node);   // (batch kernels: no vector registers to spare)
   p.jump = in_vgpr(p0.jump);
   p.jres = in_vgpr(p0.jres);
   p.pfx = in_vgpr(p0.pfx);
