@@ -452,8 +452,9 @@ def part_c3(pf, torch, args, plan, tune=False):
                              "gbases_per_s": round(total / t_plain / 1e9, 2)}
     out["speedup_vs_per_text_calls"] = round(t_plain / (ms / 1e3), 2)
     out["vs_one_text_kernel"] = round(jms / ms, 3)
-    out["plan"] = use if use is not None else "library choice (per text: 256-position tiles " \
-                                              "up to 512 bases, else 2048)"
+    out["plan"] = use if use is not None else (
+        "library choice (2048-position tiles; 256 for texts up to 512 bases when a table "
+        "has 4096 or more of them)")
     b.close()
     return out
 

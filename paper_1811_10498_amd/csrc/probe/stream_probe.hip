@@ -45,11 +45,13 @@ __global__ __launch_bounds__(1024) void stream_probe_kernel(const uint8_t* src, 
 // Mode 0 with the next tile's loads issued before this tile's stores: the
 // wait for those loads then leaves the stores in flight (vmcnt(8)) instead
 // of draining them (the vector-memory counter of gfx950 retires loads and
-// stores in issue order).
+// stores in issue order).  Tiles are handed out as in the scan: wave w of
+// workgroup b starts at tile w*G + b (G workgroups), so neighbouring tiles
+// belong to neighbouring workgroups.
 __global__ __launch_bounds__(1024) void stream_probe_pipelined(const uint8_t* src, int32_t* dst,
                                                                uint64_t tiles, uint32_t* sink) {
   const uint32_t lane = threadIdx.x & 63;
-  const uint64_t wave = (uint64_t)blockIdx.x * 16 + (threadIdx.x >> 6);
+  const uint64_t wave = (uint64_t)(threadIdx.x >> 6) * gridDim.x + blockIdx.x;
   const uint64_t nwaves = (uint64_t)gridDim.x * 16;
   if (wave >= tiles) return;
   uint32_t acc = 0;

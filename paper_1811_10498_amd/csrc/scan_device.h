@@ -342,40 +342,36 @@ __device__ __forceinline__ void walk_cells(uint64_t q, const ScanParams& p, cons
 // single-child steps (chain record, see the table layout) the next bases are
 // compared with the whole run at once -- all of them match and the walk jumps
 // to the end of the run, or the walk ends inside it, where no pattern ends.
-// The run record and the ordinary edge for the next base are loaded together,
-// so a step costs one round trip either way.
+// A step reads the state's node record: the edge word of the next base and
+// the run record with the state's output, from one cache line, so a step
+// costs one round trip either way.  `fin`: s is final and its output is
+// still to be counted (it comes with s's record).
 __device__ __forceinline__ void walk_lds(uint32_t s, uint32_t q, const uint32_t* __restrict__ pk,
                                          const uint32_t* __restrict__ iv,
-                                         const uint32_t* __restrict__ next,
-                                         const OutEntry* __restrict__ out,
-                                         const uint32_t* __restrict__ chain, int32_t& best,
-                                         unsigned long long& occ) {
+                                         const u32x4* __restrict__ node, bool fin,
+                                         int32_t& best, unsigned long long& occ) {
   for (;;) {
     // validity bits and codes of the 16 bases from q (first base on top)
     const uint32_t ivw = __builtin_amdgcn_alignbit(iv[(q >> 5) + 1], iv[q >> 5], q & 31u);
     const uint32_t win =
         (uint32_t)(((((uint64_t)pk[q >> 4] << 32) | pk[(q >> 4) + 1]) << (2 * (q & 15u))) >> 32);
-    const u32x2 ch = *reinterpret_cast<const u32x2*>(chain + 2ull * s);
-    const uint32_t e = next[(uint64_t)s * 4 + (win >> 30)];
-    const uint32_t len = ch.x & 15u;
+    const u32x4 nb = node[2ull * s + 1];
+    const uint32_t e = reinterpret_cast<const uint32_t*>(node)[8ull * s + (win >> 30)];
+    if (fin) {
+      best = (int32_t)nb.z;
+      occ += nb.w;
+    }
+    const uint32_t len = nb.x & 15u;
     if (len >= 2) {
-      if ((ivw & ((1u << len) - 1u)) | ((win ^ ch.x) & (0xFFFFFFFFu << (32 - 2 * len)))) break;
-      s = ch.y & kStateMask;
+      if ((ivw & ((1u << len) - 1u)) | ((win ^ nb.x) & (0xFFFFFFFFu << (32 - 2 * len)))) break;
+      s = nb.y & kStateMask;
+      fin = (nb.y & kFinalBit) != 0;
       q += len;
-      if (ch.y & kFinalBit) {
-        const OutEntry o = out[s];
-        best = o.pid;
-        occ += o.mult;
-      }
       continue;
     }
     if ((ivw & 1u) || e == 0) break;
     s = e & kStateMask;
-    if (e & kFinalBit) {
-      const OutEntry o = out[s];
-      best = o.pid;
-      occ += o.mult;
-    }
+    fin = (e & kFinalBit) != 0;
     ++q;
   }
 }
@@ -411,11 +407,10 @@ __device__ __forceinline__ int32_t deep_walk(uint32_t e, uint32_t D, uint32_t ld
                                              const uint32_t* bmpre, const u32x4* lvl,
                                              const uint32_t* __restrict__ pk,
                                              const uint32_t* __restrict__ iv,
-                                             const uint32_t* __restrict__ next,
+                                             const u32x4* __restrict__ node,
                                              const OutEntry* __restrict__ out,
                                              const uint32_t* __restrict__ jump,
                                              const OutEntry* __restrict__ jres,
-                                             const uint32_t* __restrict__ chain,
                                              unsigned long long& occ) {
   const uint32_t qt = e & 0x7FFFu;
   int32_t best = 0;
@@ -457,6 +452,8 @@ __device__ __forceinline__ int32_t deep_walk(uint32_t e, uint32_t D, uint32_t ld
       }
       s = L.z + j;
     } else {
+      // the state after D steps; the finals passed on the way (the jump
+      // entry's output: the longest ID and every occurrence) are counted here
       const uint32_t jj = jump[x];
       if (jj & kFinalBit) {
         const OutEntry o = jres[x];
@@ -467,7 +464,7 @@ __device__ __forceinline__ int32_t deep_walk(uint32_t e, uint32_t D, uint32_t ld
       if (!s) return best;
     }
   }
-  walk_lds(s, q, pk, iv, next, out, chain, best, occ);
+  walk_lds(s, q, pk, iv, node, false, best, occ);
   return best;
 }
 
@@ -806,8 +803,10 @@ __device__ __forceinline__ void deferred_walks(const ScanParams& p, const WalkEn
         ivlo[m] = ivhi[m] = 0;
       }
     }
-    // the jump entries of the windows (walks from the root start at state 0);
-    // a state's output is read from its node record with its next step
+    // the jump entries of the windows (walks from the root start at state 0):
+    // the finals passed within the first D bases come with the entry's
+    // output; every later state's output is read from its node record with
+    // its next step
     bool fin[M];
     #pragma unroll
     for (int m = 0; m < M; ++m)
@@ -817,8 +816,12 @@ __device__ __forceinline__ void deferred_walks(const ScanParams& p, const WalkEn
       live[m] = valid[m];
       fin[m] = false;
       if (valid[m] && !slow[m]) {
+        if (jj[m] & kFinalBit) {
+          const OutEntry o = p.jres[c[m][0] >> (32 - 2 * D)];
+          best[m] = o.pid;
+          occ[m] += o.mult;
+        }
         s[m] = jj[m] & kStateMask;
-        fin[m] = (jj[m] & kFinalBit) != 0;
         q[m] = D;
         live[m] = s[m] != 0;
       }
@@ -1475,8 +1478,8 @@ __global__ __launch_bounds__(BLOCK) void pfac_scan_kernel(ScanParams p0) {
           else
             walk<true>(0u, t0 + qt, nullptr, nullptr, p.next, p.out, text, n, enc, best, occ);
         } else {
-          best = deep_walk(e, D, p.lds_trie, p.levels, lds, bmpre, lvl, pk, iv, p.next, p.out,
-                           p.jump, p.jres, p.chain, occ);
+          best = deep_walk(e, D, p.lds_trie, p.levels, lds, bmpre, lvl, pk, iv, p.node, p.out,
+                           p.jump, p.jres, occ);
         }
         res[i] = best;
         nz |= (uint32_t)best;

@@ -8,7 +8,9 @@ reach:
   scan without pre-zeroing), with a ragged last tile;
 * a large pattern set with K = 12 (the one-hash second filter) on ASCII text
   with non-bases and lower case, so that tiles holding them test the filter
-  entry by entry instead of while classifying.
+  entry by entry instead of while classifying;
+* walks kept for the end of the wave (and walks at once) with patterns
+  shorter than the filter depth, whose finals lie within the jump.
 
 Every text is compared with the oracle position by position, with its hit
 count and its occurrence total."""
@@ -101,3 +103,34 @@ def test_one_hash_filter_on_text_with_non_bases():
     torch.cuda.synchronize()
     assert r2.num_hits() == pos.size and r2.total() == total_ref
     assert np.array_equal(r2.hit_list()[:, 0], pos)
+
+
+def test_deferred_walks_with_patterns_shorter_than_the_filter_depth():
+    """Walks kept for the end of the wave on a set with patterns of 3..12
+    bases: the depth-D jump entry then passes finals on the way (or leads to
+    no state at all past a short pattern), which the deferred and the inline
+    walks both count from the jump table's output."""
+    g = W.rng(95)
+    n = 1 << 20
+    text = W.uniform_ascii(n, g).copy()
+    pats = W.random_patterns(300, 3, 12, g) + W.cut_patterns(text, 200, 5, 30, g)
+    text[g.choice(n, size=2000, replace=False)] = ord("N")
+    tab = pf.Table(pats)
+    m_ref, total_ref = oracle.scan(pats, text, threads=16)
+    pos, ids = oracle.hits_of(m_ref)
+    dt = torch.from_numpy(text).to(DEV)
+    for plan in ({"walks": pf.PFAC_WALKS_DEFERRED},
+                 {"walks": pf.PFAC_WALKS_DEFERRED, "depth": 6},
+                 {"walks": pf.PFAC_WALKS_DEFERRED, "depth": 10, "levels": pf.PFAC_LEVELS_NONE},
+                 {"walks": pf.PFAC_WALKS_INLINE, "depth": 9, "levels": pf.PFAC_LEVELS_NONE}):
+        print("plan", plan, flush=True)
+        r = pf.match(tab, dt, hit_cap=pos.size + 64, plan=plan)
+        torch.cuda.synchronize()
+        assert np.array_equal(r.match.cpu().numpy(), m_ref), plan
+        assert r.num_hits() == pos.size and r.total() == total_ref, plan
+        h = r.hit_list()
+        assert np.array_equal(h[:, 0], pos) and np.array_equal(h[:, 1], ids), plan
+        r2 = pf.match(tab, dt, hit_cap=pos.size + 64, plan=plan, dense=False)
+        torch.cuda.synchronize()
+        assert r2.num_hits() == pos.size and r2.total() == total_ref, plan
+        assert np.array_equal(r2.hit_list()[:, 1], ids), plan
