@@ -96,6 +96,9 @@ class Request:
     completed: float = -1.0
     result: Optional["RequestResult"] = None
     ready: Optional[torch.cuda.Event] = None   # device texts: written by the submitter's stream
+    # sizes derived from the texts, computed once (a request's texts do not
+    # change while it is served)
+    _memo: dict = field(default_factory=dict, repr=False, compare=False)
 
     def segments(self):
         """(buffer, offsets, lengths) runs of the request's texts, in order."""
@@ -108,7 +111,9 @@ class Request:
     def lengths(self) -> np.ndarray:
         if isinstance(self.texts, TextBatch):
             return self.texts.lengths
-        return np.array([_nbytes(t) for t in self.texts], dtype=np.int64)
+        if "lengths" not in self._memo:
+            self._memo["lengths"] = np.array([_nbytes(t) for t in self.texts], dtype=np.int64)
+        return self._memo["lengths"]
 
     @property
     def num_texts(self) -> int:
@@ -119,7 +124,9 @@ class Request:
 
     @property
     def bases(self) -> int:
-        return int(self.lengths.sum())
+        if "bases" not in self._memo:
+            self._memo["bases"] = int(self.lengths.sum())
+        return self._memo["bases"]
 
     def host_text_bytes(self) -> int:
         """Bytes its host texts take once copied (16-byte aligned runs)."""
@@ -132,6 +139,11 @@ class Request:
     def device_bytes(self) -> int:
         """What a dispatch allocates for the request: its copied host texts,
         its dense match arrays, its hit slots (12 bytes each) and counters."""
+        if "device_bytes" not in self._memo:
+            self._memo["device_bytes"] = self._device_bytes()
+        return self._memo["device_bytes"]
+
+    def _device_bytes(self) -> int:
         L_ = self.lengths
         return (self.host_text_bytes() + 4 * int(((L_ + 3) // 4 * 4).sum())
                 + 12 * hit_cap_of(L_) + 16 * (int(L_.size) + 1))
@@ -408,20 +420,30 @@ class Server:
         for r in reqs:
             if r.ready is not None:
                 stream.wait_event(r.ready)
-        first, lens, tids = [], [], []
-        ntext = 0
-        for r in reqs:
-            first.append(ntext)
-            ntext += r.num_texts
-            lens.append(r.lengths)
-            tids.append(np.full(r.num_texts, r.table, dtype=np.uint32))
-        lengths = np.concatenate(lens).astype(np.int64)
-        tids = np.concatenate(tids)
         addrs, hold = self._texts(reqs, stream)
-        cap = sum(hit_cap_of(r.lengths) for r in reqs)
-        # each text's output starts at a multiple of 4 elements (16-byte stores)
-        match_offsets = match_layout(lengths).astype(np.int64)
-        extent = int(match_offsets[-1] + lengths[-1]) if ntext else 0
+        # a one-request dispatch of a shape seen before: its prepared batch,
+        # with the layout arrays computed when it was made
+        sig = b = None
+        if len(reqs) == 1 and reqs[0].num_texts > 0:
+            sig, base, rel = self._signature(reqs[0], addrs)
+            b = self._prepared.get((sig, si))
+        if b is not None:
+            lengths, tids, cap, match_offsets, extent = b.shape
+            first, ntext = [0], int(lengths.size)
+        else:
+            first, lens, tids = [], [], []
+            ntext = 0
+            for r in reqs:
+                first.append(ntext)
+                ntext += r.num_texts
+                lens.append(r.lengths)
+                tids.append(np.full(r.num_texts, r.table, dtype=np.uint32))
+            lengths = np.concatenate(lens).astype(np.int64)
+            tids = np.concatenate(tids)
+            cap = sum(hit_cap_of(r.lengths) for r in reqs)
+            # each text's output starts at a multiple of 4 elements (16-byte stores)
+            match_offsets = match_layout(lengths).astype(np.int64)
+            extent = int(match_offsets[-1] + lengths[-1]) if ntext else 0
         dev = self.device
         mt = torch.empty(max(1, extent), dtype=torch.int32, device=dev)
         hits = torch.empty((cap, 3), dtype=torch.int32, device=dev)
@@ -429,12 +451,8 @@ class Server:
         if self.trace is not None:
             ev_start = torch.cuda.Event(enable_timing=True)
             ev_start.record(stream)
-        sig = None
-        if len(reqs) == 1 and ntext > 0:
-            sig, base, rel = self._signature(reqs[0], addrs)
         key = None if sig is None else (sig, si)
-        if key is not None and key in self._prepared:
-            b = self._prepared[key]
+        if b is not None:
             self._prepared.move_to_end(key)
             self.prepared_hits += 1
             with torch.cuda.stream(stream):
@@ -457,7 +475,7 @@ class Server:
                     stream.cuda_stream)
             L.check(rc, "pfac_match_batch")
             if key is not None:
-                self._prepare(key, descs, ntext)
+                self._prepare(key, descs, ntext, (lengths, tids, cap, match_offsets, extent))
         if self.trace is not None:
             ev_end = torch.cuda.Event(enable_timing=True)
             ev_end.record(stream)
@@ -533,9 +551,11 @@ class Server:
             del self._prepared[k]                 # prepared batches name the old table
         return new
 
-    def _prepare(self, key, descs, ntext):
+    def _prepare(self, key, descs, ntext, shape):
         """Keep a prepared batch for a one-request dispatch shape (offsets
-        relative to the request's first text)."""
+        relative to the request's first text), with the dispatch's layout
+        arrays (`shape`: lengths, table indices, hit capacity, output
+        offsets, output extent)."""
         h = ctypes.c_void_p()
         pl = ctypes.byref(self._plan) if self._plan is not None else None
         rc = self._lib.pfac_batch_create(ctypes.cast(self._tabs, ctypes.c_void_p),
@@ -543,7 +563,7 @@ class Server:
                                          ctypes.byref(h))
         if rc != 0:
             return
-        self._prepared[key] = _Prepared(self._lib, h)
+        self._prepared[key] = _Prepared(self._lib, h, shape)
         while len(self._prepared) > self._prepared_cap:
             self._prepared.popitem(last=False)
 
@@ -698,9 +718,10 @@ class _Prepared:
     """A prepared batch kept for a dispatch shape (its own scratch and
     layout; outputs are passed per launch)."""
 
-    def __init__(self, lib, handle):
+    def __init__(self, lib, handle, shape):
         self._lib = lib
         self.handle = handle
+        self.shape = shape
 
     def __del__(self):
         try:
