@@ -289,6 +289,7 @@ class Server:
         self.max_seen_inflight = 0
         self.dispatch_sizes: List[int] = []
         self.prepared_hits = 0
+        self._events: List[torch.cuda.Event] = []
         self._prepared: "collections.OrderedDict" = collections.OrderedDict()
         self._prepared_cap = int(prepared_cache)
         # with `trace`, every dispatch's device interval: timing events recorded
@@ -455,9 +456,8 @@ class Server:
         if b is not None:
             self._prepared.move_to_end(key)
             self.prepared_hits += 1
-            with torch.cuda.stream(stream):
-                rc = self._lib.pfac_batch_launch(b.handle, base, mt.data_ptr(), hits.data_ptr(),
-                                                 cap, counters.data_ptr(), stream.cuda_stream)
+            rc = self._lib.pfac_batch_launch(b.handle, base, mt.data_ptr(), hits.data_ptr(),
+                                             cap, counters.data_ptr(), stream.cuda_stream)
             L.check(rc, "pfac_batch_launch")
         else:
             base = int(addrs.min()) if ntext else 0
@@ -468,11 +468,10 @@ class Server:
             descs["table"][:ntext] = tids
             descs["enc"][:ntext] = ENCODINGS["ascii"]
             pl = ctypes.byref(self._plan) if self._plan is not None else None
-            with torch.cuda.stream(stream):
-                rc = self._lib.pfac_match_batch(
-                    ctypes.cast(self._tabs, ctypes.c_void_p), len(self.tables), descs.ctypes.data,
-                    ntext, base, mt.data_ptr(), hits.data_ptr(), cap, counters.data_ptr(), pl,
-                    stream.cuda_stream)
+            rc = self._lib.pfac_match_batch(
+                ctypes.cast(self._tabs, ctypes.c_void_p), len(self.tables), descs.ctypes.data,
+                ntext, base, mt.data_ptr(), hits.data_ptr(), cap, counters.data_ptr(), pl,
+                stream.cuda_stream)
             L.check(rc, "pfac_match_batch")
             if key is not None:
                 self._prepare(key, descs, ntext, (lengths, tids, cap, match_offsets, extent))
@@ -483,8 +482,8 @@ class Server:
         host_c = torch.empty(counters.numel(), dtype=torch.int64, pin_memory=True)
         with torch.cuda.stream(stream):
             host_c.copy_(counters, non_blocking=True)
-            ev = torch.cuda.Event()
-            ev.record(stream)
+        ev = self._event()
+        ev.record(stream)
         t = self.now()
         for r in reqs:
             r.dispatched = t
@@ -516,10 +515,9 @@ class Server:
         pl = ctypes.byref(self._plan) if self._plan is not None else None
         addr = int(addrs[0])
         tab = self.tables[r.table]
-        with torch.cuda.stream(stream):
-            rc = self._lib.pfac_match(tab.handle, addr, n, ENCODINGS["ascii"], mt.data_ptr(),
-                                      hits.data_ptr(), cap, counters.data_ptr(), pl,
-                                      stream.cuda_stream)
+        rc = self._lib.pfac_match(tab.handle, addr, n, ENCODINGS["ascii"], mt.data_ptr(),
+                                  hits.data_ptr(), cap, counters.data_ptr(), pl,
+                                  stream.cuda_stream)
         L.check(rc, "pfac_match")
         if self.trace is not None:
             ev_end = torch.cuda.Event(enable_timing=True)
@@ -528,8 +526,8 @@ class Server:
         host_c = torch.empty(2, dtype=torch.int64, pin_memory=True)
         with torch.cuda.stream(stream):
             host_c.copy_(counters, non_blocking=True)
-            ev = torch.cuda.Event()
-            ev.record(stream)
+        ev = self._event()
+        ev.record(stream)
         r.dispatched = self.now()
         self.busy[si] += 1
         hold.append(tab)
@@ -653,11 +651,17 @@ class Server:
         self.done.append(r)
         self.busy[d.stream_idx] -= 1
 
+    def _event(self) -> torch.cuda.Event:
+        """A completion event from the pool (events of completed dispatches
+        are recorded again)."""
+        return self._events.pop() if self._events else torch.cuda.Event()
+
     def _complete(self):
         still = []
         for d in self.inflight:
             if d.event.query():
                 self._finish(d)
+                self._events.append(d.event)
             else:
                 still.append(d)
         self.inflight = still
