@@ -107,8 +107,10 @@ typedef struct {
                            used when every pattern has more than D bases: their first
                            K = min(shortest pattern, 16) bases hashed twice into an
                            LDS bitmap of 2^hash_bits bits (12..20); only windows whose
-                           two bits are set walk on.  0 = library choice,
-                           PFAC_HASH_NONE = no second filter */
+                           two bits are set walk on (for K <= 12 and sets that let
+                           more than 30 % of windows through the depth-D filter:
+                           hashed once, see pfac_build_host_hash1).  0 = library
+                           choice, PFAC_HASH_NONE = no second filter */
   uint32_t walks;       /* where the walks that pass the filters run:
                            PFAC_WALKS_INLINE = by the wave that found them, with the
                            tile; PFAC_WALKS_DEFERRED = the wave keeps each one (start
