@@ -145,8 +145,9 @@ class Request:
 
     def _device_bytes(self) -> int:
         L_ = self.lengths
-        return (self.host_text_bytes() + 4 * int(((L_ + 3) // 4 * 4).sum())
-                + 12 * hit_cap_of(L_) + 16 * (int(L_.size) + 1))
+        padded = self.bases + int(((-L_) & 3).sum())     # runs padded to 4 elements
+        cap = self.bases // 16 + 64 * int(L_.size)       # hit_cap_of(L_)
+        return self.host_text_bytes() + 4 * padded + 12 * cap + 16 * (int(L_.size) + 1)
 
 
 @dataclass
@@ -242,6 +243,7 @@ class _Dispatch:
     lengths: np.ndarray
     args: tuple                      # what a retry with a larger hit buffer needs
     hold: list = field(default_factory=list)   # staging / device texts kept alive
+    prepared: Optional["_Prepared"] = None     # the prepared batch it launched
 
 
 class Server:
@@ -272,6 +274,11 @@ class Server:
             from .matcher import _plan_struct
             self._plan = _plan_struct(plan)
         self.device = torch.device(device or "cuda")
+        if self.device.index is None:
+            # an explicit index: torch resolves the current device on every
+            # call that is given a device without one
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        self._dev = self.device.index
         n = max(1, min(int(streams), MAX_STREAMS))
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n)]
         # dispatches in flight per stream: a long one-text launch fills the
@@ -306,14 +313,17 @@ class Server:
         completes; the dispatch waits for the work the submitting stream has
         queued so far (the producer of those texts)."""
         for b, o, n in req.segments():
-            live = n > 0
-            if np.any(live) and int((o + n)[live].max()) > _nbytes(b):
+            if not o.size:
+                continue
+            end = o + n
+            if int(end.max()) > _nbytes(b) and int(end[n > 0].max(initial=0)) > _nbytes(b):
+                # (empty texts may sit anywhere)
                 raise ValueError("request %d: a text runs past the end of its buffer" % req.rid)
             if torch.is_tensor(b) and (b.dtype != torch.uint8 or not b.is_contiguous()):
                 raise TypeError("request %d: texts must be contiguous uint8" % req.rid)
         if any(_on_device(b) for b, _, _ in req.segments()):
             req.ready = torch.cuda.Event()
-            req.ready.record(torch.cuda.current_stream(self.device))
+            req.ready.record(torch.cuda.current_stream(self._dev))
         self.gate.offer(req)
 
     def _admit(self):
@@ -327,6 +337,9 @@ class Server:
         """Per text of the dispatch: absolute device address; host texts are
         copied through one pinned buffer into one device buffer."""
         segs = [s for r in reqs for s in r.segments()]
+        if len(segs) == 1 and _on_device(segs[0][0]):
+            b, o, _ = segs[0]
+            return o.view(np.uint64) + np.uint64(b.data_ptr()), [b]
         host = [(b, o, n) for b, o, n in segs if not _on_device(b)]
         hold = []
         dev_buf = None
@@ -345,8 +358,7 @@ class Server:
             for i, (dst, lo, hi) in spans.items():
                 sv[dst:dst + hi - lo] = segs[i][0][lo:hi]
             dev_buf = torch.empty(total, dtype=torch.uint8, device=self.device)
-            with torch.cuda.stream(stream):
-                dev_buf.copy_(staging, non_blocking=True)
+            self._on_stream(stream, dev_buf.copy_, staging, non_blocking=True)
             hold += [staging, dev_buf]
         addrs = []
         for i, (b, o, n) in enumerate(segs):
@@ -362,7 +374,7 @@ class Server:
 
     def _signature(self, r: Request, addrs: np.ndarray):
         base = int(addrs.min()) if addrs.size else 0
-        rel = (addrs - np.uint64(base)).astype(np.int64)
+        rel = (addrs - np.uint64(base)).view(np.int64)
         L_ = r.lengths
         return (r.table, int(L_.size), _digest(L_), _digest(rel)), base, rel
 
@@ -427,7 +439,7 @@ class Server:
         sig = b = None
         if len(reqs) == 1 and reqs[0].num_texts > 0:
             sig, base, rel = self._signature(reqs[0], addrs)
-            b = self._prepared.get((sig, si))
+            b = self._instance(sig, si)
         if b is not None:
             lengths, tids, cap, match_offsets, extent = b.shape
             first, ntext = [0], int(lengths.size)
@@ -452,10 +464,12 @@ class Server:
         if self.trace is not None:
             ev_start = torch.cuda.Event(enable_timing=True)
             ev_start.record(stream)
-        key = None if sig is None else (sig, si)
         if b is not None:
-            self._prepared.move_to_end(key)
+            self._prepared.move_to_end(sig)
             self.prepared_hits += 1
+            b.busy += 1
+            b.si = si
+            hold.append(b)              # kept until the launch completes, even if evicted
             rc = self._lib.pfac_batch_launch(b.handle, base, mt.data_ptr(), hits.data_ptr(),
                                              cap, counters.data_ptr(), stream.cuda_stream)
             L.check(rc, "pfac_batch_launch")
@@ -473,15 +487,14 @@ class Server:
                 ntext, base, mt.data_ptr(), hits.data_ptr(), cap, counters.data_ptr(), pl,
                 stream.cuda_stream)
             L.check(rc, "pfac_match_batch")
-            if key is not None:
-                self._prepare(key, descs, ntext, (lengths, tids, cap, match_offsets, extent))
+            if sig is not None:
+                self._prepare(sig, descs, ntext, (lengths, tids, cap, match_offsets, extent))
         if self.trace is not None:
             ev_end = torch.cuda.Event(enable_timing=True)
             ev_end.record(stream)
             self.trace.append((si, ev_start, ev_end, len(reqs)))
         host_c = torch.empty(counters.numel(), dtype=torch.int64, pin_memory=True)
-        with torch.cuda.stream(stream):
-            host_c.copy_(counters, non_blocking=True)
+        self._on_stream(stream, host_c.copy_, counters, non_blocking=True)
         ev = self._event()
         ev.record(stream)
         t = self.now()
@@ -492,7 +505,7 @@ class Server:
         # table replaced meanwhile is freed after its last dispatch)
         hold.append(list(self.tables))
         self.inflight.append(_Dispatch(reqs, si, ev, host_c, mt, hits, counters, first,
-                                       match_offsets, lengths, (addrs, tids, stream), hold))
+                                       match_offsets, lengths, (addrs, tids, stream), hold, b))
         self.max_seen_inflight = max(self.max_seen_inflight, len(self.inflight))
         self.dispatch_sizes.append(len(reqs))
         return True
@@ -524,8 +537,7 @@ class Server:
             ev_end.record(stream)
             self.trace.append((si, ev_start, ev_end, 1))
         host_c = torch.empty(2, dtype=torch.int64, pin_memory=True)
-        with torch.cuda.stream(stream):
-            host_c.copy_(counters, non_blocking=True)
+        self._on_stream(stream, host_c.copy_, counters, non_blocking=True)
         ev = self._event()
         ev.record(stream)
         r.dispatched = self.now()
@@ -545,23 +557,39 @@ class Server:
         new = self.tables[index].update(add=add, remove_ids=remove_ids)
         self.tables[index] = new
         self._tabs = (ctypes.c_void_p * len(self.tables))(*[t.handle.value for t in self.tables])
-        for k in [k for k in self._prepared if k[0][0] == index]:
+        for k in [k for k in self._prepared if k[0] == index]:
             del self._prepared[k]                 # prepared batches name the old table
         return new
 
-    def _prepare(self, key, descs, ntext, shape):
+    def _instance(self, sig, si: int) -> Optional["_Prepared"]:
+        """A prepared batch of dispatch shape `sig` that stream `si` may
+        launch now: one with no launch in flight, or whose launches in flight
+        are on `si` (the stream orders them; a prepared batch's scratch is
+        its own, so two streams must not run one at once)."""
+        for b in self._prepared.get(sig, ()):
+            if b.busy == 0 or b.si == si:
+                return b
+        return None
+
+    def _prepare(self, sig, descs, ntext, shape):
         """Keep a prepared batch for a one-request dispatch shape (offsets
         relative to the request's first text), with the dispatch's layout
         arrays (`shape`: lengths, table indices, hit capacity, output
-        offsets, output extent)."""
-        h = ctypes.c_void_p()
+        offsets, output extent).  A shape gets one for each stream that runs
+        such dispatches when it is first seen, so that it can be in flight on
+        all of them at once without a later create (about 0.6 ms each, with
+        allocations and a synchronisation)."""
+        insts = self._prepared.setdefault(sig, [])
+        want = max(1, len(self.streams) - 1)
         pl = ctypes.byref(self._plan) if self._plan is not None else None
-        rc = self._lib.pfac_batch_create(ctypes.cast(self._tabs, ctypes.c_void_p),
-                                         len(self.tables), descs.ctypes.data, ntext, pl,
-                                         ctypes.byref(h))
-        if rc != 0:
-            return
-        self._prepared[key] = _Prepared(self._lib, h, shape)
+        while len(insts) < want:
+            h = ctypes.c_void_p()
+            rc = self._lib.pfac_batch_create(ctypes.cast(self._tabs, ctypes.c_void_p),
+                                             len(self.tables), descs.ctypes.data, ntext, pl,
+                                             ctypes.byref(h))
+            if rc != 0:
+                break
+            insts.append(_Prepared(self._lib, h, shape))
         while len(self._prepared) > self._prepared_cap:
             self._prepared.popitem(last=False)
 
@@ -571,6 +599,8 @@ class Server:
         if isinstance(d.args[0], str):
             self._finish_single(d, c)
             return
+        if d.prepared is not None:
+            d.prepared.busy -= 1
         if c[0] > d.hits.shape[0]:
             # the hit buffer was too small: redo the dispatch with room for all
             addrs, tids, stream = d.args
@@ -595,18 +625,21 @@ class Server:
         else:
             extra = 0
         t = self.now()
+        # per-text counts: views of this dispatch's own pinned counter buffer
         per_hits, per_occ = c[2::2], c[3::2]
-        hit_start = np.concatenate([[0], np.cumsum(per_hits)]).astype(np.int64)
         lease = _Lease(self.gate, sum(r.device_bytes() for r in d.reqs) + extra, len(d.reqs))
+        h0 = 0
+        one = len(d.reqs) == 1
         for r, f in zip(d.reqs, d.first_text):
             k = r.num_texts
             Lr = d.lengths[f:f + k]
             m0 = int(d.match_offsets[f]) if k else 0
             m1 = int(d.match_offsets[f + k - 1]) + int(Lr[-1]) if k else 0
-            mats = d.match[m0:m1]
-            res = RequestResult(mats, d.match_offsets[f:f + k] - m0, Lr,
-                                d.hits[int(hit_start[f]):int(hit_start[f + k])], f,
-                                per_hits[f:f + k].copy(), per_occ[f:f + k].copy())
+            h1 = int(c[0]) if one else h0 + int(per_hits[f:f + k].sum())
+            offs = d.match_offsets[f:f + k]
+            res = RequestResult(d.match[m0:m1], offs - m0 if m0 else offs, Lr, d.hits[h0:h1], f,
+                                per_hits[f:f + k], per_occ[f:f + k])
+            h0 = h1
             weakref.finalize(res, lease.drop)
             r.completed = t
             r.ready = None
@@ -650,6 +683,15 @@ class Server:
         del res
         self.done.append(r)
         self.busy[d.stream_idx] -= 1
+
+    def _on_stream(self, stream, fn, *args, **kw):
+        """fn(*args, **kw) with `stream` current on the server's device."""
+        prev = torch.cuda.current_stream(self._dev)
+        torch.cuda.set_stream(stream)
+        try:
+            return fn(*args, **kw)
+        finally:
+            torch.cuda.set_stream(prev)
 
     def _event(self) -> torch.cuda.Event:
         """A completion event from the pool (events of completed dispatches
@@ -726,6 +768,8 @@ class _Prepared:
         self._lib = lib
         self.handle = handle
         self.shape = shape
+        self.busy = 0                  # launches in flight
+        self.si = -1                   # stream of the last launch
 
     def __del__(self):
         try:
