@@ -15,6 +15,7 @@ if not torch.cuda.is_available():
 import paper_1811_10498_amd as pf  # noqa: E402
 from paper_1811_10498_amd.serve import (Request, Server, TextBatch,  # noqa: E402
                                        hit_cap_of, plain_per_request)
+from _gpu_common import joined_oracle  # noqa: E402
 
 DEV = torch.device("cuda:0")
 
@@ -112,6 +113,64 @@ def test_kept_results_hold_their_reservation():
     import gc
     gc.collect()
     assert srv.gate.reserved == 0
+
+
+def test_prepared_batches_shared_across_streams():
+    """Reads requests (1,000 texts each, so each is dispatched alone through
+    a prepared batch) of two shapes on two tables, device-resident at
+    different offsets, served in three rounds on three short-request
+    streams: every shape gets one prepared batch per such stream the first
+    time it is seen, later rounds launch them from whichever stream takes
+    the request (each at its own text base), and every text of every
+    request agrees with the oracle: dense run, hit and occurrence counts, and
+    hit rows."""
+    tries = W.served_tries(seed=6, sizes=[800, 2500], pool_bases=400_000)
+    tables = [pf.Table(t) for t in tries]
+    g = W.rng(61)
+    slot, ntext = 160, 1000
+    pool_h = W.uniform_ascii(slot * ntext * 12, g).copy()
+    allp = tries[0] + tries[1]
+    for at in g.integers(0, pool_h.size - 64, size=6000):     # planted occurrences
+        pat = np.frombuffer(allp[int(g.integers(0, len(allp)))], dtype=np.uint8)
+        pool_h[at:at + pat.size] = pat
+    pool = torch.from_numpy(pool_h).to(DEV)
+    lens = [np.full(ntext, 150), g.integers(100, 161, size=ntext)]     # two shapes
+    srv = Server(tables, budget_bytes=4 << 30, streams=4)
+    rid = 0
+    for rnd in range(3):
+        reqs = []
+        for k in range(8):
+            start = int(g.integers(0, 12 - 1)) * slot * ntext
+            reqs.append(Request(rid, k % 2, TextBatch(pool, start + slot * np.arange(ntext),
+                                                      lens[(k // 2) % 2]), 0.0))
+            rid += 1
+        print("round", rnd, "prepared launches so far", srv.prepared_hits, flush=True)
+        srv.run(reqs)
+        for r in reqs:
+            tb = r.texts
+            refs = joined_oracle(tries[r.table], [pool_h[int(o):int(o) + int(n)]
+                                                  for o, n in zip(tb.offsets, tb.lengths)])
+            res = r.result
+            h = res.hits.cpu().numpy()
+            hp = 0
+            for i, (m_ref, occ_ref) in enumerate(refs):
+                assert np.array_equal(res.text_match(i).cpu().numpy(), m_ref), (r.rid, i)
+                pos, ids = oracle.hits_of(m_ref)
+                assert res.num_hits[i] == pos.size and res.occurrences[i] == occ_ref, (r.rid, i)
+                hh = h[hp:hp + pos.size]
+                assert np.all(hh[:, 0] == i), (r.rid, i)
+                assert np.array_equal(hh[:, 1].astype(np.uint32), pos), (r.rid, i)
+                assert np.array_equal(hh[:, 2], ids), (r.rid, i)
+                hp += pos.size
+            assert hp == h.shape[0], r.rid
+        hits_seen = sum(int(r.result.num_hits.sum()) for r in reqs)
+        assert hits_seen > 100, hits_seen
+        srv.done.clear()
+    # four shapes (two tables x two length sets), three instances each
+    assert len(srv._prepared) == 4
+    assert all(len(v) == 3 for v in srv._prepared.values())
+    assert all(b.busy == 0 for v in srv._prepared.values() for b in v)
+    assert srv.prepared_hits >= 16
 
 
 def test_dispatches_overlap_on_the_device():
