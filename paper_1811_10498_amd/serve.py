@@ -741,8 +741,15 @@ class Server:
         self.t0 = time.perf_counter()
         while pending or not self.idle():
             t = self.now()
-            while pending and pending[0].arrival <= t:
-                self.submit(pending.popleft())
+            # arrived requests are queued up to a dispatch's worth of bases
+            # between dispatch steps: a burst of arrivals does not hold the
+            # device idle while all of it is queued (latency counts from
+            # arrival anyway), and short requests still coalesce
+            queued = 0
+            while pending and pending[0].arrival <= t and queued < self.max_dispatch_bases:
+                r = pending.popleft()
+                self.submit(r)
+                queued += r.bases
             self.step()
             if not pending and self.idle():
                 break
@@ -752,6 +759,8 @@ class Server:
                 raise RuntimeError("request %d cannot be admitted: %d of %d budget bytes are "
                                    "held by results not yet dropped"
                                    % (self.gate.queue[0].rid, self.gate.reserved, self.budget))
+            if pending and pending[0].arrival <= self.now():
+                continue                          # more arrivals to queue first
             if self.inflight and not any(d.event.query() for d in self.inflight):
                 time.sleep(poll_s)
             elif not self.inflight and pending:
