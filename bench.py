@@ -459,7 +459,7 @@ def part_c3(pf, torch, args, plan, tune=False):
     return out
 
 
-def part_c4(pf, torch, args, plan, num_requests=600, load=0.7, plain_requests=None):
+def part_c4(pf, torch, args, plan, num_requests=2000, load=0.7, plain_requests=None):
     """Served workload: 8 resident tries (1,000 .. 200,000 patterns), requests
     equiprobable among a batch of 10,000 150-base reads, a 1 Mbase contig and
     a 50 Mbase chromosome-like text, texts already in device memory.  Closed
@@ -737,7 +737,7 @@ def main():
                     help="wall seconds of oracle passes for the CPU baseline")
     ap.add_argument("--autotune", action="store_true",
                     help="let the autotuner pick the plans of the packed and batched workloads")
-    ap.add_argument("--requests", type=int, default=600, help="served requests")
+    ap.add_argument("--requests", type=int, default=2000, help="served requests")
     ap.add_argument("--c2-output", default="both", choices=("both", "dense", "hits"),
                     help="outputs timed on the packed workload (profiling runs take one)")
     ap.add_argument("--calibrate-copy", action="store_true",
