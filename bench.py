@@ -493,7 +493,8 @@ def part_c4(pf, torch, args, plan, num_requests=2000, load=0.7, plain_requests=N
 
     kw = dict(budget_bytes=32 << 30, keep_results=False, plan=plan)
     srv = Server(tables, trace=True, **kw)
-    srv.run(make([0.0] * num_requests)[:60])          # warm-up (and prepared batches)
+    warm = max(60, num_requests // 10)                 # the first tenth warms up
+    srv.run(make([0.0] * num_requests)[:warm])        # warm-up (and prepared batches)
     srv.done.clear()
     srv.trace.clear()
     closed = srv.run(make([0.0] * num_requests))
@@ -512,7 +513,7 @@ def part_c4(pf, torch, args, plan, num_requests=2000, load=0.7, plain_requests=N
     rate = load * cap / (bases / num_requests)
     arr = np.cumsum(W.rng(45).exponential(1.0 / rate, size=num_requests))
     srv2 = Server(tables, **kw)
-    srv2.run(make(arr[:60] - arr[0]))                 # warm the prepared batches of this server
+    srv2.run(make(arr[:warm] - arr[0]))               # warm the prepared batches of this server
     srv2.done.clear()
     opened = srv2.run(make(arr))
     # the baseline on the same requests as the closed loop (a sample would
